@@ -1,0 +1,40 @@
+"""Active-set rule and one semi-smooth Newton step (oracle; test infrastructure only).
+
+Algorithm 1 (primal-dual active set).  Readings:
+  * the update U_{k+1} = U_k + G^-1 R_k and the active-set test
+    (M^-1 R)_i + c (U - U_old)_i > 0 are consistent when R_k is minus
+    the residual of eq. (residual); with R the residual as written there,
+    the Newton step solves G^ dU = -P R and the active set is
+        A = { phi-dofs i : -(M_L^-1 R)_i + c (phi - phi_old)_i > 0 },
+    i.e. the multiplier -R_i wants phi to grow above phi_old;
+  * M is the row-sum-lumped phi mass matrix, c = 1.
+"""
+import numpy as np
+
+from . import operator as op
+from .fe import Mesh
+from .krylov import fgmres
+from .multigrid import Hierarchy
+
+
+def active_set(mesh: Mesh, R, phi, phi_old, c=1.0):
+    ML = op.lumped_phi_mass(mesh)
+    Rp = R[mesh.dim * mesh.n_nodes:]
+    ind = -Rp / ML + c * (phi - phi_old)
+    return (ind > 0.0).astype(np.uint8), ind
+
+
+def newton_step(cfg, levels_nk, u, phi, phi_old, phi_t):
+    """One step: residual, active set, linearisation, FGMRES + GMG, update."""
+    mesh = Mesh(cfg.dim, cfg.N, cfg.k)
+    m = op.material_of(cfg)
+    R = op.residual(mesh, m, u, phi, phi_t)
+    act, ind = active_set(mesh, R, phi, phi_old, cfg.as_c)
+    hier = Hierarchy(cfg, levels_nk, u, phi, phi_t, act)
+    fine = hier.levels[-1]
+    b = -fine.pvec * R
+    dU, info = fgmres(lambda v: fine.A @ v, hier.vcycle, b, cfg.restart, cfg.rtol, cfg.max_iter)
+    d, nn = cfg.dim, mesh.n_nodes
+    u_new = u + dU[: d * nn].reshape(d, nn)
+    phi_new = phi + dU[d * nn:]
+    return dict(R=R, active=act, indicator=ind, b=b, dU=dU, u=u_new, phi=phi_new, info=info, hier=hier)

@@ -1,0 +1,202 @@
+"""Pins of the oracle's multigrid, Krylov and Newton pieces."""
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+from oracle import fe, krylov, multigrid as mg, newton
+from oracle import operator as op
+from oracle.splitmix import mix64, GAMMA, uniform_pm1
+from synth import CONFIGS, level_list, make_inputs, node_coords
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------- SplitMix64
+def test_splitmix_published_vector():
+    ref = [int(l) for l in open(os.path.join(GOLDEN, "splitmix64_seed1234567.txt")) if l.strip() and l[0] != "#"]
+    s = np.uint64(1234567)
+    with np.errstate(over="ignore"):
+        got = [int(mix64(s + np.uint64(n) * GAMMA)) for n in range(1, 6)]
+    assert got == ref
+
+
+def test_uniform_range_and_streams():
+    a = uniform_pm1(7, 0, 100000)
+    b = uniform_pm1(7, 1, 100000)
+    assert a.min() >= -1 and a.max() < 1 and abs(a.mean()) < 0.01
+    assert not np.array_equal(a[:10], b[:10])
+
+
+# ------------------------------------------------------------- transfers
+@pytest.mark.parametrize("fine,coarse", [((8, 2), (4, 2)), ((4, 4), (4, 2)), ((4, 2), (4, 1)),
+                                         ((6, 3), (3, 3)), ((4, 4), (4, 1))])
+def test_prolongation_reproduces_coarse_polynomials(fine, coarse):
+    mf, mc = fe.Mesh(1, *fine), fe.Mesh(1, *coarse)
+    P1 = mg.prolongation_1d(mf, mc)
+    xf = np.arange(mf.M) / (mf.k * mf.N)
+    xc = np.arange(mc.M) / (mc.k * mc.N)
+    rng = np.random.default_rng(0)
+    for deg in range(mc.k + 1):
+        f = np.polynomial.Polynomial(rng.standard_normal(deg + 1))
+        assert np.allclose(P1 @ f(xc), f(xf), atol=1e-12)
+    # injection: coarse node positions are fine node positions
+    idx = mg.injection_index(fe.Mesh(2, *fine), fe.Mesh(2, *coarse))
+    Xf, Xc = node_coords(2, *fine), node_coords(2, *coarse)
+    assert np.allclose(Xf[idx], Xc, atol=0)
+
+
+def test_restriction_is_adjoint_and_masked():
+    cfg = CONFIGS["C2"].with_(N=8, n_h_levels=2)
+    inp = make_inputs(cfg)
+    H = mg.Hierarchy(cfg, level_list(cfg), inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
+    P = H.P[1]
+    f, c = H.levels[1], H.levels[0]
+    rng = np.random.default_rng(1)
+    x, y = rng.standard_normal(f.mesh.n_dofs), rng.standard_normal(c.mesh.n_dofs)
+    assert abs((P.T @ x) @ y - x @ (P @ y)) <= 1e-12 * np.linalg.norm(x) * np.linalg.norm(y)
+    assert np.all((P @ y)[f.pvec == 0] == 0) and np.all((P.T @ x)[c.pvec == 0] == 0)
+
+
+# ------------------------------------------------------------- Chebyshev
+def test_chebyshev_residual_polynomial_closed_form():
+    # diag(lam), D = I: 1 - lam p(lam) = T_s((theta - lam)/delta) / T_s(theta/delta)
+    class L:
+        pass
+    n, nu = 40, 25
+    lam = np.linspace(0.05, 2.0, n)
+    lev = L()
+    lev.nu, lev.D = nu, np.ones(n)
+    lev.Ablk = sp.diags(lam)
+    lmax = (2.0, 2.0)
+    for s in (1, 2, 4, 5, 7):
+        x = mg.chebyshev_block(lev, lmax, np.ones(n), s, 0.24, 1.2)
+        lo, hi = 0.24 * 2.0, 1.2 * 2.0
+        th, de = (hi + lo) / 2, (hi - lo) / 2
+        T = np.polynomial.chebyshev.Chebyshev.basis(s)
+        assert np.allclose(1 - lam * x, T((th - lam) / de) / T(th / de), atol=1e-13)
+
+
+# ------------------------------------------------------------- Lanczos
+def test_cg_lanczos_full_space_gives_exact_spectrum_top():
+    rng = np.random.default_rng(2)
+    n = 12
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(np.linspace(1, 50, n)) @ Q.T
+    D = np.diag(A).copy()
+    al, be = mg.cg_lanczos(A, D, rng.standard_normal(n), n)
+    ref = sla.eigh(A, np.diag(D), eigvals_only=True)[-1]
+    assert abs(mg.lanczos_ritz_max(al, be) - ref) <= 1e-8 * ref
+
+
+def test_lanczos_bounds_on_c1_blocks():
+    cfg = CONFIGS["C1"]
+    inp = make_inputs(cfg)
+    H = mg.Hierarchy(cfg, level_list(cfg), inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
+    lev = H.levels[1]
+    nu = lev.nu
+    for b, sl in ((0, slice(0, nu)), (1, slice(nu, None))):
+        A = lev.A[sl, sl].toarray()
+        ev = sla.eigh(A, np.diag(lev.D[sl]), eigvals_only=True)[-1]
+        est = H.lam[1][b]
+        assert est <= ev * (1 + 1e-12) and est >= 0.95 * ev
+
+
+def test_lanczos_fully_masked_block_is_one():
+    al, be = mg.cg_lanczos(np.eye(3), np.ones(3), np.zeros(3), 15)
+    assert al == [] and mg.lanczos_ritz_max(al, be) == 1.0
+
+
+# ------------------------------------------------------------- V-cycle / coarse
+def test_single_level_cycle_is_exact_solve():
+    cfg = CONFIGS["C2"].with_(N=4, n_h_levels=1)
+    inp = make_inputs(cfg, ("rhs",))
+    H = mg.Hierarchy(cfg, level_list(cfg), inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
+    A = H.levels[0].A
+    b = inp["rhs"]
+    assert np.allclose(H.vcycle(b), spla.spsolve(A.tocsc(), b), rtol=1e-10, atol=1e-14)
+
+
+@pytest.mark.parametrize("name,kw", [("C1", dict(N=16)), ("C2", dict(N=8, n_h_levels=2)),
+                                     ("C3", dict(N=4, n_h_levels=2)), ("C4", dict(dim=2, N=8, n_h_levels=2))])
+def test_two_grid_error_operator_contracts(name, kw):
+    # intact material (phi = phi~ = 1), the workload's displacement, no active set:
+    # the two-grid error operator of the V-cycle must contract (power iteration)
+    cfg = CONFIGS[name].with_(**kw)
+    inp = make_inputs(cfg)
+    lv = level_list(cfg)[-2:]
+    one = np.ones(cfg.n_nodes)
+    H = mg.Hierarchy(cfg, lv, inp["u"], one, one, np.zeros(cfg.n_nodes, np.uint8))
+    A = H.levels[-1].A
+    rng = np.random.default_rng(3)
+    e = rng.standard_normal(A.shape[0])
+    rho = 0.0
+    for _ in range(25):
+        e_new = e - H.vcycle(A @ e)
+        rho = np.linalg.norm(e_new) / np.linalg.norm(e)
+        e = e_new / np.linalg.norm(e_new)
+    assert rho < 0.8
+
+
+# ------------------------------------------------------------- FGMRES
+def test_fgmres_against_direct_solve_nonsymmetric():
+    rng = np.random.default_rng(4)
+    n = 60
+    A = np.eye(n) * 4 + rng.standard_normal((n, n)) * 0.3
+    b = rng.standard_normal(n)
+    Minv = np.linalg.inv(np.diag(np.diag(A)))
+    for m in (5, 30):
+        x, info = krylov.fgmres(lambda v: A @ v, lambda v: Minv @ v, b, m=m, rtol=1e-10, max_iter=500)
+        assert info["converged"]
+        assert np.linalg.norm(b - A @ x) <= 1e-10 * np.linalg.norm(b)
+        assert np.allclose(x, np.linalg.solve(A, b), rtol=1e-8)
+
+
+def test_fgmres_reports_nonconvergence():
+    rng = np.random.default_rng(5)
+    A = np.diag(np.linspace(1, 1e4, 80))
+    b = rng.standard_normal(80)
+    x, info = krylov.fgmres(lambda v: A @ v, lambda v: v, b, m=5, rtol=1e-12, max_iter=3)
+    assert not info["converged"] and info["iterations"] == 3
+
+
+def test_gmg_fgmres_c1_vs_spsolve():
+    cfg = CONFIGS["C1"]
+    inp = make_inputs(cfg, ("rhs",))
+    H = mg.Hierarchy(cfg, level_list(cfg), inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
+    A = H.levels[-1].A
+    b = H.levels[-1].pvec * inp["rhs"]
+    x, info = krylov.fgmres(lambda v: A @ v, H.vcycle, b, cfg.restart, cfg.rtol, cfg.max_iter)
+    assert info["converged"] and np.linalg.norm(b - A @ x) <= 1e-8 * np.linalg.norm(b)
+    xs = spla.spsolve(A.tocsc(), b)
+    cond = np.linalg.cond(A.toarray())
+    assert np.linalg.norm(x - xs) <= cond * 1e-8 * np.linalg.norm(xs)
+
+
+# ------------------------------------------------------------- Newton
+def test_active_set_sign_convention():
+    # phi = phi_old: active exactly where the phase-field residual is negative
+    mesh = fe.Mesh(2, 3, 1)
+    R = np.zeros(mesh.n_dofs)
+    nn = mesh.n_nodes
+    R[2 * nn:] = np.linspace(-1, 1, nn)
+    act, _ = newton.active_set(mesh, R, np.ones(nn), np.ones(nn))
+    assert np.array_equal(act.astype(bool), R[2 * nn:] < 0)
+    # phi above phi_old pushes towards active
+    act2, _ = newton.active_set(mesh, np.zeros(mesh.n_dofs), np.full(nn, 1.0), np.full(nn, 0.5))
+    assert act2.all()
+
+
+def test_newton_step_solves_linearised_system():
+    cfg = CONFIGS["C2"].with_(N=8, n_h_levels=2)
+    inp = make_inputs(cfg)
+    out = newton.newton_step(cfg, level_list(cfg), inp["u"], inp["phi"], inp["phi_old"], inp["phi_tilde"])
+    A = out["hier"].levels[-1].A
+    assert out["info"]["converged"]
+    assert np.linalg.norm(out["b"] - A @ out["dU"]) <= 1e-8 * np.linalg.norm(out["b"])
+    # constrained dofs do not move
+    p = out["hier"].levels[-1].pvec
+    assert np.all(out["dU"][p == 0] == 0)
