@@ -1,0 +1,186 @@
+/*
+ * mfpff: matrix-free linear solves for the semi-smooth Newton step of the
+ * coupled displacement / phase-field fracture problem, on AMD MI355X (gfx950).
+ *
+ * Method: Jodlbauer, Langer, Wick, "Parallel matrix-free higher-order finite
+ * element solvers for phase-field fracture problems".  Each Newton step of
+ * the primal-dual active-set method (Algorithm 1) solves G dU = -R on the
+ * inactive set, with R the residual of eq. (residual) and G its derivative
+ * eq. (G) (phi~ frozen, so G is block lower triangular, Section 3.3).  The
+ * product with G is evaluated cell by cell without a stored matrix
+ * (Section 3.4); GMRES is preconditioned by a monolithic geometric multigrid
+ * V-cycle with a block-diagonal Chebyshev-Jacobi smoother (Section 3.3).
+ *
+ * Conventions (all entry points):
+ *   - Domain [0,1]^dim, N cells per direction, Q_k with equispaced nodes,
+ *     Gauss quadrature with k+1 points per direction.
+ *   - Nodes are numbered lexicographically, node = i0 + M*i1 (+ M*M*i2),
+ *     M = k*N + 1; n_nodes = M^dim.
+ *   - Vectors are component-blocked: [u_0 | ... | u_{dim-1} | phi], each
+ *     block n_nodes long; n_dofs = (dim+1)*n_nodes.  The displacement u
+ *     argument is the first dim blocks of that layout (dim*n_nodes values).
+ *   - Vector and field arguments are DEVICE pointers owned by the caller,
+ *     contiguous, 8-byte doubles unless stated (4-byte floats when a
+ *     precision argument says FP32).  The library keeps no caller pointer
+ *     past the call.
+ *   - The active set is one byte per node (non-zero = the phi-dof of that
+ *     node is fixed, delta phi = 0).  Homogeneous Dirichlet conditions fix
+ *     every displacement dof on the two faces normal to the last axis when
+ *     `dirichlet` is set.  Fixed dofs get identity rows and columns:
+ *     G^ = P G P + (I - P), P the diagonal 0/1 matrix of free dofs.
+ *   - Work is enqueued on the HIP stream given at creation.  Entry points
+ *     that return host values (gmres_solve, residual_param_vjp, newton_step,
+ *     level_info) synchronise that stream; the others are asynchronous.
+ *   - Errors are reported by status codes; no exception crosses this ABI.
+ *     mfpff_last_error() returns a message for the last failure of a context.
+ *   - A context is not thread-safe; use one per host thread.
+ */
+#ifndef MFPFF_H
+#define MFPFF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MFPFF_MAX_LEVELS 16
+
+typedef struct mfpff_ctx mfpff_ctx;
+
+typedef enum {
+  MFPFF_OK = 0,
+  MFPFF_ERR_ARG = 1,      /* invalid argument (sizes, degree, level index, null pointer) */
+  MFPFF_ERR_STATE = 2,    /* called before mfpff_set_linearization */
+  MFPFF_ERR_OOM = 3,      /* device allocation failed */
+  MFPFF_ERR_HIP = 4,      /* a HIP runtime call failed */
+  MFPFF_ERR_NOCONV = 5,   /* GMRES reached max_iter; the last iterate is returned */
+  MFPFF_ERR_NUMERIC = 6   /* non-finite value or failed factorisation */
+} mfpff_status;
+
+typedef enum { MFPFF_F64 = 0, MFPFF_F32 = 1 } mfpff_prec;
+
+typedef enum {
+  MFPFF_OP_G = 0,         /* y = G^ x */
+  MFPFF_OP_GT = 1,        /* y = G^T-hat x (transpose: coupling moves to the u rows) */
+  MFPFF_OP_BLOCKDIAG = 2  /* y = diag(G^_uu, G^_phiphi) x (smoother operator) */
+} mfpff_op;
+
+/* Problem description.  Levels run from the coarsest (index 0) to the
+ * finest (index n_levels-1).  Consecutive levels are either an h-step
+ * (N halves, same degree) or a p-step (same N, lower degree dividing the
+ * finer one); coarse nodes are then a subset of fine nodes. */
+typedef struct {
+  int dim;                          /* 2 or 3 */
+  int n_levels;                     /* 1 .. MFPFF_MAX_LEVELS */
+  int level_N[MFPFF_MAX_LEVELS];    /* cells per direction */
+  int level_k[MFPFF_MAX_LEVELS];    /* degree, 1 .. 4 */
+  int dirichlet;                    /* 1: delta u = 0 on the faces normal to the last axis */
+  double lambda, mu;                /* Lame parameters */
+  double Gc, eps, kappa;            /* toughness, length scale, degradation floor (Section 2.1) */
+  double as_c;                      /* constant c of the active-set rule of Algorithm 1 */
+  int cheb_degree;                  /* Chebyshev polynomial degree s (s-1 operator products) */
+  double cheb_lo, cheb_hi;          /* interval factors (Section 3.3: 0.24, 1.2) */
+  int lanczos_steps;                /* CG steps of the lambda_max estimate */
+  unsigned long long lanczos_seed;  /* SplitMix64 seed of the start vectors */
+  int vcycle_prec;                  /* mfpff_prec of levels and smoothers inside the V-cycle */
+  int restart;                      /* GMRES restart length m (<= 64) */
+  int max_iter;                     /* total GMRES iteration cap */
+  double rtol;                      /* relative true-residual tolerance */
+} mfpff_problem;
+
+typedef struct {
+  int iterations;                   /* GMRES iterations (preconditioner applications) */
+  int converged;                    /* 1 if ||b - G^ x|| <= rtol ||b|| */
+  double rel_residual;              /* ||b - G^ x|| / ||b|| computed at the end */
+  double ms_setup;                  /* time of set_linearization inside newton_step, ms */
+  double ms_solve;                  /* time of the GMRES solve, ms */
+  int n_active;                     /* newton_step: size of the active set */
+} mfpff_solve_info;
+
+typedef struct {
+  int N, k;
+  long long n_nodes, n_dofs;
+  double lambda_u, lambda_phi;      /* Ritz estimates of lambda_max(D^-1 G^_bb), after linearisation */
+  int lanczos_steps_u, lanczos_steps_phi;
+} mfpff_level_desc;
+
+/* Build the level hierarchy, 1D tables and all device storage for a problem
+ * (the mesh set-up of the solver).  `hip_stream` is a hipStream_t (NULL:
+ * the default stream).  On success *out owns every device allocation. */
+mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx** out);
+
+/* Release a context and everything it owns.  NULL is ignored. */
+void mfpff_destroy(mfpff_ctx* ctx);
+
+/* Message describing the last failure on this context ("" if none). */
+const char* mfpff_last_error(const mfpff_ctx* ctx);
+
+/* Sizes and smoother data of one level. Synchronises. */
+mfpff_status mfpff_level_info(mfpff_ctx* ctx, int level, mfpff_level_desc* out);
+
+/* Freeze the linearisation point of eq. (G): u (dim*n_nodes), phi, phi_old
+ * and phi_tilde (n_nodes each; phi_tilde NULL means phi_old) and the active
+ * set (n_nodes bytes) on the finest level.  Injects fields and masks to every
+ * coarser level, builds the diagonals, the Chebyshev intervals (CG-Lanczos
+ * estimates) and the factorised coarse blocks. */
+mfpff_status mfpff_set_linearization(mfpff_ctx* ctx, const double* u, const double* phi,
+                                     const double* phi_old, const uint8_t* active,
+                                     const double* phi_tilde);
+
+/* y = op(G^_level) x on one level.  x, y: n_dofs of that level, FP64 or FP32
+ * per `prec` (FP32 uses the FP32 copy of the level data).  x and y must not
+ * alias. */
+mfpff_status mfpff_apply_jacobian(mfpff_ctx* ctx, int level, const void* x, void* y, int prec, int op);
+
+/* Diagonal of G^_level (1 at fixed dofs), FP64, n_dofs of the level. */
+mfpff_status mfpff_diagonal(mfpff_ctx* ctx, int level, double* diag);
+
+/* z = diag(C_u, C_phi) r on level >= 1: the block Chebyshev-Jacobi polynomial
+ * of the smoother applied to r from a zero start (FP64). */
+mfpff_status mfpff_smooth(mfpff_ctx* ctx, int level, const double* r, double* z);
+
+/* Masked transfer between level-1 and level (level >= 1): direction 0 is
+ * prolongation (in: level-1 vector, out: level vector), 1 is restriction
+ * (the transpose).  FP64. */
+mfpff_status mfpff_transfer(mfpff_ctx* ctx, int level, int direction, const double* in, double* out);
+
+/* Exact FP64 solve with the coarsest level operator (block lower triangular). */
+mfpff_status mfpff_coarse_solve(mfpff_ctx* ctx, const double* r, double* x);
+
+/* One V-cycle of the monolithic multigrid on the finest level: z = V(r). */
+mfpff_status mfpff_vcycle(mfpff_ctx* ctx, const double* r, double* z);
+
+/* Right-preconditioned flexible GMRES(m), classical Gram-Schmidt twice, x0 = 0,
+ * until ||b - G^ x|| <= rtol ||b|| (FP64 outer iteration; V-cycle precision per
+ * the problem).  MFPFF_ERR_NOCONV leaves the last iterate in x.  Synchronises. */
+mfpff_status mfpff_gmres_solve(mfpff_ctx* ctx, const double* b, double* x, mfpff_solve_info* info);
+
+/* Residual of eq. (residual) on the finest level at (u, phi) with phi~ in
+ * the degradation of the displacement equation; unconstrained (no masks). */
+mfpff_status mfpff_residual(mfpff_ctx* ctx, const double* u, const double* phi,
+                            const double* phi_tilde, double* R);
+
+/* Parameter cotangents of the residual: dGc = <v, dR/dGc>, deps = <v, dR/deps>
+ * (host doubles).  Synchronises. */
+mfpff_status mfpff_residual_param_vjp(mfpff_ctx* ctx, const double* u, const double* phi,
+                                      const double* phi_tilde, const double* v,
+                                      double* dGc_host, double* deps_host);
+
+/* Active set of Algorithm 1 from the residual R (as returned by
+ * mfpff_residual): active_i = [ -(M_L^-1 R_phi)_i + c (phi - phi_old)_i > 0 ],
+ * M_L the row-sum-lumped phi mass matrix. */
+mfpff_status mfpff_active_set(mfpff_ctx* ctx, const double* R, const double* phi,
+                              const double* phi_old, uint8_t* active);
+
+/* One semi-smooth Newton step of Algorithm 1 on the finest level: residual,
+ * active set (written to `active`), linearisation, b = -P R, GMRES solve,
+ * u += du, phi += dphi (u, phi updated in place).  Synchronises. */
+mfpff_status mfpff_newton_step(mfpff_ctx* ctx, double* u, double* phi, const double* phi_old,
+                               const double* phi_tilde, uint8_t* active, mfpff_solve_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFPFF_H */

@@ -1,0 +1,270 @@
+// Dense FP64 kernels of the coarse-grid solve (gfx950).
+//
+// The coarsest level is solved exactly with the block lower-triangular
+// structure of the Jacobian (Section 3.3): x_u = G_uu^-1 r_u,
+// x_phi = G_phiphi^-1 (r_phi - G_phiu x_u).  Each diagonal block is factorised
+// once per linearisation by a blocked right-looking Cholesky (panels of 32
+// factored in LDS, trailing updates as tiled products), and the inverse
+// factor W = L^-1 is formed by a blocked triangular solve, so that a V-cycle
+// applies the coarse inverse as four dense matrix-vector products
+// (A^-1 = W^T W) instead of sequential substitutions.
+#include <cmath>
+
+#include "internal.h"
+
+namespace mfpff {
+
+constexpr int TB = 32;
+
+__global__ void set_fixed_diag_kernel(double* A, long long ld, const uint8_t* mask, long long nn, int dim) {
+  const long long n = (long long)(dim + 1) * nn;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const long long comp = i / nn;
+    const uint8_t m = mask[i - comp * nn];
+    const bool f = comp < dim ? (m & kMaskU) : (m & kMaskPhi);
+    if (f) A[i * ld + i] = 1.0;
+  }
+}
+void k_dense_set_fixed_diag(double* A, long long ld, const uint8_t* mask, long long nn, int dim, hipStream_t s) {
+  long long nb = ((dim + 1) * nn + kThreads - 1) / kThreads;
+  hipLaunchKernelGGL(set_fixed_diag_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, A, ld, mask, nn, dim);
+}
+
+__global__ void extract_block_kernel(double* dst, long long ldd, const double* src, long long lds, long long r0, long long c0,
+                                     long long nr, long long nc) {
+  const long long total = nr * nc;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total; i += (long long)gridDim.x * blockDim.x) {
+    const long long r = i / nc, c = i - (i / nc) * nc;
+    dst[r * ldd + c] = src[(r0 + r) * lds + c0 + c];
+  }
+}
+void k_extract_block(double* dst, long long ldd, const double* src, long long lds, long long r0, long long c0, long long nr,
+                     long long nc, hipStream_t s) {
+  long long nb = (nr * nc + kThreads - 1) / kThreads;
+  if (nb > 65536) nb = 65536;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(extract_block_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, dst, ldd, src, lds, r0, c0, nr, nc);
+}
+
+// Factor the diagonal block at k0 in LDS (identity padding past n); block 0
+// writes L11 to `diag` (copied into A by the next kernel, so that no block
+// reads a half-written diagonal block), block b >= 1 solves
+// X L11^T = A[rows of b][k0:k0+TB] in place.
+__global__ void potrf_panel_kernel(double* A, int n, int k0, int* info, double* diag) {
+  __shared__ double L[TB][TB + 1];
+  __shared__ double X[TB][TB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, j = e % TB;
+    const int gi = k0 + i, gj = k0 + j;
+    L[i][j] = (gi < n && gj < n) ? A[(long long)gi * n + gj] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int j = 0; j < TB; ++j) {
+    if (tid == 0) {
+      double d = L[j][j];
+      if (!(d > 0.0)) {
+        if (blockIdx.x == 0) atomicMax(info, k0 + j + 1);
+        d = 1.0;
+      }
+      L[j][j] = sqrt(d);
+    }
+    __syncthreads();
+    for (int i = j + 1 + tid; i < TB; i += blockDim.x) L[i][j] /= L[j][j];
+    __syncthreads();
+    for (int e = tid; e < TB * TB; e += blockDim.x) {
+      const int i = e / TB, l = e % TB;
+      if (l > j && i >= l) L[i][l] -= L[i][j] * L[l][j];
+    }
+    __syncthreads();
+  }
+  if (blockIdx.x == 0) {
+    for (int e = tid; e < TB * TB; e += blockDim.x) diag[e] = L[e / TB][e % TB];
+    return;
+  }
+  const int r0 = k0 + blockIdx.x * TB;
+  for (int e = tid; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, j = e % TB;
+    const int gi = r0 + i, gj = k0 + j;
+    X[i][j] = (gi < n && gj < n) ? A[(long long)gi * n + gj] : 0.0;
+  }
+  __syncthreads();
+  if (tid < TB) {
+    const int i = tid;
+    for (int j = 0; j < TB; ++j) {
+      double v = X[i][j];
+      for (int l = 0; l < j; ++l) v -= X[i][l] * L[j][l];
+      X[i][j] = v / L[j][j];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, j = e % TB;
+    const int gi = r0 + i, gj = k0 + j;
+    if (gi < n && gj < n) A[(long long)gi * n + gj] = X[i][j];
+  }
+}
+
+__global__ void copy_diag_kernel(double* A, int n, int k0, const double* diag) {
+  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, j = e % TB;
+    const int gi = k0 + i, gj = k0 + j;
+    if (gi < n && gj < n && j <= i) A[(long long)gi * n + gj] = diag[e];
+  }
+}
+
+// Trailing update A[i][j] -= sum_l L[i][l] L[j][l], l in the panel, for tiles bi >= bj.
+__global__ void syrk_update_kernel(double* A, int n, int k0) {
+  __shared__ double Li[TB][TB + 1];
+  __shared__ double Lj[TB][TB + 1];
+  const int k1 = k0 + TB;
+  // blockIdx.x -> (bi, bj), bi >= bj
+  int t = blockIdx.x, bi = 0;
+  while (t > bi) {
+    t -= bi + 1;
+    ++bi;
+  }
+  const int bj = t;
+  const int ri = k1 + bi * TB, rj = k1 + bj * TB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, l = e % TB;
+    const int gl = k0 + l;
+    Li[i][l] = (ri + i < n && gl < n) ? A[(long long)(ri + i) * n + gl] : 0.0;
+    Lj[i][l] = (rj + i < n && gl < n) ? A[(long long)(rj + i) * n + gl] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, j = e % TB;
+    const int gi = ri + i, gj = rj + j;
+    if (gi < n && gj < n && gj <= gi) {
+      double acc = 0;
+#pragma unroll 8
+      for (int l = 0; l < TB; ++l) acc += Li[i][l] * Lj[j][l];
+      A[(long long)gi * n + gj] -= acc;
+    }
+  }
+}
+
+hipError_t cholesky_lower(double* A, int n, int* info_dev, double* scratch, hipStream_t s) {
+  for (int k0 = 0; k0 < n; k0 += TB) {
+    const int nrb = (n - k0 + TB - 1) / TB;
+    hipLaunchKernelGGL(potrf_panel_kernel, dim3(nrb), dim3(kThreads), 0, s, A, n, k0, info_dev, scratch);
+    hipLaunchKernelGGL(copy_diag_kernel, dim3(1), dim3(kThreads), 0, s, A, n, k0, (const double*)scratch);
+    const int k1 = k0 + TB;
+    if (k1 < n) {
+      const int nt = (n - k1 + TB - 1) / TB;
+      hipLaunchKernelGGL(syrk_update_kernel, dim3(nt * (nt + 1) / 2), dim3(kThreads), 0, s, A, n, k0);
+    }
+  }
+  return hipGetLastError();
+}
+
+__global__ void eye_kernel(double* W, int n) {
+  const long long total = (long long)n * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x)
+    W[e] = (e / n == e % n) ? 1.0 : 0.0;
+}
+// W[k0:k0+TB, 0:ncols] = L11^-1 W[k0:k0+TB, 0:ncols]   (thread per column)
+__global__ void trsm_diag_kernel(double* W, const double* L, int n, int k0, int ncols) {
+  __shared__ double L11[TB][TB + 1];
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, j = e % TB;
+    const int gi = k0 + i, gj = k0 + j;
+    L11[i][j] = (gi < n && gj < n) ? L[(long long)gi * n + gj] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  const int col = blockIdx.x * blockDim.x + tid;
+  if (col >= ncols) return;
+  double x[TB];
+#pragma unroll
+  for (int i = 0; i < TB; ++i) x[i] = (k0 + i < n) ? W[(long long)(k0 + i) * n + col] : 0.0;
+#pragma unroll
+  for (int i = 0; i < TB; ++i) {
+    double v = x[i];
+    for (int l = 0; l < i; ++l) v -= L11[i][l] * x[l];
+    x[i] = v / L11[i][i];
+  }
+#pragma unroll
+  for (int i = 0; i < TB; ++i)
+    if (k0 + i < n) W[(long long)(k0 + i) * n + col] = x[i];
+}
+// W[r][c] -= sum_l L[r][k0+l] W[k0+l][c] for r >= k0+TB, c < ncols
+__global__ void trsm_update_kernel(double* W, const double* L, int n, int k0, int ncols) {
+  __shared__ double Ls[TB][TB + 1];
+  __shared__ double Ws[TB][TB + 1];
+  const int r0 = k0 + TB + blockIdx.y * TB;
+  const int c0 = blockIdx.x * TB;
+  const int tid = threadIdx.x;
+  for (int e = tid; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, l = e % TB;
+    Ls[i][l] = (r0 + i < n && k0 + l < n) ? L[(long long)(r0 + i) * n + k0 + l] : 0.0;
+    Ws[i][l] = (k0 + i < n && c0 + l < ncols) ? W[(long long)(k0 + i) * n + c0 + l] : 0.0;
+  }
+  __syncthreads();
+  for (int e = tid; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, j = e % TB;
+    if (r0 + i < n && c0 + j < ncols) {
+      double acc = 0;
+#pragma unroll 8
+      for (int l = 0; l < TB; ++l) acc += Ls[i][l] * Ws[l][j];
+      W[(long long)(r0 + i) * n + c0 + j] -= acc;
+    }
+  }
+}
+
+hipError_t tri_inverse_lower(double* W, const double* L, int n, hipStream_t s) {
+  const long long total = (long long)n * n;
+  long long nb = (total + kThreads - 1) / kThreads;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(eye_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, W, n);
+  for (int k0 = 0; k0 < n; k0 += TB) {
+    const int ncols = k0 + TB < n ? k0 + TB : n;
+    hipLaunchKernelGGL(trsm_diag_kernel, dim3((ncols + kThreads - 1) / kThreads), dim3(kThreads), 0, s, W, L, n, k0, ncols);
+    const int rows = n - (k0 + TB);
+    if (rows > 0) {
+      dim3 grid((ncols + TB - 1) / TB, (rows + TB - 1) / TB);
+      hipLaunchKernelGGL(trsm_update_kernel, grid, dim3(kThreads), 0, s, W, L, n, k0, ncols);
+    }
+  }
+  return hipGetLastError();
+}
+
+__global__ void transpose_kernel(double* At, const double* A, int n) {
+  __shared__ double t[TB][TB + 1];
+  const int bx = blockIdx.x * TB, by = blockIdx.y * TB;
+  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, j = e % TB;
+    if (by + i < n && bx + j < n) t[i][j] = A[(long long)(by + i) * n + bx + j];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
+    const int i = e / TB, j = e % TB;
+    if (bx + i < n && by + j < n) At[(long long)(bx + i) * n + by + j] = t[j][i];
+  }
+}
+void k_transpose(double* At, const double* A, int n, hipStream_t s) {
+  dim3 grid((n + TB - 1) / TB, (n + TB - 1) / TB);
+  hipLaunchKernelGGL(transpose_kernel, grid, dim3(kThreads), 0, s, At, A, n);
+}
+
+// y = alpha * A x + yin  (one wave per row)
+__global__ void gemv_kernel(double* y, const double* A, long long lda, const double* x, int rows, int cols, double alpha,
+                            const double* yin) {
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+  if (row >= rows) return;
+  const double* a = A + (long long)row * lda;
+  double acc = 0;
+  for (int j = lane; j < cols; j += 64) acc += a[j] * x[j];
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
+  if (lane == 0) y[row] = alpha * acc + (yin ? yin[row] : 0.0);
+}
+void k_gemv(double* y, const double* A, long long lda, const double* x, int rows, int cols, double alpha, const double* yin,
+            hipStream_t s) {
+  const int rpb = kThreads / 64;
+  hipLaunchKernelGGL(gemv_kernel, dim3((rows + rpb - 1) / rpb), dim3(kThreads), 0, s, y, A, lda, x, rows, cols, alpha, yin);
+}
+
+}  // namespace mfpff

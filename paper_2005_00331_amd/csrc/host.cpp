@@ -1,0 +1,1111 @@
+// Host solver core and C ABI of libmfpff (see include/mfpff.h).
+//
+// Orchestrates the GPU kernels: level hierarchy set-up, linearisation
+// (field injection, diagonals, CG-Lanczos estimates, coarse factorisation),
+// the monolithic V-cycle of Section 3.3, flexible GMRES with classical
+// Gram-Schmidt twice (Givens rotations on the host), and the active-set
+// Newton step of Algorithm 1.  All device work is enqueued on one stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/mfpff.h"
+#include "internal.h"
+
+using namespace mfpff;
+
+namespace {
+
+struct HipError {
+  hipError_t e;
+  const char* what;
+};
+struct StatusError {
+  mfpff_status st;
+  std::string msg;
+};
+
+#define HIPCHK(call)                                  \
+  do {                                                \
+    hipError_t _e = (call);                           \
+    if (_e != hipSuccess) throw HipError{_e, #call};  \
+  } while (0)
+
+#define LAUNCHCHK() HIPCHK(hipGetLastError())
+
+template <typename T>
+T* dalloc(size_t n) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw StatusError{MFPFF_ERR_OOM, "device allocation failed"};
+  return (T*)p;
+}
+
+struct HostSparse {
+  int n_out = 0, n_in = 0, width = 0;
+  std::vector<int> col;
+  std::vector<double> val;
+};
+
+struct DevSparse {
+  Sparse1D s{};
+  int* col = nullptr;
+  double* val = nullptr;
+  float* valf = nullptr;
+};
+
+struct Level {
+  Geom g{};
+  long long nn = 0, n = 0;
+  double* lin = nullptr;   // (d+2)*nn
+  float* lin32 = nullptr;
+  uint8_t* mask = nullptr;
+  double* dinv = nullptr;
+  float* dinv32 = nullptr;
+  double* diag = nullptr;  // FP64 diagonal of G^ (1 at fixed dofs)
+  double lam[2] = {1.0, 1.0};
+  int lsteps[2] = {0, 0};
+  std::vector<double> c1u, c2u, c1p, c2p;  // Chebyshev step coefficients, index i = 1..s-1
+  double ith_u = 1.0, ith_p = 1.0;
+  void* w[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // V-cycle vectors b, x, r, t, d, z
+  DevSparse P1, R1;  // transfer from level-1 to this level
+};
+enum { WB = 0, WX = 1, WR = 2, WT = 3, WD = 4, WZ = 5 };
+
+}  // namespace
+
+struct mfpff_ctx {
+  mfpff_problem prob{};
+  hipStream_t s = nullptr;
+  int dim = 2, L = 0;  // L = index of the finest level
+  bool f32 = false;
+  std::vector<Level> lv;
+  Tables<double>* tab64[kMaxDeg + 1] = {};
+  Tables<float>* tab32[kMaxDeg + 1] = {};
+  double* w1d = nullptr;  // integrals of the finest-degree 1D basis functions
+  double* ml = nullptr;   // lumped phi mass on the finest level
+  // transfer temporaries (finest-level size)
+  double* t64a = nullptr;
+  double* t64b = nullptr;
+  float* t32a = nullptr;
+  float* t32b = nullptr;
+  // coarse solve
+  int nu0 = 0, np0 = 0;
+  double* dense = nullptr;
+  double* Auu = nullptr;
+  double* App = nullptr;
+  double* Wu = nullptr;
+  double* WuT = nullptr;
+  double* Wp = nullptr;
+  double* WpT = nullptr;
+  double* Gpu = nullptr;
+  double* cs_in = nullptr;
+  double* cs_out = nullptr;
+  double* cs_t = nullptr;
+  int* info_dev = nullptr;
+  double* chol_scratch = nullptr;
+  // Lanczos / scratch (finest size, FP64)
+  LanczosState* lst = nullptr;
+  double* s64[5] = {};
+  double* part = nullptr;
+  int part_len = 0;
+  // GMRES
+  int m = 30;
+  double* V = nullptr;
+  double* Z = nullptr;
+  double* gw = nullptr;
+  double* gr = nullptr;
+  double* hdev = nullptr;
+  double* hhost = nullptr;
+  double* ycoef = nullptr;
+  // Newton
+  double* R = nullptr;
+  double* b = nullptr;
+  double* dU = nullptr;
+  double* pvjp_part = nullptr;
+  double* pvjp_out = nullptr;
+  bool linearized = false;
+  std::string err;
+};
+
+namespace {
+
+Geom make_geom(int dim, int N, int k) {
+  Geom g{};
+  g.dim = dim;
+  g.k = k;
+  g.N = N;
+  g.M = k * N + 1;
+  g.n_nodes = 1;
+  for (int a = 0; a < dim; ++a) g.n_nodes *= g.M;
+  g.h = 1.0 / N;
+  return g;
+}
+
+double lagr(int k, int j, double x) {
+  double v = 1.0;
+  for (int m = 0; m <= k; ++m)
+    if (m != j) v *= (x - (double)m / k) / ((double)j / k - (double)m / k);
+  return v;
+}
+
+// 1D prolongation: fine node i gets the coarse basis values at its position.
+void build_transfer(const Geom& gf, const Geom& gc, HostSparse& P, HostSparse& R) {
+  const long long den = (long long)gf.k * gf.N;
+  std::vector<std::vector<std::pair<int, double>>> rows(gf.M), cols(gc.M);
+  for (int i = 0; i < gf.M; ++i) {
+    long long cell = (long long)i * gc.N / den;
+    if (cell > gc.N - 1) cell = gc.N - 1;
+    const double xi = (double)((long long)i * gc.N - cell * den) / (double)den;
+    for (int j = 0; j <= gc.k; ++j) {
+      const double w = lagr(gc.k, j, xi);
+      if (w != 0.0) {
+        const int jc = (int)(gc.k * cell + j);
+        rows[i].push_back({jc, w});
+        cols[jc].push_back({i, w});
+      }
+    }
+  }
+  auto pack = [](std::vector<std::vector<std::pair<int, double>>>& lst, int nin, HostSparse& S) {
+    S.n_out = (int)lst.size();
+    S.n_in = nin;
+    S.width = 0;
+    for (auto& r : lst) S.width = std::max(S.width, (int)r.size());
+    S.col.assign((size_t)S.n_out * S.width, -1);
+    S.val.assign((size_t)S.n_out * S.width, 0.0);
+    for (int o = 0; o < S.n_out; ++o)
+      for (size_t j = 0; j < lst[o].size(); ++j) {
+        S.col[(size_t)o * S.width + j] = lst[o][j].first;
+        S.val[(size_t)o * S.width + j] = lst[o][j].second;
+      }
+  };
+  pack(rows, gc.M, P);
+  pack(cols, gf.M, R);
+}
+
+DevSparse upload(const HostSparse& h, hipStream_t s) {
+  DevSparse d;
+  const size_t n = (size_t)h.n_out * h.width;
+  d.col = dalloc<int>(n);
+  d.val = dalloc<double>(n);
+  d.valf = dalloc<float>(n);
+  std::vector<float> vf(h.val.begin(), h.val.end());
+  HIPCHK(hipMemcpy(d.col, h.col.data(), n * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d.val, h.val.data(), n * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d.valf, vf.data(), n * sizeof(float), hipMemcpyHostToDevice));
+  d.s.n_out = h.n_out;
+  d.s.n_in = h.n_in;
+  d.s.width = h.width;
+  d.s.col = d.col;
+  d.s.val = d.val;
+  d.s.valf = d.valf;
+  return d;
+}
+
+// Largest eigenvalue of the symmetric tridiagonal (diag a, off b) by Sturm bisection.
+double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& b) {
+  const int n = (int)a.size();
+  if (n == 0) return 1.0;
+  double lo = a[0], hi = a[0];
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::fabs(b[i - 1]) : 0.0) + (i < n - 1 ? std::fabs(b[i]) : 0.0);
+    lo = std::min(lo, a[i] - r);
+    hi = std::max(hi, a[i] + r);
+  }
+  // count of eigenvalues < x
+  auto count = [&](double x) {
+    int c = 0;
+    double q = a[0] - x;
+    if (q < 0) ++c;
+    for (int i = 1; i < n; ++i) {
+      const double qq = (q == 0.0) ? 1e-300 : q;
+      q = a[i] - x - b[i - 1] * b[i - 1] / qq;
+      if (q < 0) ++c;
+    }
+    return c;
+  };
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (mid <= lo || mid >= hi) break;
+    if (count(mid) >= n) hi = mid;  // all eigenvalues below mid
+    else lo = mid;
+  }
+  return 0.5 * (lo + hi);
+}
+
+template <typename T>
+CellArgs<T> cell_args(mfpff_ctx* c, const Level& L, const T* lin, const T* x, T* y, T scale) {
+  CellArgs<T> a{};
+  a.g = L.g;
+  a.m = MatParams{c->prob.lambda, c->prob.mu, c->prob.Gc, c->prob.eps, c->prob.kappa};
+  a.x = x;
+  a.y = y;
+  a.u = lin;
+  a.phi = lin + (size_t)c->dim * L.nn;
+  a.phit = lin + (size_t)(c->dim + 1) * L.nn;
+  a.mask = L.mask;
+  a.scale = scale;
+  return a;
+}
+
+template <typename T>
+const T* level_lin(mfpff_ctx* c, const Level& L);
+template <>
+const double* level_lin<double>(mfpff_ctx*, const Level& L) { return L.lin; }
+template <>
+const float* level_lin<float>(mfpff_ctx*, const Level& L) { return L.lin32; }
+template <typename T>
+const T* level_dinv(const Level& L);
+template <>
+const double* level_dinv<double>(const Level& L) { return L.dinv; }
+template <>
+const float* level_dinv<float>(const Level& L) { return L.dinv32; }
+template <typename T>
+const Tables<T>* tab(mfpff_ctx* c, int k);
+template <>
+const Tables<double>* tab<double>(mfpff_ctx* c, int k) { return c->tab64[k]; }
+template <>
+const Tables<float>* tab<float>(mfpff_ctx* c, int k) { return c->tab32[k]; }
+
+// y = op(G^) x on level l, or y = b - G^ x when b != null (op = G)
+template <typename T>
+void apply_op(mfpff_ctx* c, int l, int mode, const T* x, T* y, const T* b) {
+  Level& L = c->lv[l];
+  const T scale = b ? T(-1) : T(1);
+  k_mask_init<T>(y, b, x, L.mask, L.nn, c->dim, scale, c->s);
+  LAUNCHCHK();
+  CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), x, y, scale);
+  HIPCHK(launch_cell<T>(mode, a, tab<T>(c, L.g.k), c->s));
+}
+
+// z = diag(C_u, C_phi) r (Chebyshev from zero), work vectors d, t
+template <typename T>
+void chebyshev(mfpff_ctx* c, int l, const T* r, T* z, T* d, T* t) {
+  Level& L = c->lv[l];
+  const T* dinv = level_dinv<T>(L);
+  k_cheb_init<T>(z, d, r, dinv, L.nn, c->dim, (T)L.ith_u, (T)L.ith_p, c->s);
+  LAUNCHCHK();
+  for (size_t i = 0; i < L.c1u.size(); ++i) {
+    apply_op<T>(c, l, MODE_BLOCK, z, t, nullptr);
+    k_cheb_step<T>(z, d, r, t, dinv, L.nn, c->dim, (T)L.c1u[i], (T)L.c2u[i], (T)L.c1p[i], (T)L.c2p[i], c->s);
+    LAUNCHCHK();
+  }
+}
+
+// separable masked transfer; dir 0: out(level l) = P~ in(level l-1) [add to out if add];
+// dir 1: out(level l-1) = R~ in(level l)
+template <typename T>
+void transfer(mfpff_ctx* c, int l, int dir, const T* in, T* out, bool add, T* ta, T* tb) {
+  Level& F = c->lv[l];
+  Level& C = c->lv[l - 1];
+  const int d = c->dim, nc = d + 1;
+  if (dir == 0) {
+    k_copy<T>(ta, in, C.n, c->s);
+    k_mask_comp<T>(ta, C.mask, C.nn, d, c->s);
+    long long dims[3] = {C.g.M, C.g.M, C.g.M};
+    T* src = ta;
+    T* dst = tb;
+    for (int ax = 0; ax < d; ++ax) {
+      const bool last = ax == d - 1;
+      T* o = (last && !add) ? out : dst;
+      k_axis_apply<T>(o, src, F.P1.s, ax, d, dims, nc, c->s);
+      dims[ax] = F.g.M;
+      if (!last) std::swap(src, dst);
+      else src = o;
+    }
+    if (add) k_add_masked<T>(out, src, F.mask, F.nn, d, c->s);
+    else k_mask_comp<T>(out, F.mask, F.nn, d, c->s);
+  } else {
+    k_copy<T>(ta, in, F.n, c->s);
+    k_mask_comp<T>(ta, F.mask, F.nn, d, c->s);
+    long long dims[3] = {F.g.M, F.g.M, F.g.M};
+    T* src = ta;
+    T* dst = tb;
+    for (int ax = 0; ax < d; ++ax) {
+      const bool last = ax == d - 1;
+      T* o = last ? out : dst;
+      k_axis_apply<T>(o, src, F.R1.s, ax, d, dims, nc, c->s);
+      dims[ax] = C.g.M;
+      std::swap(src, dst);
+    }
+    k_mask_comp<T>(out, C.mask, C.nn, d, c->s);
+  }
+  LAUNCHCHK();
+}
+
+void coarse_solve64(mfpff_ctx* c, const double* r, double* x) {
+  const int nu = c->nu0, np = c->np0;
+  k_gemv(c->cs_t, c->Wu, nu, r, nu, nu, 1.0, nullptr, c->s);
+  k_gemv(x, c->WuT, nu, c->cs_t, nu, nu, 1.0, nullptr, c->s);
+  k_gemv(c->cs_t + nu, c->Gpu, nu, x, np, nu, -1.0, r + nu, c->s);
+  k_gemv(c->cs_t, c->Wp, np, c->cs_t + nu, np, np, 1.0, nullptr, c->s);
+  k_gemv(x + nu, c->WpT, np, c->cs_t, np, np, 1.0, nullptr, c->s);
+  LAUNCHCHK();
+}
+
+template <typename T>
+void coarse_solve_T(mfpff_ctx* c, const T* r, T* x);
+template <>
+void coarse_solve_T<double>(mfpff_ctx* c, const double* r, double* x) {
+  coarse_solve64(c, r, x);
+}
+template <>
+void coarse_solve_T<float>(mfpff_ctx* c, const float* r, float* x) {
+  const long long n = c->lv[0].n;
+  k_cast_f2d(c->cs_in, r, n, c->s);
+  coarse_solve64(c, c->cs_in, c->cs_out);
+  k_cast_d2f(x, c->cs_out, n, c->s);
+}
+
+template <typename T>
+void vcycle_rec(mfpff_ctx* c, int l) {
+  Level& L = c->lv[l];
+  T* b = (T*)L.w[WB];
+  T* x = (T*)L.w[WX];
+  if (l == 0) {
+    coarse_solve_T<T>(c, b, x);
+    return;
+  }
+  T* r = (T*)L.w[WR];
+  T* t = (T*)L.w[WT];
+  T* d = (T*)L.w[WD];
+  T* z = (T*)L.w[WZ];
+  T* ta = std::is_same<T, double>::value ? (T*)c->t64a : (T*)c->t32a;
+  T* tb = std::is_same<T, double>::value ? (T*)c->t64b : (T*)c->t32b;
+  chebyshev<T>(c, l, b, x, d, t);
+  apply_op<T>(c, l, MODE_APPLY, x, r, b);
+  transfer<T>(c, l, 1, r, (T*)c->lv[l - 1].w[WB], false, ta, tb);
+  vcycle_rec<T>(c, l - 1);
+  transfer<T>(c, l, 0, (const T*)c->lv[l - 1].w[WX], x, true, ta, tb);
+  apply_op<T>(c, l, MODE_APPLY, x, r, b);
+  chebyshev<T>(c, l, r, z, d, t);
+  k_axpy<T>(x, T(1), z, L.n, c->s);
+  LAUNCHCHK();
+}
+
+// z = V(r) on the finest level, FP64 in/out
+void precondition(mfpff_ctx* c, const double* r, double* z) {
+  Level& F = c->lv[c->L];
+  if (c->f32) {
+    k_cast_d2f((float*)F.w[WB], r, F.n, c->s);
+    vcycle_rec<float>(c, c->L);
+    k_cast_f2d(z, (const float*)F.w[WX], F.n, c->s);
+  } else {
+    k_copy<double>((double*)F.w[WB], r, F.n, c->s);
+    vcycle_rec<double>(c, c->L);
+    k_copy<double>(z, (const double*)F.w[WX], F.n, c->s);
+  }
+  LAUNCHCHK();
+}
+
+void cheb_coefficients(mfpff_ctx* c, Level& L) {
+  const int s = c->prob.cheb_degree;
+  L.c1u.clear();
+  L.c2u.clear();
+  L.c1p.clear();
+  L.c2p.clear();
+  double th[2], de[2], rho[2];
+  for (int b = 0; b < 2; ++b) {
+    const double lo = c->prob.cheb_lo * L.lam[b], hi = c->prob.cheb_hi * L.lam[b];
+    th[b] = 0.5 * (hi + lo);
+    de[b] = 0.5 * (hi - lo);
+    rho[b] = de[b] / th[b];  // 1/sigma
+  }
+  L.ith_u = 1.0 / th[0];
+  L.ith_p = 1.0 / th[1];
+  for (int i = 1; i < s; ++i) {
+    double c1[2], c2[2];
+    for (int b = 0; b < 2; ++b) {
+      const double sigma = th[b] / de[b];
+      const double rn = 1.0 / (2.0 * sigma - rho[b]);
+      c1[b] = rn * rho[b];
+      c2[b] = 2.0 * rn / de[b];
+      rho[b] = rn;
+    }
+    L.c1u.push_back(c1[0]);
+    L.c2u.push_back(c2[0]);
+    L.c1p.push_back(c1[1]);
+    L.c2p.push_back(c2[1]);
+  }
+}
+
+void lanczos_level(mfpff_ctx* c, int l) {
+  Level& L = c->lv[l];
+  const long long n = L.n, nu = (long long)c->dim * L.nn;
+  double *v = c->s64[0], *r = c->s64[1], *z = c->s64[2], *p = c->s64[3], *t = c->s64[4];
+  LanczosState* st = c->lst + l;
+  const int nb = dot_blocks(n);
+  k_splitmix_start(v, L.mask, L.nn, c->dim, c->prob.lanczos_seed, 2 * l, 2 * l + 1, c->s);
+  k_copy<double>(r, v, n, c->s);
+  k_lanczos_rz_partials(c->part, r, L.dinv, z, nu, n, c->s);
+  k_lanczos_init(st, c->part, nb, c->s);
+  k_copy<double>(p, z, n, c->s);
+  for (int j = 0; j < c->prob.lanczos_steps; ++j) {
+    apply_op<double>(c, l, MODE_BLOCK, p, t, nullptr);
+    k_seg_dot_partials(c->part, p, t, nu, n, c->s);
+    k_lanczos_alpha(st, c->part, nb, j, c->s);
+    k_lanczos_update_r(r, z, c->part, t, L.dinv, st, nu, n, c->s);
+    k_lanczos_beta(st, c->part, nb, j, c->s);
+    k_lanczos_update_p(p, z, st, nu, n, c->s);
+  }
+  LAUNCHCHK();
+}
+
+void coarse_setup(mfpff_ctx* c) {
+  Level& C = c->lv[0];
+  const long long n = C.n;
+  HIPCHK(hipMemsetAsync(c->dense, 0, (size_t)n * n * sizeof(double), c->s));
+  CellArgs<double> a = cell_args<double>(c, C, C.lin, nullptr, nullptr, 1.0);
+  a.dense = c->dense;
+  a.ld = n;
+  HIPCHK(launch_cell<double>(MODE_ELEM, a, c->tab64[C.g.k], c->s));
+  k_dense_set_fixed_diag(c->dense, n, C.mask, C.nn, c->dim, c->s);
+  const int nu = c->nu0, np = c->np0;
+  k_extract_block(c->Auu, nu, c->dense, n, 0, 0, nu, nu, c->s);
+  k_extract_block(c->App, np, c->dense, n, nu, nu, np, np, c->s);
+  k_extract_block(c->Gpu, nu, c->dense, n, nu, 0, np, nu, c->s);
+  HIPCHK(hipMemsetAsync(c->info_dev, 0, 2 * sizeof(int), c->s));
+  HIPCHK(cholesky_lower(c->Auu, nu, c->info_dev, c->chol_scratch, c->s));
+  HIPCHK(cholesky_lower(c->App, np, c->info_dev + 1, c->chol_scratch, c->s));
+  HIPCHK(tri_inverse_lower(c->Wu, c->Auu, nu, c->s));
+  HIPCHK(tri_inverse_lower(c->Wp, c->App, np, c->s));
+  k_transpose(c->WuT, c->Wu, nu, c->s);
+  k_transpose(c->WpT, c->Wp, np, c->s);
+  LAUNCHCHK();
+}
+
+void require_state(mfpff_ctx* c) {
+  if (!c->linearized) throw StatusError{MFPFF_ERR_STATE, "set_linearization has not been called"};
+}
+void require_level(mfpff_ctx* c, int l) {
+  if (l < 0 || l > c->L) throw StatusError{MFPFF_ERR_ARG, "level index out of range"};
+}
+void require_ptr(const void* p, const char* name) {
+  if (!p) throw StatusError{MFPFF_ERR_ARG, std::string("null pointer: ") + name};
+}
+
+void ensure_gmres(mfpff_ctx* c) {
+  if (c->V) return;
+  const long long n = c->lv[c->L].n;
+  c->m = c->prob.restart;
+  c->V = dalloc<double>((size_t)(c->m + 1) * n);
+  c->Z = dalloc<double>((size_t)c->m * n);
+  c->gw = dalloc<double>(n);
+  c->gr = dalloc<double>(n);
+  c->hdev = dalloc<double>(4 * 80);
+  c->ycoef = dalloc<double>(80);
+  HIPCHK(hipHostMalloc((void**)&c->hhost, 4 * 80 * sizeof(double), hipHostMallocDefault));
+}
+
+double dev_norm(mfpff_ctx* c, const double* x, long long n, double* out_dev) {
+  const int nb = dot_blocks(n);
+  k_multidot_partials(c->part, x, n, 1, x, n, c->s);
+  k_multidot_finish(out_dev, c->part, nb, 1, c->s);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(c->hhost, out_dev, sizeof(double), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  return std::sqrt(c->hhost[0]);
+}
+
+// Right-preconditioned FGMRES(m), CGS2, x0 = 0.
+mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* info) {
+  ensure_gmres(c);
+  const int m = c->m;
+  const long long n = c->lv[c->L].n;
+  const int nb = dot_blocks(n);
+  double* h1 = c->hdev;        // j+1 values
+  double* h2 = c->hdev + 80;   // j+1 values
+  double* hn = c->hdev + 160;  // norm^2 then norm
+  k_fill<double>(x, 0.0, n, c->s);
+  const double bnorm = dev_norm(c, b, n, hn);
+  int it = 0;
+  const double tol = c->prob.rtol * bnorm;
+  std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+  double relres = 0.0;
+  bool conv = false;
+  if (bnorm == 0.0) {
+    conv = true;
+  }
+  while (!conv) {
+    // r = b - G^ x
+    apply_op<double>(c, c->L, MODE_APPLY, x, c->gr, b);
+    const double beta = dev_norm(c, c->gr, n, hn);
+    relres = beta / bnorm;
+    if (beta <= tol) {
+      conv = true;
+      break;
+    }
+    if (it >= c->prob.max_iter) break;
+    std::fill(H.begin(), H.end(), 0.0);
+    std::fill(g.begin(), g.end(), 0.0);
+    g[0] = beta;
+    c->hhost[200] = beta;  // pinned staging; the stream orders it before later copies into hhost
+    HIPCHK(hipMemcpyAsync(c->ycoef, &c->hhost[200], sizeof(double), hipMemcpyHostToDevice, c->s));
+    k_scale_dev(c->V, c->gr, c->ycoef, n, c->s);
+    int jend = 0;
+    for (int j = 0; j < m; ++j) {
+      double* vj = c->V + (size_t)j * n;
+      double* zj = c->Z + (size_t)j * n;
+      precondition(c, vj, zj);
+      apply_op<double>(c, c->L, MODE_APPLY, zj, c->gw, nullptr);
+      // CGS2
+      k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
+      k_multidot_finish(h1, c->part, nb, j + 1, c->s);
+      k_maxpy_dev(c->gw, c->V, n, j + 1, h1, -1.0, n, c->s);
+      k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
+      k_multidot_finish(h2, c->part, nb, j + 1, c->s);
+      k_maxpy_dev(c->gw, c->V, n, j + 1, h2, -1.0, n, c->s);
+      k_multidot_partials(c->part, c->gw, n, 1, c->gw, n, c->s);
+      k_multidot_finish(hn, c->part, nb, 1, c->s);
+      LAUNCHCHK();
+      HIPCHK(hipMemcpyAsync(c->hhost, c->hdev, 3 * 80 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+      HIPCHK(hipStreamSynchronize(c->s));
+      const double hnorm = std::sqrt(c->hhost[160]);
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = c->hhost[i] + c->hhost[80 + i];
+      H[(size_t)(j + 1) * m + j] = hnorm;
+      for (int i = 0; i < j; ++i) {
+        const double tmp = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)(i + 1) * m + j] = -sn[i] * H[(size_t)i * m + j] + cs[i] * H[(size_t)(i + 1) * m + j];
+        H[(size_t)i * m + j] = tmp;
+      }
+      const double a = H[(size_t)j * m + j], bb = H[(size_t)(j + 1) * m + j];
+      if (bb == 0.0) {
+        cs[j] = 1.0;
+        sn[j] = 0.0;
+      } else {
+        const double rr = std::hypot(a, bb);
+        cs[j] = a / rr;
+        sn[j] = bb / rr;
+      }
+      H[(size_t)j * m + j] = cs[j] * a + sn[j] * bb;
+      H[(size_t)(j + 1) * m + j] = 0.0;
+      g[j + 1] = -sn[j] * g[j];
+      g[j] = cs[j] * g[j];
+      ++it;
+      jend = j + 1;
+      if (std::fabs(g[j + 1]) <= tol || it >= c->prob.max_iter || hnorm == 0.0) break;
+      c->hhost[200] = hnorm;
+      HIPCHK(hipMemcpyAsync(c->ycoef, &c->hhost[200], sizeof(double), hipMemcpyHostToDevice, c->s));
+      k_scale_dev(c->V + (size_t)(j + 1) * n, c->gw, c->ycoef, n, c->s);
+    }
+    for (int i = jend - 1; i >= 0; --i) {
+      double sacc = g[i];
+      for (int k = i + 1; k < jend; ++k) sacc -= H[(size_t)i * m + k] * y[k];
+      y[i] = sacc / H[(size_t)i * m + i];
+    }
+    for (int i = 0; i < jend; ++i) c->hhost[240 + i] = y[i];
+    HIPCHK(hipMemcpyAsync(c->ycoef, &c->hhost[240], jend * sizeof(double), hipMemcpyHostToDevice, c->s));
+    k_maxpy_dev(x, c->Z, n, jend, c->ycoef, 1.0, n, c->s);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(c->s));  // ycoef host staging is reused next cycle
+  }
+  if (info) {
+    info->iterations = it;
+    info->converged = conv ? 1 : 0;
+    info->rel_residual = relres;
+  }
+  return conv ? MFPFF_OK : MFPFF_ERR_NOCONV;
+}
+
+void set_linearization(mfpff_ctx* c, const double* u, const double* phi, const double* phi_old, const uint8_t* active,
+                       const double* phit) {
+  const int d = c->dim;
+  Level& F = c->lv[c->L];
+  k_fine_fields(F.lin, F.mask, u, phi, phit ? phit : phi_old, active, F.g, c->prob.dirichlet, c->s);
+  LAUNCHCHK();
+  for (int l = c->L - 1; l >= 0; --l) {
+    k_inject(c->lv[l].lin, c->lv[l].mask, c->lv[l + 1].lin, c->lv[l + 1].mask, c->lv[l].g, c->lv[l + 1].g,
+             c->prob.dirichlet, c->s);
+    LAUNCHCHK();
+  }
+  for (int l = 0; l <= c->L; ++l) {
+    Level& L = c->lv[l];
+    if (c->f32) k_cast_d2f(L.lin32, L.lin, (long long)(d + 2) * L.nn, c->s);
+    // diagonal
+    double* tmp = c->s64[0];
+    k_fill<double>(tmp, 0.0, L.n, c->s);
+    CellArgs<double> a = cell_args<double>(c, L, L.lin, nullptr, tmp, 1.0);
+    HIPCHK(launch_diag<double>(a, c->tab64[L.g.k], c->s));
+    k_diag_finish<double>(L.dinv, L.diag, tmp, L.mask, L.nn, d, c->s);
+    if (c->f32) k_cast_d2f(L.dinv32, L.dinv, L.n, c->s);
+    LAUNCHCHK();
+  }
+  for (int l = 1; l <= c->L; ++l) lanczos_level(c, l);
+  coarse_setup(c);
+  // read back Lanczos scalars and the factorisation status
+  std::vector<LanczosState> hs(c->L + 1);
+  HIPCHK(hipMemcpyAsync(hs.data(), c->lst, (c->L + 1) * sizeof(LanczosState), hipMemcpyDeviceToHost, c->s));
+  int info[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(info, c->info_dev, 2 * sizeof(int), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (info[0] || info[1]) throw StatusError{MFPFF_ERR_NUMERIC, "coarse Cholesky factorisation failed (non-positive pivot)"};
+  for (int l = 1; l <= c->L; ++l) {
+    Level& L = c->lv[l];
+    for (int b = 0; b < 2; ++b) {
+      const int cnt = hs[l].count[b];
+      std::vector<double> dg(cnt), off(cnt > 0 ? cnt - 1 : 0);
+      for (int j = 0; j < cnt; ++j) {
+        const double al = hs[l].alphas[b][j];
+        dg[j] = 1.0 / al + (j > 0 ? hs[l].betas[b][j - 1] / hs[l].alphas[b][j - 1] : 0.0);
+        if (j < cnt - 1) off[j] = std::sqrt(hs[l].betas[b][j]) / al;
+      }
+      L.lam[b] = cnt == 0 ? 1.0 : (cnt == 1 ? dg[0] : tridiag_max_eig(dg, off));
+      L.lsteps[b] = cnt;
+    }
+    cheb_coefficients(c, L);
+  }
+  c->linearized = true;
+}
+
+}  // namespace
+
+namespace {
+mfpff_status run(mfpff_ctx* c, const std::function<mfpff_status()>& fn) {
+  if (!c) return MFPFF_ERR_ARG;
+  try {
+    c->err.clear();
+    return fn();
+  } catch (const StatusError& e) {
+    c->err = e.msg;
+    return e.st;
+  } catch (const HipError& e) {
+    c->err = std::string("HIP error ") + hipGetErrorString(e.e) + " in " + e.what;
+    return MFPFF_ERR_HIP;
+  } catch (const std::exception& e) {
+    c->err = e.what();
+    return MFPFF_ERR_ARG;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx** out) {
+  if (!prob || !out) return MFPFF_ERR_ARG;
+  *out = nullptr;
+  const mfpff_problem& p = *prob;
+  if (p.dim != 2 && p.dim != 3) return MFPFF_ERR_ARG;
+  if (p.n_levels < 1 || p.n_levels > MFPFF_MAX_LEVELS) return MFPFF_ERR_ARG;
+  if (p.cheb_degree < 1 || p.cheb_degree > 32 || p.lanczos_steps < 0 || p.lanczos_steps > 64) return MFPFF_ERR_ARG;
+  if (p.restart < 1 || p.restart > 64 || p.max_iter < 0 || !(p.rtol >= 0.0)) return MFPFF_ERR_ARG;
+  if (p.vcycle_prec != MFPFF_F64 && p.vcycle_prec != MFPFF_F32) return MFPFF_ERR_ARG;
+  if (!(p.eps > 0.0) || !(p.kappa >= 0.0) || !(p.cheb_hi > p.cheb_lo) || !(p.cheb_lo > 0.0)) return MFPFF_ERR_ARG;
+  for (int l = 0; l < p.n_levels; ++l) {
+    if (p.level_N[l] < 1 || p.level_k[l] < 1 || p.level_k[l] > kMaxDeg) return MFPFF_ERR_ARG;
+    if (l > 0) {
+      const int Nc = p.level_N[l - 1], kc = p.level_k[l - 1], Nf = p.level_N[l], kf = p.level_k[l];
+      const bool hstep = (Nf == 2 * Nc && kf == kc);
+      const bool pstep = (Nf == Nc && kf > kc && kf % kc == 0);
+      if (!hstep && !pstep) return MFPFF_ERR_ARG;
+    }
+  }
+  mfpff_ctx* c = new mfpff_ctx();
+  c->prob = p;
+  c->s = (hipStream_t)hip_stream;
+  c->dim = p.dim;
+  c->L = p.n_levels - 1;
+  c->f32 = p.vcycle_prec == MFPFF_F32;
+  mfpff_status st = run(c, [&]() -> mfpff_status {
+    const int d = c->dim;
+    c->lv.resize(p.n_levels);
+    for (int l = 0; l < p.n_levels; ++l) {
+      Level& L = c->lv[l];
+      L.g = make_geom(d, p.level_N[l], p.level_k[l]);
+      L.nn = L.g.n_nodes;
+      L.n = (long long)(d + 1) * L.nn;
+      L.lin = dalloc<double>((size_t)(d + 2) * L.nn);
+      L.mask = dalloc<uint8_t>(L.nn);
+      L.dinv = dalloc<double>(L.n);
+      L.diag = dalloc<double>(L.n);
+      if (c->f32) {
+        L.lin32 = dalloc<float>((size_t)(d + 2) * L.nn);
+        L.dinv32 = dalloc<float>(L.n);
+      }
+      const size_t es = c->f32 ? sizeof(float) : sizeof(double);
+      for (int w = 0; w < 6; ++w) {
+        void* ptr = nullptr;
+        if (hipMalloc(&ptr, (size_t)L.n * es) != hipSuccess) throw StatusError{MFPFF_ERR_OOM, "device allocation failed"};
+        L.w[w] = ptr;
+      }
+      if (l > 0) {
+        HostSparse P, R;
+        build_transfer(L.g, c->lv[l - 1].g, P, R);
+        L.P1 = upload(P, c->s);
+        L.R1 = upload(R, c->s);
+      }
+      const int k = L.g.k;
+      if (!c->tab64[k]) {
+        Tables<double> t{};
+        make_tables(k, t);
+        Tables<float> tf{};
+        for (int i = 0; i <= kMaxDeg; ++i) {
+          tf.w[i] = (float)t.w[i];
+          for (int j = 0; j <= kMaxDeg; ++j) {
+            tf.B[i][j] = (float)t.B[i][j];
+            tf.D[i][j] = (float)t.D[i][j];
+            tf.C[i][j] = (float)t.C[i][j];
+          }
+        }
+        c->tab64[k] = dalloc<Tables<double>>(1);
+        c->tab32[k] = dalloc<Tables<float>>(1);
+        HIPCHK(hipMemcpy(c->tab64[k], &t, sizeof(t), hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(c->tab32[k], &tf, sizeof(tf), hipMemcpyHostToDevice));
+      }
+    }
+    Level& F = c->lv[c->L];
+    const long long nF = F.n;
+    c->t64a = dalloc<double>(nF);
+    c->t64b = dalloc<double>(nF);
+    if (c->f32) {
+      c->t32a = dalloc<float>(nF);
+      c->t32b = dalloc<float>(nF);
+    }
+    for (int i = 0; i < 5; ++i) c->s64[i] = dalloc<double>(nF);
+    c->part_len = 512 * 80;
+    c->part = dalloc<double>(c->part_len);
+    c->lst = dalloc<LanczosState>(c->L + 1);
+    HIPCHK(hipMemset(c->lst, 0, (c->L + 1) * sizeof(LanczosState)));
+    // coarse storage
+    Level& C = c->lv[0];
+    c->nu0 = (int)(d * C.nn);
+    c->np0 = (int)C.nn;
+    const size_t n0 = (size_t)C.n;
+    c->dense = dalloc<double>(n0 * n0);
+    c->Auu = dalloc<double>((size_t)c->nu0 * c->nu0);
+    c->App = dalloc<double>((size_t)c->np0 * c->np0);
+    c->Wu = dalloc<double>((size_t)c->nu0 * c->nu0);
+    c->WuT = dalloc<double>((size_t)c->nu0 * c->nu0);
+    c->Wp = dalloc<double>((size_t)c->np0 * c->np0);
+    c->WpT = dalloc<double>((size_t)c->np0 * c->np0);
+    c->Gpu = dalloc<double>((size_t)c->np0 * c->nu0);
+    c->cs_in = dalloc<double>(n0);
+    c->cs_out = dalloc<double>(n0);
+    c->cs_t = dalloc<double>(n0);
+    c->info_dev = dalloc<int>(2);
+    c->chol_scratch = dalloc<double>(32 * 32);
+    // lumped mass on the finest level: integrals of the 1D basis functions
+    Tables<double> t{};
+    make_tables(F.g.k, t);
+    double w1[kMaxDeg + 1] = {};
+    for (int i = 0; i <= F.g.k; ++i)
+      for (int q = 0; q <= F.g.k; ++q) w1[i] += t.w[q] * t.B[q][i];
+    c->w1d = dalloc<double>(kMaxDeg + 1);
+    HIPCHK(hipMemcpy(c->w1d, w1, sizeof(w1), hipMemcpyHostToDevice));
+    c->ml = dalloc<double>(F.nn);
+    k_lumped_mass(c->ml, F.g, c->w1d, c->s);
+    c->R = dalloc<double>(nF);
+    c->b = dalloc<double>(nF);
+    c->dU = dalloc<double>(nF);
+    const long long pb = cell_blocks(F.g, MODE_PVJP);
+    c->pvjp_part = dalloc<double>((size_t)2 * pb);
+    c->pvjp_out = dalloc<double>(2);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(c->s));
+    return MFPFF_OK;
+  });
+  if (st != MFPFF_OK) {
+    fprintf(stderr, "mfpff_create: %s\n", c->err.c_str());
+    mfpff_destroy(c);
+    return st;
+  }
+  *out = c;
+  return MFPFF_OK;
+}
+
+void mfpff_destroy(mfpff_ctx* c) {
+  if (!c) return;
+  if (c->s) hipStreamSynchronize(c->s);
+  else hipDeviceSynchronize();
+  auto F = [](void* p) {
+    if (p) hipFree(p);
+  };
+  for (auto& L : c->lv) {
+    F(L.lin);
+    F(L.lin32);
+    F(L.mask);
+    F(L.dinv);
+    F(L.dinv32);
+    F(L.diag);
+    for (auto w : L.w) F(w);
+    F(L.P1.col);
+    F(L.P1.val);
+    F(L.P1.valf);
+    F(L.R1.col);
+    F(L.R1.val);
+    F(L.R1.valf);
+  }
+  for (int k = 0; k <= kMaxDeg; ++k) {
+    F(c->tab64[k]);
+    F(c->tab32[k]);
+  }
+  void* ps[] = {c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
+                c->WpT, c->Gpu, c->cs_in, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lst, c->part, c->V,
+                c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out};
+  for (void* p : ps) F(p);
+  for (int i = 0; i < 5; ++i) F(c->s64[i]);
+  if (c->hhost) hipHostFree(c->hhost);
+  delete c;
+}
+
+const char* mfpff_last_error(const mfpff_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+mfpff_status mfpff_level_info(mfpff_ctx* c, int level, mfpff_level_desc* out) {
+  return run(c, [&]() {
+    require_level(c, level);
+    require_ptr(out, "out");
+    const Level& L = c->lv[level];
+    out->N = L.g.N;
+    out->k = L.g.k;
+    out->n_nodes = L.nn;
+    out->n_dofs = L.n;
+    out->lambda_u = L.lam[0];
+    out->lambda_phi = L.lam[1];
+    out->lanczos_steps_u = L.lsteps[0];
+    out->lanczos_steps_phi = L.lsteps[1];
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_set_linearization(mfpff_ctx* c, const double* u, const double* phi, const double* phi_old,
+                                     const uint8_t* active, const double* phi_tilde) {
+  return run(c, [&]() {
+    require_ptr(u, "u");
+    require_ptr(phi, "phi");
+    require_ptr(phi_old, "phi_old");
+    require_ptr(active, "active");
+    c->linearized = false;
+    set_linearization(c, u, phi, phi_old, active, phi_tilde);
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_apply_jacobian(mfpff_ctx* c, int level, const void* x, void* y, int prec, int op) {
+  return run(c, [&]() {
+    require_state(c);
+    require_level(c, level);
+    require_ptr(x, "x");
+    require_ptr(y, "y");
+    if (x == y) throw StatusError{MFPFF_ERR_ARG, "x and y alias"};
+    int mode;
+    if (op == MFPFF_OP_G) mode = MODE_APPLY;
+    else if (op == MFPFF_OP_GT) mode = MODE_APPLY_T;
+    else if (op == MFPFF_OP_BLOCKDIAG) mode = MODE_BLOCK;
+    else throw StatusError{MFPFF_ERR_ARG, "unknown operator"};
+    if (prec == MFPFF_F64) {
+      apply_op<double>(c, level, mode, (const double*)x, (double*)y, nullptr);
+    } else if (prec == MFPFF_F32) {
+      if (!c->f32) throw StatusError{MFPFF_ERR_ARG, "FP32 level data exist only with an FP32 V-cycle"};
+      apply_op<float>(c, level, mode, (const float*)x, (float*)y, nullptr);
+    } else {
+      throw StatusError{MFPFF_ERR_ARG, "unknown precision"};
+    }
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_diagonal(mfpff_ctx* c, int level, double* diag) {
+  return run(c, [&]() {
+    require_state(c);
+    require_level(c, level);
+    require_ptr(diag, "diag");
+    k_copy<double>(diag, c->lv[level].diag, c->lv[level].n, c->s);
+    LAUNCHCHK();
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_smooth(mfpff_ctx* c, int level, const double* r, double* z) {
+  return run(c, [&]() {
+    require_state(c);
+    require_level(c, level);
+    if (level < 1) throw StatusError{MFPFF_ERR_ARG, "the coarsest level has no smoother"};
+    require_ptr(r, "r");
+    require_ptr(z, "z");
+    if (r == z) throw StatusError{MFPFF_ERR_ARG, "r and z alias"};
+    chebyshev<double>(c, level, r, z, c->s64[0], c->s64[1]);
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_transfer(mfpff_ctx* c, int level, int direction, const double* in, double* out) {
+  return run(c, [&]() {
+    require_level(c, level);
+    if (level < 1) throw StatusError{MFPFF_ERR_ARG, "transfer needs level >= 1"};
+    if (direction != 0 && direction != 1) throw StatusError{MFPFF_ERR_ARG, "direction must be 0 or 1"};
+    require_state(c);
+    require_ptr(in, "in");
+    require_ptr(out, "out");
+    transfer<double>(c, level, direction, in, out, false, c->t64a, c->t64b);
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_coarse_solve(mfpff_ctx* c, const double* r, double* x) {
+  return run(c, [&]() {
+    require_state(c);
+    require_ptr(r, "r");
+    require_ptr(x, "x");
+    coarse_solve64(c, r, x);
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_vcycle(mfpff_ctx* c, const double* r, double* z) {
+  return run(c, [&]() {
+    require_state(c);
+    require_ptr(r, "r");
+    require_ptr(z, "z");
+    precondition(c, r, z);
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_gmres_solve(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* info) {
+  return run(c, [&]() {
+    require_state(c);
+    require_ptr(b, "b");
+    require_ptr(x, "x");
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, c->s));
+    mfpff_solve_info loc{};
+    mfpff_status st = gmres(c, b, x, &loc);
+    HIPCHK(hipEventRecord(e1, c->s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    loc.ms_solve = ms;
+    if (info) *info = loc;
+    if (st == MFPFF_ERR_NOCONV) c->err = "GMRES reached max_iter";
+    return st;
+  });
+}
+
+mfpff_status mfpff_residual(mfpff_ctx* c, const double* u, const double* phi, const double* phi_tilde, double* R) {
+  return run(c, [&]() {
+    require_ptr(u, "u");
+    require_ptr(phi, "phi");
+    require_ptr(phi_tilde, "phi_tilde");
+    require_ptr(R, "R");
+    Level& F = c->lv[c->L];
+    k_fill<double>(R, 0.0, F.n, c->s);
+    CellArgs<double> a = cell_args<double>(c, F, F.lin, nullptr, R, 1.0);
+    a.u = u;
+    a.phi = phi;
+    a.phit = phi_tilde;
+    a.mask = nullptr;
+    HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_residual_param_vjp(mfpff_ctx* c, const double* u, const double* phi, const double* phi_tilde,
+                                      const double* v, double* dGc_host, double* deps_host) {
+  return run(c, [&]() {
+    require_ptr(phi, "phi");
+    require_ptr(v, "v");
+    require_ptr(dGc_host, "dGc_host");
+    require_ptr(deps_host, "deps_host");
+    Level& F = c->lv[c->L];
+    CellArgs<double> a = cell_args<double>(c, F, F.lin, v, nullptr, 1.0);
+    a.u = u;
+    a.phi = phi;
+    a.phit = phi_tilde;
+    a.mask = nullptr;
+    a.partials = c->pvjp_part;
+    HIPCHK(launch_cell<double>(MODE_PVJP, a, c->tab64[F.g.k], c->s));
+    const long long nb = cell_blocks(F.g, MODE_PVJP);
+    k_sum_pvjp(c->pvjp_out, c->pvjp_part, (int)nb, c->s);
+    LAUNCHCHK();
+    double out2[2];
+    HIPCHK(hipMemcpyAsync(out2, c->pvjp_out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    *dGc_host = out2[0];
+    *deps_host = out2[1];
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_active_set(mfpff_ctx* c, const double* R, const double* phi, const double* phi_old, uint8_t* active) {
+  return run(c, [&]() {
+    require_ptr(R, "R");
+    require_ptr(phi, "phi");
+    require_ptr(phi_old, "phi_old");
+    require_ptr(active, "active");
+    Level& F = c->lv[c->L];
+    k_active_set(active, R, phi, phi_old, c->ml, F.nn, c->dim, c->prob.as_c, c->s);
+    LAUNCHCHK();
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_newton_step(mfpff_ctx* c, double* u, double* phi, const double* phi_old, const double* phi_tilde,
+                               uint8_t* active, mfpff_solve_info* info) {
+  return run(c, [&]() {
+    require_ptr(u, "u");
+    require_ptr(phi, "phi");
+    require_ptr(phi_old, "phi_old");
+    require_ptr(active, "active");
+    const double* pt = phi_tilde ? phi_tilde : phi_old;
+    Level& F = c->lv[c->L];
+    const int d = c->dim;
+    hipEvent_t e0, e1, e2;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventCreate(&e2));
+    HIPCHK(hipEventRecord(e0, c->s));
+    // residual and active set
+    k_fill<double>(c->R, 0.0, F.n, c->s);
+    CellArgs<double> a = cell_args<double>(c, F, F.lin, nullptr, c->R, 1.0);
+    a.u = u;
+    a.phi = phi;
+    a.phit = pt;
+    a.mask = nullptr;
+    HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
+    k_active_set(active, c->R, phi, phi_old, c->ml, F.nn, d, c->prob.as_c, c->s);
+    LAUNCHCHK();
+    c->linearized = false;
+    set_linearization(c, u, phi, phi_old, active, pt);
+    HIPCHK(hipEventRecord(e1, c->s));
+    // b = -P R
+    k_copy<double>(c->b, c->R, F.n, c->s);
+    k_mask_vec(c->b, F.mask, F.nn, d, -1.0, c->s);
+    LAUNCHCHK();
+    mfpff_solve_info loc{};
+    mfpff_status st = gmres(c, c->b, c->dU, &loc);
+    k_axpy<double>(u, 1.0, c->dU, (long long)d * F.nn, c->s);
+    k_axpy<double>(phi, 1.0, c->dU + (size_t)d * F.nn, F.nn, c->s);
+    LAUNCHCHK();
+    HIPCHK(hipEventRecord(e2, c->s));
+    HIPCHK(hipEventSynchronize(e2));
+    float ms1 = 0, ms2 = 0;
+    HIPCHK(hipEventElapsedTime(&ms1, e0, e1));
+    HIPCHK(hipEventElapsedTime(&ms2, e1, e2));
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    hipEventDestroy(e2);
+    loc.ms_setup = ms1;
+    loc.ms_solve = ms2;
+    std::vector<uint8_t> mh(F.nn);
+    HIPCHK(hipMemcpy(mh.data(), F.mask, F.nn, hipMemcpyDeviceToHost));
+    int na = 0;
+    for (auto v : mh) na += (v & kMaskPhi) ? 1 : 0;
+    loc.n_active = na;
+    if (info) *info = loc;
+    if (st == MFPFF_ERR_NOCONV) c->err = "GMRES reached max_iter";
+    return st;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,152 @@
+// Internal declarations shared by the host solver core and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace mfpff {
+
+constexpr int kMaxDeg = 4;
+constexpr int kThreads = 256;
+
+// Geometry of one structured level: unit square/cube, N cells per direction,
+// Q_k with equispaced nodes, M = k*N + 1 nodes per direction.
+struct Geom {
+  int dim, k, N, M;
+  long long n_nodes;
+  double h;
+};
+
+struct MatParams {
+  double lam, mu, Gc, eps, kappa;
+};
+
+// 1D tables of one degree k on the unit interval (q = k+1 Gauss points):
+//   B[q][i]  = l_i(x_q)           Lagrange basis on equispaced nodes
+//   D[q][i]  = l_i'(x_q)
+//   C[q][r]  = derivative at x_q of the Lagrange polynomial through the Gauss
+//              points that is 1 at x_r (collocation derivative)
+//   w[q]     = Gauss weight
+template <typename T>
+struct Tables {
+  T B[kMaxDeg + 1][kMaxDeg + 1];
+  T D[kMaxDeg + 1][kMaxDeg + 1];
+  T C[kMaxDeg + 1][kMaxDeg + 1];
+  T w[kMaxDeg + 1];
+};
+
+void make_tables(int k, Tables<double>& t);
+
+// Node mask bits
+constexpr uint8_t kMaskPhi = 1;   // phi dof fixed (active set)
+constexpr uint8_t kMaskU = 2;     // all displacement dofs fixed (Dirichlet)
+
+enum CellMode : int {
+  MODE_APPLY = 0,     // full operator G
+  MODE_APPLY_T = 1,   // transpose G^T
+  MODE_BLOCK = 2,     // diag(G_uu, G_phiphi)
+  MODE_RESIDUAL = 3,  // residual (no x)
+  MODE_PVJP = 4,      // parameter cotangents (x = v)
+  MODE_ELEM = 5       // element columns of G scattered into a dense matrix
+};
+
+template <typename T>
+struct CellArgs {
+  Geom g;
+  MatParams m;
+  const T* x;          // input vector (APPLY*, BLOCK, PVJP), (d+1)*n_nodes
+  T* y;                // output accumulated with atomics
+  const T* u;          // displacement, d*n_nodes
+  const T* phi;        // n_nodes
+  const T* phit;       // n_nodes
+  const uint8_t* mask; // per node, may be null (nothing fixed)
+  T scale;             // contributions multiply by this (+1 apply, -1 residual form)
+  double* partials;    // PVJP: 2 doubles per block
+  double* dense;       // ELEM: row-major (d+1)*n_nodes square matrix
+  long long ld;        // ELEM: leading dimension
+};
+
+// ---- launchers (cell_kernel.hip)
+template <typename T>
+hipError_t launch_cell(int mode, const CellArgs<T>& a, const Tables<T>* tab_dev, hipStream_t s);
+template <typename T>
+hipError_t launch_diag(const CellArgs<T>& a, const Tables<T>* tab_dev, hipStream_t s);
+long long cell_blocks(const Geom& g, int mode);
+
+// ---- vector kernels (vector_ops.hip); n = element count
+template <typename T>
+void k_mask_init(T* y, const T* b, const T* x, const uint8_t* mask, long long nn, int dim, T scale, hipStream_t s);
+template <typename T>
+void k_copy(T* y, const T* x, long long n, hipStream_t s);
+template <typename T>
+void k_fill(T* y, T v, long long n, hipStream_t s);
+template <typename T>
+void k_axpy(T* y, T a, const T* x, long long n, hipStream_t s);
+template <typename T>
+void k_diag_finish(T* dinv, double* diag_out, const T* diag, const uint8_t* mask, long long nn, int dim, hipStream_t s);
+template <typename T>
+void k_cheb_init(T* z, T* d, const T* r, const T* dinv, long long nn, int dim, T inv_th_u, T inv_th_p, hipStream_t s);
+template <typename T>
+void k_cheb_step(T* z, T* d, const T* r, const T* t, const T* dinv, long long nn, int dim,
+                 T c1u, T c2u, T c1p, T c2p, hipStream_t s);
+void k_cast_d2f(float* y, const double* x, long long n, hipStream_t s);
+void k_cast_f2d(double* y, const float* x, long long n, hipStream_t s);
+void k_mask_vec(double* y, const uint8_t* mask, long long nn, int dim, double scale, hipStream_t s);
+void k_inject(double* lin_c, uint8_t* mask_c, const double* lin_f, const uint8_t* mask_f,
+              const Geom& gc, const Geom& gf, int dirichlet, hipStream_t s);
+void k_fine_fields(double* lin, uint8_t* mask, const double* u, const double* phi, const double* phit,
+                   const uint8_t* active, const Geom& g, int dirichlet, hipStream_t s);
+void k_lumped_mass(double* ml, const Geom& g, const double* w1d, hipStream_t s);
+void k_active_set(uint8_t* act, const double* R, const double* phi, const double* phi_old, const double* ml,
+                  long long nn, int dim, double c, hipStream_t s);
+void k_splitmix_start(double* v, const uint8_t* mask, long long nn, int dim, unsigned long long seed,
+                      int stream_u, int stream_p, hipStream_t s);
+
+// Reductions: partial sums per block, then a one-block finish.
+int dot_blocks(long long n);
+void k_multidot_partials(double* part, const double* V, long long ldv, int nvec, const double* w, long long n, hipStream_t s);
+void k_multidot_finish(double* out, const double* part, int nblocks, int nvec, hipStream_t s);
+void k_seg_dot_partials(double* part, const double* a, const double* b, long long nu, long long n, hipStream_t s);
+void k_maxpy_dev(double* w, const double* V, long long ldv, int nvec, const double* coef, double sign, long long n, hipStream_t s);
+void k_scale_dev(double* y, const double* x, const double* denom, long long n, hipStream_t s);
+void k_sum_pvjp(double* out2, const double* part, int nblocks, hipStream_t s);
+
+// CG-Lanczos device scalars
+struct LanczosState {
+  double rz[2], alpha[2], beta[2];
+  int active[2], count[2];
+  double alphas[2][64], betas[2][64];
+};
+void k_lanczos_alpha(LanczosState* st, const double* part, int nblocks, int step, hipStream_t s);
+void k_lanczos_update_r(double* r, double* z, double* part, const double* t, const double* dinv,
+                        const LanczosState* st, long long nu, long long n, hipStream_t s);
+void k_lanczos_beta(LanczosState* st, const double* part, int nblocks, int step, hipStream_t s);
+void k_lanczos_update_p(double* p, const double* z, const LanczosState* st, long long nu, long long n, hipStream_t s);
+void k_lanczos_init(LanczosState* st, const double* part, int nblocks, hipStream_t s);
+void k_lanczos_rz_partials(double* part, const double* r, const double* dinv, double* z, long long nu, long long n, hipStream_t s);
+
+// ---- transfers (transfer.hip): apply a 1D sparse matrix along one axis
+struct Sparse1D {
+  int n_out, n_in, width;   // rows (outputs), columns (inputs), entries per row (padded)
+  const int* col;           // n_out*width, -1 = padding
+  const double* val;        // n_out*width
+  const float* valf;
+};
+template <typename T>
+void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, const long long* dims_in,
+                  int ncomp, hipStream_t s);
+template <typename T>
+void k_mask_comp(T* y, const uint8_t* mask, long long nn, int dim, hipStream_t s);
+template <typename T>
+void k_add_masked(T* y, const T* x, const uint8_t* mask, long long nn, int dim, hipStream_t s);
+
+// ---- dense coarse solver (dense.hip), row-major FP64
+void k_dense_set_fixed_diag(double* A, long long ld, const uint8_t* mask, long long nn, int dim, hipStream_t s);
+void k_extract_block(double* dst, long long ldd, const double* src, long long lds, long long r0, long long c0,
+                     long long nr, long long nc, hipStream_t s);
+hipError_t cholesky_lower(double* A, int n, int* info_dev, double* scratch, hipStream_t s);  // info_dev zeroed by the caller
+hipError_t tri_inverse_lower(double* W, const double* L, int n, hipStream_t s);
+void k_transpose(double* At, const double* A, int n, hipStream_t s);
+void k_gemv(double* y, const double* A, long long lda, const double* x, int rows, int cols, double alpha,
+            const double* yin, hipStream_t s);
+
+}  // namespace mfpff

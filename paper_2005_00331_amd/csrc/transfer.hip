@@ -1,0 +1,106 @@
+// Level transfers (gfx950).  The prolongation between nested structured
+// levels is the Kronecker product over axes of one 1D interpolation matrix
+// (coarse basis functions evaluated at fine nodes), applied per component;
+// restriction is its transpose.  Both are applied axis by axis: each pass
+// maps one axis through a padded row-sparse 1D matrix (thread per output
+// entry, gather, no atomics), so a 3D transfer reads each input a few times
+// instead of (2k+1)^3 times.
+#include "internal.h"
+
+namespace mfpff {
+
+struct Dims3 {
+  long long n[3];
+};
+
+template <typename T>
+__global__ void axis_apply_kernel(T* out, const T* in, const int* col, const double* val, const float* valf, int width,
+                                  int axis, int dim, Dims3 din, int nout_axis, int ncomp) {
+  long long nin[3] = {din.n[0], din.n[1], din.n[2]};
+  long long no[3] = {nin[0], nin[1], nin[2]};
+  no[axis] = nout_axis;
+  long long per_in = 1, per_out = 1;
+  for (int a = 0; a < dim; ++a) {
+    per_in *= nin[a];
+    per_out *= no[a];
+  }
+  const long long total = per_out * ncomp;
+  long long sin[3] = {1, nin[0], nin[0] * nin[1]};
+  for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long long)gridDim.x * blockDim.x) {
+    const long long comp = idx / per_out;
+    long long rem = idx - comp * per_out;
+    long long o[3] = {0, 0, 0};
+    for (int a = 0; a < dim; ++a) {
+      o[a] = rem % no[a];
+      rem /= no[a];
+    }
+    long long base = comp * per_in;
+    for (int a = 0; a < dim; ++a)
+      if (a != axis) base += o[a] * sin[a];
+    const int row = (int)o[axis];
+    T acc = 0;
+    for (int j = 0; j < width; ++j) {
+      const int ci = col[row * width + j];
+      if (ci < 0) break;
+      const T w = sizeof(T) == 8 ? (T)val[row * width + j] : (T)valf[row * width + j];
+      acc += w * in[base + (long long)ci * sin[axis]];
+    }
+    out[idx] = acc;
+  }
+}
+
+template <typename T>
+void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, const long long* dims_in, int ncomp, hipStream_t s) {
+  Dims3 d{{dims_in[0], dims_in[1], dim == 3 ? dims_in[2] : 1}};
+  long long total = ncomp;
+  for (int a = 0; a < dim; ++a) total *= (a == axis ? A.n_out : d.n[a]);
+  long long nb = (total + kThreads - 1) / kThreads;
+  if (nb > 65536) nb = 65536;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(axis_apply_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, out, in, A.col, A.val, A.valf, A.width,
+                     axis, dim, d, A.n_out, ncomp);
+}
+
+// zero the fixed dofs of a level vector
+template <typename T>
+__global__ void mask_comp_kernel(T* y, const uint8_t* mask, long long nn, int dim) {
+  const long long n = (long long)(dim + 1) * nn;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const long long comp = i / nn;
+    const uint8_t m = mask[i - comp * nn];
+    const bool f = comp < dim ? (m & kMaskU) : (m & kMaskPhi);
+    if (f) y[i] = T(0);
+  }
+}
+template <typename T>
+void k_mask_comp(T* y, const uint8_t* mask, long long nn, int dim, hipStream_t s) {
+  long long nb = ((dim + 1) * nn + kThreads - 1) / kThreads;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(mask_comp_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, y, mask, nn, dim);
+}
+// y += P x on free dofs (x already interpolated)
+template <typename T>
+__global__ void add_masked_kernel(T* y, const T* x, const uint8_t* mask, long long nn, int dim) {
+  const long long n = (long long)(dim + 1) * nn;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
+    const long long comp = i / nn;
+    const uint8_t m = mask[i - comp * nn];
+    const bool f = comp < dim ? (m & kMaskU) : (m & kMaskPhi);
+    if (!f) y[i] += x[i];
+  }
+}
+template <typename T>
+void k_add_masked(T* y, const T* x, const uint8_t* mask, long long nn, int dim, hipStream_t s) {
+  long long nb = ((dim + 1) * nn + kThreads - 1) / kThreads;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(add_masked_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, y, x, mask, nn, dim);
+}
+
+template void k_axis_apply<double>(double*, const double*, const Sparse1D&, int, int, const long long*, int, hipStream_t);
+template void k_axis_apply<float>(float*, const float*, const Sparse1D&, int, int, const long long*, int, hipStream_t);
+template void k_mask_comp<double>(double*, const uint8_t*, long long, int, hipStream_t);
+template void k_mask_comp<float>(float*, const uint8_t*, long long, int, hipStream_t);
+template void k_add_masked<double>(double*, const double*, const uint8_t*, long long, int, hipStream_t);
+template void k_add_masked<float>(float*, const float*, const uint8_t*, long long, int, hipStream_t);
+
+}  // namespace mfpff

@@ -1,0 +1,487 @@
+// Vector, reduction and small bookkeeping kernels (gfx950).
+// Element-wise kernels are grid-stride loops over contiguous vectors; reductions
+// write one partial per workgroup and a single workgroup finishes them in a
+// fixed order, so repeated runs are bitwise identical.
+#include "internal.h"
+
+namespace mfpff {
+
+static inline unsigned grid_for(long long n, int per = kThreads) {
+  long long b = (n + per - 1) / per;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+#define GSTRIDE(i, n) for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < (n); i += (long long)gridDim.x * blockDim.x)
+
+__device__ __forceinline__ bool fixed_at(const uint8_t* mask, long long i, long long nn, int dim) {
+  if (!mask) return false;
+  const long long comp = i / nn;
+  const uint8_t m = mask[i - comp * nn];
+  return comp < dim ? (m & kMaskU) : (m & kMaskPhi);
+}
+
+// y = b + scale * (I - P) x   (b may be null)
+template <typename T>
+__global__ void mask_init_kernel(T* y, const T* b, const T* x, const uint8_t* mask, long long nn, int dim, T scale) {
+  const long long n = (long long)(dim + 1) * nn;
+  GSTRIDE(i, n) {
+    T v = b ? b[i] : T(0);
+    if (fixed_at(mask, i, nn, dim)) v += scale * x[i];
+    y[i] = v;
+  }
+}
+template <typename T>
+void k_mask_init(T* y, const T* b, const T* x, const uint8_t* mask, long long nn, int dim, T scale, hipStream_t s) {
+  hipLaunchKernelGGL(mask_init_kernel<T>, dim3(grid_for((dim + 1) * nn)), dim3(kThreads), 0, s, y, b, x, mask, nn, dim, scale);
+}
+
+template <typename T>
+__global__ void copy_kernel(T* y, const T* x, long long n) { GSTRIDE(i, n) y[i] = x[i]; }
+template <typename T>
+void k_copy(T* y, const T* x, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(copy_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, y, x, n);
+}
+template <typename T>
+__global__ void fill_kernel(T* y, T v, long long n) { GSTRIDE(i, n) y[i] = v; }
+template <typename T>
+void k_fill(T* y, T v, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(fill_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, y, v, n);
+}
+template <typename T>
+__global__ void axpy_kernel(T* y, T a, const T* x, long long n) { GSTRIDE(i, n) y[i] += a * x[i]; }
+template <typename T>
+void k_axpy(T* y, T a, const T* x, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(axpy_kernel<T>, dim3(grid_for(n)), dim3(kThreads), 0, s, y, a, x, n);
+}
+
+// dinv = 1/diag on free dofs, 1 on fixed dofs; optional FP64 copy of the diagonal itself
+template <typename T>
+__global__ void diag_finish_kernel(T* dinv, double* dout, const T* diag, const uint8_t* mask, long long nn, int dim) {
+  const long long n = (long long)(dim + 1) * nn;
+  GSTRIDE(i, n) {
+    const bool f = fixed_at(mask, i, nn, dim);
+    const T dv = f ? T(1) : diag[i];
+    if (dinv) dinv[i] = T(1) / dv;
+    if (dout) dout[i] = (double)dv;
+  }
+}
+template <typename T>
+void k_diag_finish(T* dinv, double* dout, const T* diag, const uint8_t* mask, long long nn, int dim, hipStream_t s) {
+  hipLaunchKernelGGL(diag_finish_kernel<T>, dim3(grid_for((dim + 1) * nn)), dim3(kThreads), 0, s, dinv, dout, diag, mask, nn, dim);
+}
+
+// Chebyshev start: z = D^-1 r / theta_b, d = z
+template <typename T>
+__global__ void cheb_init_kernel(T* z, T* d, const T* r, const T* dinv, long long nn, int dim, T itu, T itp) {
+  const long long n = (long long)(dim + 1) * nn;
+  const long long nu = (long long)dim * nn;
+  GSTRIDE(i, n) {
+    const T v = dinv[i] * r[i] * (i < nu ? itu : itp);
+    z[i] = v;
+    d[i] = v;
+  }
+}
+template <typename T>
+void k_cheb_init(T* z, T* d, const T* r, const T* dinv, long long nn, int dim, T itu, T itp, hipStream_t s) {
+  hipLaunchKernelGGL(cheb_init_kernel<T>, dim3(grid_for((dim + 1) * nn)), dim3(kThreads), 0, s, z, d, r, dinv, nn, dim, itu, itp);
+}
+// Chebyshev step: d = c1 d + c2 D^-1 (r - t); z += d
+template <typename T>
+__global__ void cheb_step_kernel(T* z, T* d, const T* r, const T* t, const T* dinv, long long nn, int dim,
+                                 T c1u, T c2u, T c1p, T c2p) {
+  const long long n = (long long)(dim + 1) * nn;
+  const long long nu = (long long)dim * nn;
+  GSTRIDE(i, n) {
+    const bool isu = i < nu;
+    const T dn = (isu ? c1u : c1p) * d[i] + (isu ? c2u : c2p) * dinv[i] * (r[i] - t[i]);
+    d[i] = dn;
+    z[i] += dn;
+  }
+}
+template <typename T>
+void k_cheb_step(T* z, T* d, const T* r, const T* t, const T* dinv, long long nn, int dim, T c1u, T c2u, T c1p, T c2p,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(cheb_step_kernel<T>, dim3(grid_for((dim + 1) * nn)), dim3(kThreads), 0, s, z, d, r, t, dinv, nn, dim,
+                     c1u, c2u, c1p, c2p);
+}
+
+__global__ void d2f_kernel(float* y, const double* x, long long n) { GSTRIDE(i, n) y[i] = (float)x[i]; }
+__global__ void f2d_kernel(double* y, const float* x, long long n) { GSTRIDE(i, n) y[i] = (double)x[i]; }
+void k_cast_d2f(float* y, const double* x, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(d2f_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, y, x, n);
+}
+void k_cast_f2d(double* y, const float* x, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(f2d_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, y, x, n);
+}
+
+// y = scale * P y (zero fixed dofs, scale the rest)
+__global__ void mask_vec_kernel(double* y, const uint8_t* mask, long long nn, int dim, double scale) {
+  const long long n = (long long)(dim + 1) * nn;
+  GSTRIDE(i, n) y[i] = fixed_at(mask, i, nn, dim) ? 0.0 : scale * y[i];
+}
+void k_mask_vec(double* y, const uint8_t* mask, long long nn, int dim, double scale, hipStream_t s) {
+  hipLaunchKernelGGL(mask_vec_kernel, dim3(grid_for((dim + 1) * nn)), dim3(kThreads), 0, s, y, mask, nn, dim, scale);
+}
+
+__device__ __forceinline__ uint8_t dirichlet_bit(long long node, const Geom& g, int dirichlet) {
+  if (!dirichlet) return 0;
+  long long stride = 1;
+  for (int a = 0; a < g.dim - 1; ++a) stride *= g.M;
+  const long long i = (node / stride) % g.M;
+  return (i == 0 || i == g.M - 1) ? kMaskU : (uint8_t)0;
+}
+
+// Finest level: pack u, phi, phi~ into the level field array and build the mask.
+__global__ void fine_fields_kernel(double* lin, uint8_t* mask, const double* u, const double* phi, const double* phit,
+                                   const uint8_t* active, Geom g, int dirichlet) {
+  const long long nn = g.n_nodes;
+  GSTRIDE(i, nn) {
+    for (int c = 0; c < g.dim; ++c) lin[c * nn + i] = u[c * nn + i];
+    lin[g.dim * nn + i] = phi[i];
+    lin[(g.dim + 1) * nn + i] = phit[i];
+    mask[i] = (uint8_t)((active && active[i]) ? kMaskPhi : 0) | dirichlet_bit(i, g, dirichlet);
+  }
+}
+void k_fine_fields(double* lin, uint8_t* mask, const double* u, const double* phi, const double* phit, const uint8_t* active,
+                   const Geom& g, int dirichlet, hipStream_t s) {
+  hipLaunchKernelGGL(fine_fields_kernel, dim3(grid_for(g.n_nodes)), dim3(kThreads), 0, s, lin, mask, u, phi, phit, active, g,
+                     dirichlet);
+}
+
+// Coarse level: inject fields and the active bit from the coincident fine node.
+__global__ void inject_kernel(double* lin_c, uint8_t* mask_c, const double* lin_f, const uint8_t* mask_f, Geom gc, Geom gf,
+                              int dirichlet) {
+  const long long nnc = gc.n_nodes, nnf = gf.n_nodes;
+  const long long ratio = ((long long)gf.k * gf.N) / ((long long)gc.k * gc.N);
+  GSTRIDE(i, nnc) {
+    long long rem = i, fi = 0, fs = 1;
+    for (int a = 0; a < gc.dim; ++a) {
+      const long long ia = rem % gc.M;
+      rem /= gc.M;
+      fi += ia * ratio * fs;
+      fs *= gf.M;
+    }
+    for (int c = 0; c < gc.dim + 2; ++c) lin_c[c * nnc + i] = lin_f[c * nnf + fi];
+    mask_c[i] = (uint8_t)(mask_f[fi] & kMaskPhi) | dirichlet_bit(i, gc, dirichlet);
+  }
+}
+void k_inject(double* lin_c, uint8_t* mask_c, const double* lin_f, const uint8_t* mask_f, const Geom& gc, const Geom& gf,
+              int dirichlet, hipStream_t s) {
+  hipLaunchKernelGGL(inject_kernel, dim3(grid_for(gc.n_nodes)), dim3(kThreads), 0, s, lin_c, mask_c, lin_f, mask_f, gc, gf,
+                     dirichlet);
+}
+
+// Row-sum-lumped phi mass: product over axes of h * (sum of the 1D basis
+// integrals of the cells that share the node).
+__global__ void lumped_mass_kernel(double* ml, Geom g, const double* w1d) {
+  GSTRIDE(i, g.n_nodes) {
+    long long rem = i;
+    double v = 1.0;
+    for (int a = 0; a < g.dim; ++a) {
+      const long long ia = rem % g.M;
+      rem /= g.M;
+      const int loc = (int)(ia % g.k);
+      double wa;
+      if (loc == 0) wa = (ia > 0 ? w1d[g.k] : 0.0) + (ia < g.M - 1 ? w1d[0] : 0.0);
+      else wa = w1d[loc];
+      v *= g.h * wa;
+    }
+    ml[i] = v;
+  }
+}
+void k_lumped_mass(double* ml, const Geom& g, const double* w1d, hipStream_t s) {
+  hipLaunchKernelGGL(lumped_mass_kernel, dim3(grid_for(g.n_nodes)), dim3(kThreads), 0, s, ml, g, w1d);
+}
+
+// Algorithm 1 active set: -(M_L^-1 R_phi)_i + c (phi - phi_old)_i > 0
+__global__ void active_set_kernel(uint8_t* act, const double* R, const double* phi, const double* phi_old, const double* ml,
+                                  long long nn, int dim, double c) {
+  GSTRIDE(i, nn) {
+    const double ind = -R[(long long)dim * nn + i] / ml[i] + c * (phi[i] - phi_old[i]);
+    act[i] = ind > 0.0 ? 1 : 0;
+  }
+}
+void k_active_set(uint8_t* act, const double* R, const double* phi, const double* phi_old, const double* ml, long long nn,
+                  int dim, double c, hipStream_t s) {
+  hipLaunchKernelGGL(active_set_kernel, dim3(grid_for(nn)), dim3(kThreads), 0, s, act, R, phi, phi_old, ml, nn, dim, c);
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): output n of stream st with seed s is
+// mix(s + (n + 1 + st * 2^40) * 0x9E3779B97F4A7C15), mapped to [-1, 1).
+__device__ __forceinline__ double splitmix_pm1(unsigned long long seed, unsigned long long st, unsigned long long n) {
+  unsigned long long z = seed + (n + 1ULL + (st << 40)) * 0x9E3779B97F4A7C15ULL;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ULL;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBULL;
+  z = z ^ (z >> 31);
+  return (double)(z >> 11) * 0x1.0p-52 - 1.0;
+}
+__global__ void splitmix_start_kernel(double* v, const uint8_t* mask, long long nn, int dim, unsigned long long seed, int su,
+                                      int sp) {
+  const long long n = (long long)(dim + 1) * nn;
+  const long long nu = (long long)dim * nn;
+  GSTRIDE(i, n) {
+    const double r = i < nu ? splitmix_pm1(seed, (unsigned long long)su, (unsigned long long)i)
+                            : splitmix_pm1(seed, (unsigned long long)sp, (unsigned long long)(i - nu));
+    v[i] = fixed_at(mask, i, nn, dim) ? 0.0 : r;
+  }
+}
+void k_splitmix_start(double* v, const uint8_t* mask, long long nn, int dim, unsigned long long seed, int su, int sp,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(splitmix_start_kernel, dim3(grid_for((dim + 1) * nn)), dim3(kThreads), 0, s, v, mask, nn, dim, seed, su,
+                     sp);
+}
+
+// ---------------------------------------------------------------- reductions
+constexpr int kRedBlocks = 512;
+int dot_blocks(long long n) {
+  long long b = (n + kThreads - 1) / kThreads;
+  return (int)(b < kRedBlocks ? (b < 1 ? 1 : b) : kRedBlocks);
+}
+
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  // wave64 shuffle reduction then across the 4 waves
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+  __syncthreads();
+  return r;
+}
+
+// part[b * nvec + j] = sum over this block's range of V_j . w
+__global__ void multidot_partials_kernel(double* part, const double* V, long long ldv, int nvec, const double* w, long long n) {
+  __shared__ double sh[8];
+  const int nb = gridDim.x;
+  const long long chunk = (n + nb - 1) / nb;
+  const long long lo = (long long)blockIdx.x * chunk;
+  const long long hi = lo + chunk < n ? lo + chunk : n;
+  for (int j = 0; j < nvec; ++j) {
+    double acc = 0;
+    const double* v = V + (long long)j * ldv;
+    for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) acc += v[i] * w[i];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[(long long)blockIdx.x * nvec + j] = s;
+  }
+}
+void k_multidot_partials(double* part, const double* V, long long ldv, int nvec, const double* w, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(multidot_partials_kernel, dim3(dot_blocks(n)), dim3(kThreads), 0, s, part, V, ldv, nvec, w, n);
+}
+__global__ void multidot_finish_kernel(double* out, const double* part, int nblocks, int nvec) {
+  __shared__ double sh[8];
+  for (int j = 0; j < nvec; ++j) {
+    double acc = 0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) acc += part[(long long)b * nvec + j];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[j] = s;
+  }
+}
+void k_multidot_finish(double* out, const double* part, int nblocks, int nvec, hipStream_t s) {
+  hipLaunchKernelGGL(multidot_finish_kernel, dim3(1), dim3(kThreads), 0, s, out, part, nblocks, nvec);
+}
+
+// two segment sums of a.b: [0, nu) and [nu, n)
+__global__ void seg_dot_partials_kernel(double* part, const double* a, const double* b, long long nu, long long n) {
+  __shared__ double sh[8];
+  const int nb = gridDim.x;
+  for (int sgm = 0; sgm < 2; ++sgm) {
+    const long long s0 = sgm == 0 ? 0 : nu, s1 = sgm == 0 ? nu : n;
+    const long long len = s1 - s0;
+    const long long chunk = (len + nb - 1) / nb;
+    const long long lo = s0 + (long long)blockIdx.x * chunk;
+    const long long hi = lo + chunk < s1 ? lo + chunk : s1;
+    double acc = 0;
+    for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) acc += a[i] * b[i];
+    const double sum = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[2 * blockIdx.x + sgm] = sum;
+  }
+}
+void k_seg_dot_partials(double* part, const double* a, const double* b, long long nu, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(seg_dot_partials_kernel, dim3(dot_blocks(n)), dim3(kThreads), 0, s, part, a, b, nu, n);
+}
+
+// w += sign * sum_j coef[j] V_j  (coefficients read from device memory)
+__global__ void maxpy_dev_kernel(double* w, const double* V, long long ldv, int nvec, const double* coef, double sign, long long n) {
+  GSTRIDE(i, n) {
+    double acc = 0;
+    for (int j = 0; j < nvec; ++j) acc += coef[j] * V[(long long)j * ldv + i];
+    w[i] += sign * acc;
+  }
+}
+void k_maxpy_dev(double* w, const double* V, long long ldv, int nvec, const double* coef, double sign, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(maxpy_dev_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, w, V, ldv, nvec, coef, sign, n);
+}
+// y = x / denom[0]
+__global__ void scale_dev_kernel(double* y, const double* x, const double* denom, long long n) {
+  const double d = denom[0];
+  GSTRIDE(i, n) y[i] = x[i] / d;
+}
+void k_scale_dev(double* y, const double* x, const double* denom, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(scale_dev_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, y, x, denom, n);
+}
+__global__ void sum_pvjp_kernel(double* out, const double* part, int nb) {
+  __shared__ double sh[8];
+  for (int j = 0; j < 2; ++j) {
+    double acc = 0;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[2 * b + j];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) out[j] = s;
+  }
+}
+void k_sum_pvjp(double* out2, const double* part, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(sum_pvjp_kernel, dim3(1), dim3(kThreads), 0, s, out2, part, nb);
+}
+
+// ---------------------------------------------------------------- CG-Lanczos
+// Block-wise Jacobi-preconditioned CG (u block and phi block at once), all
+// scalars kept on the device.  Breakdown rules: stop a block when r.z == 0
+// or p.Ap <= 0.
+__global__ void lanczos_init_kernel(LanczosState* st, const double* part, int nb) {
+  __shared__ double sh[8];
+  for (int b = 0; b < 2; ++b) {
+    double acc = 0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[2 * i + b];
+    const double s = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+      st->rz[b] = s;
+      st->active[b] = 1;
+      st->count[b] = 0;
+      st->alpha[b] = 0;
+      st->beta[b] = 0;
+    }
+  }
+}
+void k_lanczos_init(LanczosState* st, const double* part, int nb, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_init_kernel, dim3(1), dim3(kThreads), 0, s, st, part, nb);
+}
+__global__ void lanczos_alpha_kernel(LanczosState* st, const double* part, int nb, int step) {
+  __shared__ double sh[8];
+  for (int b = 0; b < 2; ++b) {
+    double acc = 0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[2 * i + b];
+    const double pAp = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+      if (st->active[b]) {
+        if (st->rz[b] == 0.0 || !(pAp > 0.0)) {
+          st->active[b] = 0;
+          st->alpha[b] = 0;
+        } else {
+          const double al = st->rz[b] / pAp;
+          st->alpha[b] = al;
+          st->alphas[b][step] = al;
+          st->count[b] = step + 1;
+        }
+      } else {
+        st->alpha[b] = 0;
+      }
+    }
+  }
+}
+void k_lanczos_alpha(LanczosState* st, const double* part, int nb, int step, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_alpha_kernel, dim3(1), dim3(kThreads), 0, s, st, part, nb, step);
+}
+// r -= alpha_b t ; z = dinv r ; partials of r.z per block
+__global__ void lanczos_update_r_kernel(double* r, double* z, double* part, const double* t, const double* dinv,
+                                        const LanczosState* st, long long nu, long long n) {
+  __shared__ double sh[8];
+  const double au = st->active[0] ? st->alpha[0] : 0.0;
+  const double ap = st->active[1] ? st->alpha[1] : 0.0;
+  const int nb = gridDim.x;
+  for (int sgm = 0; sgm < 2; ++sgm) {
+    const long long s0 = sgm == 0 ? 0 : nu, s1 = sgm == 0 ? nu : n;
+    const long long len = s1 - s0;
+    const long long chunk = (len + nb - 1) / nb;
+    const long long lo = s0 + (long long)blockIdx.x * chunk;
+    const long long hi = lo + chunk < s1 ? lo + chunk : s1;
+    const double a = sgm == 0 ? au : ap;
+    double acc = 0;
+    for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const double rv = r[i] - a * t[i];
+      const double zv = dinv[i] * rv;
+      r[i] = rv;
+      z[i] = zv;
+      acc += rv * zv;
+    }
+    const double sum = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[2 * blockIdx.x + sgm] = sum;
+  }
+}
+void k_lanczos_update_r(double* r, double* z, double* part, const double* t, const double* dinv, const LanczosState* st,
+                        long long nu, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_update_r_kernel, dim3(dot_blocks(n)), dim3(kThreads), 0, s, r, z, part, t, dinv, st, nu, n);
+}
+// z = dinv r and partials of r.z (start of the iteration)
+__global__ void lanczos_rz_kernel(double* part, const double* r, const double* dinv, double* z, long long nu, long long n) {
+  __shared__ double sh[8];
+  const int nb = gridDim.x;
+  for (int sgm = 0; sgm < 2; ++sgm) {
+    const long long s0 = sgm == 0 ? 0 : nu, s1 = sgm == 0 ? nu : n;
+    const long long len = s1 - s0;
+    const long long chunk = (len + nb - 1) / nb;
+    const long long lo = s0 + (long long)blockIdx.x * chunk;
+    const long long hi = lo + chunk < s1 ? lo + chunk : s1;
+    double acc = 0;
+    for (long long i = lo + threadIdx.x; i < hi; i += blockDim.x) {
+      const double zv = dinv[i] * r[i];
+      z[i] = zv;
+      acc += r[i] * zv;
+    }
+    const double sum = block_sum(acc, sh);
+    if (threadIdx.x == 0) part[2 * blockIdx.x + sgm] = sum;
+  }
+}
+void k_lanczos_rz_partials(double* part, const double* r, const double* dinv, double* z, long long nu, long long n,
+                           hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_rz_kernel, dim3(dot_blocks(n)), dim3(kThreads), 0, s, part, r, dinv, z, nu, n);
+}
+__global__ void lanczos_beta_kernel(LanczosState* st, const double* part, int nb, int step) {
+  __shared__ double sh[8];
+  for (int b = 0; b < 2; ++b) {
+    double acc = 0;
+    for (int i = threadIdx.x; i < nb; i += blockDim.x) acc += part[2 * i + b];
+    const double rzn = block_sum(acc, sh);
+    if (threadIdx.x == 0) {
+      if (st->active[b]) {
+        const double be = rzn / st->rz[b];
+        st->beta[b] = be;
+        st->betas[b][step] = be;
+        st->rz[b] = rzn;
+      } else {
+        st->beta[b] = 0;
+      }
+    }
+  }
+}
+void k_lanczos_beta(LanczosState* st, const double* part, int nb, int step, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_beta_kernel, dim3(1), dim3(kThreads), 0, s, st, part, nb, step);
+}
+// p = z + beta_b p (active blocks only)
+__global__ void lanczos_update_p_kernel(double* p, const double* z, const LanczosState* st, long long nu, long long n) {
+  const int au = st->active[0], ap = st->active[1];
+  const double bu = st->beta[0], bp = st->beta[1];
+  GSTRIDE(i, n) {
+    const bool isu = i < nu;
+    if (isu ? au : ap) p[i] = z[i] + (isu ? bu : bp) * p[i];
+  }
+}
+void k_lanczos_update_p(double* p, const double* z, const LanczosState* st, long long nu, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(lanczos_update_p_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, p, z, st, nu, n);
+}
+
+#define INST(T)                                                                                                    \
+  template void k_mask_init<T>(T*, const T*, const T*, const uint8_t*, long long, int, T, hipStream_t);            \
+  template void k_copy<T>(T*, const T*, long long, hipStream_t);                                                   \
+  template void k_fill<T>(T*, T, long long, hipStream_t);                                                          \
+  template void k_axpy<T>(T*, T, const T*, long long, hipStream_t);                                                \
+  template void k_diag_finish<T>(T*, double*, const T*, const uint8_t*, long long, int, hipStream_t);              \
+  template void k_cheb_init<T>(T*, T*, const T*, const T*, long long, int, T, T, hipStream_t);                     \
+  template void k_cheb_step<T>(T*, T*, const T*, const T*, const T*, long long, int, T, T, T, T, hipStream_t);
+INST(double)
+INST(float)
+#undef INST
+
+}  // namespace mfpff

@@ -1,0 +1,78 @@
+"""Shared helpers of the GPU tests: seeded inputs, oracle hierarchies, device copies."""
+import functools
+import sys
+
+import numpy as np
+
+from oracle import multigrid as mg
+from oracle import operator as op
+from oracle.fe import Mesh
+from synth import CONFIGS, make_inputs
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_err(got, ref):
+    got, ref = np.asarray(got, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    den = np.abs(ref).max()
+    return float(np.abs(got - ref).max() / (den if den > 0 else 1.0))
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a).ravel())
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    return t.detach().cpu().numpy()
+
+
+# parity cases: (name, base config, levels coarse->fine, overrides)
+CASES = {
+    "2d_q1": ("C1", [(6, 1), (12, 1)], {}),
+    "2d_q2": ("C2", [(5, 1), (5, 2), (10, 2)], {}),
+    "2d_q3": ("C2", [(3, 1), (3, 3), (6, 3)], {}),
+    "2d_q4": ("C4", [(3, 2), (3, 4), (6, 4)], dict(dim=2)),
+    "3d_q1": ("C3", [(3, 1), (6, 1)], dict(vcycle_prec="f64")),
+    "3d_q2": ("C3", [(2, 1), (2, 2), (4, 2)], dict(vcycle_prec="f64")),
+    "3d_q3": ("C4", [(3, 1), (3, 3)], {}),
+    "3d_q4": ("C4", [(2, 2), (2, 4), (4, 4)], {}),
+    "3d_q2_f32": ("C3", [(2, 2), (4, 2)], dict(vcycle_prec="f32")),
+}
+
+
+def case_config(name):
+    base, levels, ov = CASES[name]
+    N, k = levels[-1]
+    cfg = CONFIGS[base].with_(N=N, k=k, n_h_levels=1, p_coarse=(), **ov)
+    return cfg, levels
+
+
+@functools.lru_cache(maxsize=4)
+def oracle_case(name):
+    cfg, levels = case_config(name)
+    inp = make_inputs(cfg, ("rhs",))
+    H = mg.Hierarchy(cfg, levels, inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
+    return cfg, levels, inp, H
+
+
+def gpu_context(cfg, levels, inp, **kw):
+    from paper_2005_00331_amd import Context, problem_from
+    ctx = Context(problem_from(cfg, levels, **kw))
+    ctx.set_linearization(dev(inp["u"]), dev(inp["phi"]), dev(inp["phi_old"]), dev(inp["active"]),
+                          dev(inp["phi_tilde"]))
+    return ctx
+
+
+def oracle_material(cfg):
+    return op.material_of(cfg)
+
+
+def mesh_of(cfg):
+    return Mesh(cfg.dim, cfg.N, cfg.k)

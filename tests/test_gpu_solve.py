@@ -1,0 +1,95 @@
+"""GPU parity of the residual, its parameter cotangents, FGMRES and the
+Newton step against the oracle (small sizes, every step element by element
+where the result is unique)."""
+import numpy as np
+import pytest
+
+from helpers import dev, host, rel_err, say
+from oracle import krylov, multigrid as mg, newton
+from oracle import operator as op
+from oracle.fe import Mesh
+from synth import CONFIGS, level_list, make_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _ctx(cfg, levels, **kw):
+    from paper_2005_00331_amd import Context, problem_from
+    return Context(problem_from(cfg, levels, **kw))
+
+
+@pytest.mark.parametrize("name,kw", [("C1", {}), ("C2", dict(N=10)), ("C5", dict(N=4)), ("C4", dict(N=3, k=3))])
+def test_residual_and_param_vjp(name, kw):
+    cfg = CONFIGS[name].with_(n_h_levels=1, p_coarse=(), **kw)
+    inp = make_inputs(cfg, ("cotangent",))
+    mesh = Mesh(cfg.dim, cfg.N, cfg.k)
+    m = op.material_of(cfg)
+    say(name, kw, "residual")
+    ctx = _ctx(cfg, [(cfg.N, cfg.k)])
+    R = host(ctx.residual(dev(inp["u"]), dev(inp["phi"]), dev(inp["phi_tilde"])))
+    Rref = op.residual(mesh, m, inp["u"], inp["phi"], inp["phi_tilde"])
+    assert rel_err(R, Rref) <= 1e-12
+    dGc, deps = ctx.residual_param_vjp(dev(inp["u"]), dev(inp["phi"]), dev(inp["phi_tilde"]), dev(inp["cotangent"]))
+    rGc, reps = op.param_vjp(mesh, m, inp["u"], inp["phi"], inp["phi_tilde"], inp["cotangent"])
+    assert abs(dGc - rGc) <= 1e-12 * abs(rGc) and abs(deps - reps) <= 1e-12 * abs(reps)
+
+
+def test_active_set_matches_oracle_rule():
+    cfg = CONFIGS["C2"].with_(N=12, n_h_levels=1)
+    inp = make_inputs(cfg)
+    mesh = Mesh(cfg.dim, cfg.N, cfg.k)
+    R = op.residual(mesh, op.material_of(cfg), inp["u"], inp["phi"], inp["phi_tilde"])
+    rng = np.random.default_rng(3)
+    phi_old = inp["phi"] + 1e-3 * rng.standard_normal(mesh.n_nodes)
+    ref, ind = newton.active_set(mesh, R, inp["phi"], phi_old, cfg.as_c)
+    ctx = _ctx(cfg, [(cfg.N, cfg.k)])
+    say("active set")
+    got = host(ctx.active_set(dev(R), dev(inp["phi"]), dev(phi_old)))
+    tie = np.abs(ind) <= 1e-12 * np.abs(ind).max()
+    assert np.array_equal(got[~tie], ref[~tie]) and set(np.unique(got)) <= {0, 1}
+
+
+@pytest.mark.parametrize("name,kw,prec", [("C1", {}, "f64"), ("C2", dict(N=16, n_h_levels=3), "f64"),
+                                          ("C3", dict(N=4, n_h_levels=2), "f64"),
+                                          ("C3", dict(N=4, n_h_levels=2), "f32")])
+def test_fgmres_solve(name, kw, prec):
+    cfg = CONFIGS[name].with_(**kw)
+    levels = level_list(cfg)
+    inp = make_inputs(cfg, ("rhs",))
+    H = mg.Hierarchy(cfg, levels, inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
+    A = H.levels[-1].A
+    b = H.levels[-1].pvec * inp["rhs"]
+    xo, info_o = krylov.fgmres(lambda v: A @ v, H.vcycle, b, cfg.restart, cfg.rtol, cfg.max_iter)
+    from helpers import gpu_context
+    say(name, kw, prec, "gmres")
+    ctx = gpu_context(cfg, levels, inp, vcycle_prec=prec)
+    x, info = ctx.gmres_solve(dev(b))
+    x = host(x)
+    res = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    say(name, prec, "gpu iters", info["iterations"], "oracle iters", info_o["iterations"], "true res", res)
+    assert info["converged"] == 1 and res <= cfg.rtol * 1.001
+    if prec == "f64":
+        assert abs(info["iterations"] - info_o["iterations"]) <= 1
+    assert np.linalg.norm(x - xo) <= 1e-5 * np.linalg.norm(xo)
+
+
+def test_newton_step_small():
+    cfg = CONFIGS["C2"].with_(N=16, n_h_levels=3)
+    levels = level_list(cfg)
+    inp = make_inputs(cfg)
+    out = newton.newton_step(cfg, levels, inp["u"], inp["phi"], inp["phi_old"], inp["phi_tilde"])
+    from paper_2005_00331_amd import Context, problem_from
+    ctx = Context(problem_from(cfg, levels))
+    u, phi = dev(inp["u"]), dev(inp["phi"])
+    say("newton step")
+    act, info = ctx.newton_step(u, phi, dev(inp["phi_old"]), dev(inp["phi_tilde"]))
+    act = host(act)
+    ind = out["indicator"]
+    tie = np.abs(ind) <= 1e-12 * np.abs(ind).max()
+    assert np.array_equal(act[~tie], out["active"][~tie])
+    assert info["converged"] == 1
+    nn = inp["phi"].size
+    dU = np.concatenate([host(u) - inp["u"].ravel(), host(phi) - inp["phi"]])
+    A = out["hier"].levels[-1].A
+    assert np.linalg.norm(out["b"] - A @ dU) <= 1.001 * cfg.rtol * np.linalg.norm(out["b"])
+    assert np.linalg.norm(dU - out["dU"]) <= 1e-5 * np.linalg.norm(out["dU"])
