@@ -1,0 +1,189 @@
+"""Benchmark: one semi-smooth Newton step of the phase-field fracture problem.
+
+Workload (default): 2D unit square, 256x256 cells, Q2 for (u_x, u_y, phi)
+= 789,507 dofs, FP64; residual, active set, linearisation (diagonals,
+Lanczos estimates, coarse factorisation), FGMRES(30) preconditioned by a
+5-level monolithic GMG V-cycle to a 1e-8 relative residual, and the update.
+Each timed step restarts from the same seeded synthetic state, with all
+inputs resident in HBM before timing starts.
+
+Prints one JSON line with the metric, the Newton-step throughput (DoF/s),
+the live roofline of the dominant kernel (the finest-level cell kernel,
+timed with HIP events on the library's stream) and the oracle timed on the
+host cores on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Jacobian-apply DoFs/s and GMG-GMRES time per Newton step, FP64 vs mixed"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes_per_apply(dim, n_nodes, elem):
+    """x read + y written ((dim+1) comps each), u (dim comps), phi, phi~ read, 1-byte mask."""
+    return ((dim + 1) * 2 + dim + 2) * elem * n_nodes + n_nodes
+
+
+def build_context(cfg, prec=None):
+    import torch
+    from paper_2005_00331_amd import Context, problem_from
+    from synth import level_list, make_inputs
+    levels = level_list(cfg)
+    ctx = Context(problem_from(cfg, levels, vcycle_prec=prec))
+    inp = make_inputs(cfg)
+
+    def d(a):
+        return torch.from_numpy(a.ravel().copy()).cuda()
+    state = {k: d(v) for k, v in inp.items()}
+    return ctx, levels, state
+
+
+def time_newton(ctx, state, steps, warmup):
+    import torch
+    u = state["u"].clone()
+    phi = state["phi"].clone()
+    act = torch.empty_like(state["active"])
+    infos = []
+
+    def step():
+        u.copy_(state["u"])
+        phi.copy_(state["phi"])
+        _, info = ctx.newton_step(u, phi, state["phi_old"], state["phi_tilde"], act)
+        infos.append(info)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    infos.clear()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    return (t1 - t0) / steps, infos
+
+
+def time_apply(ctx, n_launch=50):
+    """Average duration of one finest-level cell-kernel launch (FP64, full operator)."""
+    import torch
+    from paper_2005_00331_amd import OP_ACCUMULATE, OP_G
+    n = ctx.n_dofs
+    x = torch.randn(n, dtype=torch.float64, device="cuda")
+    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    for _ in range(5):
+        ctx.apply_jacobian(-1, x, y, op=OP_G | OP_ACCUMULATE)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(n_launch):
+        ctx.apply_jacobian(-1, x, y, op=OP_G | OP_ACCUMULATE)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / n_launch
+
+
+def cpu_baseline(cfg_name):
+    """Oracle Newton step on a bounded sample of the same workload family."""
+    import numpy as np
+    from oracle import newton
+    from synth import CONFIGS, level_list, make_inputs
+    try:
+        from threadpoolctl import threadpool_info
+        blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
+    except Exception:
+        blas_threads = os.cpu_count()
+    base = CONFIGS[cfg_name]
+    cfg = base.with_(N=base.N // 2, n_h_levels=base.n_h_levels - 1)   # same coarse grid, 1/4 of the dofs
+    inp = make_inputs(cfg)
+    t0 = time.perf_counter()
+    out = newton.newton_step(cfg, level_list(cfg), inp["u"], inp["phi"], inp["phi_old"], inp["phi_tilde"])
+    t = time.perf_counter() - t0
+    return {"value": cfg.n_dofs / t, "unit": "DoF/s", "cores": int(blas_threads), "kind": "oracle",
+            "sample": (f"one oracle Newton step (assembly, {cfg.n_h_levels}-level GMG hierarchy, FGMRES) on "
+                       f"{cfg.N}x{cfg.N} Q{cfg.k}, {cfg.n_dofs} dofs, {t:.1f} s, {out['info']['iterations']} GMRES "
+                       f"iterations; sparse products single-threaded, dense coarse factorisation on "
+                       f"{blas_threads} BLAS threads"),
+            "seconds": t, "iterations": out["info"]["iterations"]}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison step")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU sharding is a design in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from synth import CONFIGS
+    torch.cuda.set_device(0)
+    cfg = CONFIGS[args.workload]
+    print(f"[bench] workload {cfg.name}: {cfg.dim}D N={cfg.N} Q{cfg.k}, {cfg.n_dofs} dofs", file=sys.stderr, flush=True)
+    ctx, levels, state = build_context(cfg)
+    sec, infos = time_newton(ctx, state, args.steps, args.warmup)
+    print(f"[bench] newton step {sec * 1e3:.2f} ms, iters {[i['iterations'] for i in infos]}", file=sys.stderr,
+          flush=True)
+    t_apply = time_apply(ctx)
+    elem = 8
+    byts = algorithmic_bytes_per_apply(cfg.dim, ctx.n_nodes, elem)
+    achieved = byts / t_apply / 1e9
+    print(f"[bench] finest cell kernel {t_apply * 1e6:.1f} us, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
+    detail = {
+        "apply_dofs_per_s": ctx.n_dofs / t_apply,
+        "apply_us": t_apply * 1e6,
+        "gmres_iterations": infos[-1]["iterations"],
+        "ms_setup": infos[-1]["ms_setup"],
+        "ms_solve": infos[-1]["ms_solve"],
+        "rel_residual": infos[-1]["rel_residual"],
+        "n_active": infos[-1]["n_active"],
+    }
+    if not args.no_mixed:
+        mctx, _, mstate = build_context(cfg, prec="f32")
+        msec, minfos = time_newton(mctx, mstate, 2, 1)
+        detail["mixed_f32_vcycle"] = {"ms_per_step": msec * 1e3, "gmres_iterations": minfos[-1]["iterations"],
+                                      "ms_setup": minfos[-1]["ms_setup"], "ms_solve": minfos[-1]["ms_solve"],
+                                      "rel_residual": minfos[-1]["rel_residual"]}
+        print(f"[bench] mixed newton step {msec * 1e3:.2f} ms", file=sys.stderr, flush=True)
+        mctx.close()
+    out = {
+        "metric": METRIC,
+        "value": ctx.n_dofs / sec,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": sec * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{cfg.name}: {cfg.dim}D {cfg.N}^{cfg.dim} cells Q{cfg.k}, {cfg.n_dofs} dofs, one "
+                               f"semi-smooth Newton step, {len(levels)}-level GMG-GMRES({cfg.restart}), rtol {cfg.rtol}",
+                   "levels": levels, "n_dofs": ctx.n_dofs, "vcycle_prec": cfg.vcycle_prec},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"cell_kernel<{cfg.dim},{cfg.k},double,APPLY> on the finest level",
+                     "bytes_per_launch": byts},
+        "detail": detail,
+    }
+    ctx.close()
+    if not args.no_cpu:
+        print("[bench] oracle cpu baseline ...", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(cfg.name)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

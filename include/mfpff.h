@@ -64,7 +64,9 @@ typedef enum { MFPFF_F64 = 0, MFPFF_F32 = 1 } mfpff_prec;
 typedef enum {
   MFPFF_OP_G = 0,         /* y = G^ x */
   MFPFF_OP_GT = 1,        /* y = G^T-hat x (transpose: coupling moves to the u rows) */
-  MFPFF_OP_BLOCKDIAG = 2  /* y = diag(G^_uu, G^_phiphi) x (smoother operator) */
+  MFPFF_OP_BLOCKDIAG = 2, /* y = diag(G^_uu, G^_phiphi) x (smoother operator) */
+  MFPFF_OP_ACCUMULATE = 16 /* flag: y += P op(G) P x on the free rows, y not initialised
+                              (one cell-kernel launch, no identity part) */
 } mfpff_op;
 
 /* Problem description.  Levels run from the coarsest (index 0) to the
@@ -131,7 +133,7 @@ mfpff_status mfpff_set_linearization(mfpff_ctx* ctx, const double* u, const doub
 
 /* y = op(G^_level) x on one level.  x, y: n_dofs of that level, FP64 or FP32
  * per `prec` (FP32 uses the FP32 copy of the level data).  x and y must not
- * alias. */
+ * alias.  `op` is an mfpff_op value, optionally or-ed with MFPFF_OP_ACCUMULATE. */
 mfpff_status mfpff_apply_jacobian(mfpff_ctx* ctx, int level, const void* x, void* y, int prec, int op);
 
 /* Diagonal of G^_level (1 at fixed dofs), FP64, n_dofs of the level. */

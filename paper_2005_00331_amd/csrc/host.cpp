@@ -275,13 +275,16 @@ const Tables<double>* tab<double>(mfpff_ctx* c, int k) { return c->tab64[k]; }
 template <>
 const Tables<float>* tab<float>(mfpff_ctx* c, int k) { return c->tab32[k]; }
 
-// y = op(G^) x on level l, or y = b - G^ x when b != null (op = G)
+// y = op(G^) x on level l, or y = b - G^ x when b != null (op = G);
+// accumulate: y += P op(G) P x without initialising y
 template <typename T>
-void apply_op(mfpff_ctx* c, int l, int mode, const T* x, T* y, const T* b) {
+void apply_op(mfpff_ctx* c, int l, int mode, const T* x, T* y, const T* b, bool accumulate = false) {
   Level& L = c->lv[l];
   const T scale = b ? T(-1) : T(1);
-  k_mask_init<T>(y, b, x, L.mask, L.nn, c->dim, scale, c->s);
-  LAUNCHCHK();
+  if (!accumulate) {
+    k_mask_init<T>(y, b, x, L.mask, L.nn, c->dim, scale, c->s);
+    LAUNCHCHK();
+  }
   CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), x, y, scale);
   HIPCHK(launch_cell<T>(mode, a, tab<T>(c, L.g.k), c->s));
 }
@@ -895,15 +898,17 @@ mfpff_status mfpff_apply_jacobian(mfpff_ctx* c, int level, const void* x, void* 
     require_ptr(y, "y");
     if (x == y) throw StatusError{MFPFF_ERR_ARG, "x and y alias"};
     int mode;
-    if (op == MFPFF_OP_G) mode = MODE_APPLY;
-    else if (op == MFPFF_OP_GT) mode = MODE_APPLY_T;
-    else if (op == MFPFF_OP_BLOCKDIAG) mode = MODE_BLOCK;
+    const bool acc = (op & MFPFF_OP_ACCUMULATE) != 0;
+    const int base = op & ~MFPFF_OP_ACCUMULATE;
+    if (base == MFPFF_OP_G) mode = MODE_APPLY;
+    else if (base == MFPFF_OP_GT) mode = MODE_APPLY_T;
+    else if (base == MFPFF_OP_BLOCKDIAG) mode = MODE_BLOCK;
     else throw StatusError{MFPFF_ERR_ARG, "unknown operator"};
     if (prec == MFPFF_F64) {
-      apply_op<double>(c, level, mode, (const double*)x, (double*)y, nullptr);
+      apply_op<double>(c, level, mode, (const double*)x, (double*)y, nullptr, acc);
     } else if (prec == MFPFF_F32) {
       if (!c->f32) throw StatusError{MFPFF_ERR_ARG, "FP32 level data exist only with an FP32 V-cycle"};
-      apply_op<float>(c, level, mode, (const float*)x, (float*)y, nullptr);
+      apply_op<float>(c, level, mode, (const float*)x, (float*)y, nullptr, acc);
     } else {
       throw StatusError{MFPFF_ERR_ARG, "unknown precision"};
     }
