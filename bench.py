@@ -70,19 +70,22 @@ def time_newton(ctx, state, steps, warmup):
 
 
 def time_apply(ctx, n_launch=50):
-    """Average duration of one finest-level cell-kernel launch (FP64, full operator)."""
+    """Average duration of one finest-level cell-kernel launch (FP64, full operator).
+    2D: the owner-computes kernel (one launch per product); 3D: the atomic
+    cell kernel alone (accumulate flag, no output initialisation)."""
     import torch
     from paper_2005_00331_amd import OP_ACCUMULATE, OP_G
     n = ctx.n_dofs
+    op = OP_G if ctx.dim == 2 else (OP_G | OP_ACCUMULATE)
     x = torch.randn(n, dtype=torch.float64, device="cuda")
     y = torch.zeros(n, dtype=torch.float64, device="cuda")
     for _ in range(5):
-        ctx.apply_jacobian(-1, x, y, op=OP_G | OP_ACCUMULATE)
+        ctx.apply_jacobian(-1, x, y, op=op)
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(n_launch):
-        ctx.apply_jacobian(-1, x, y, op=OP_G | OP_ACCUMULATE)
+        ctx.apply_jacobian(-1, x, y, op=op)
     e1.record(s)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1e3 / n_launch
@@ -120,6 +123,8 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison step")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="only time the finest-level cell kernel (for kernel-trace and counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -131,6 +136,14 @@ def main():
     cfg = CONFIGS[args.workload]
     print(f"[bench] workload {cfg.name}: {cfg.dim}D N={cfg.N} Q{cfg.k}, {cfg.n_dofs} dofs", file=sys.stderr, flush=True)
     ctx, levels, state = build_context(cfg)
+    if args.apply_only:
+        zeros = torch.zeros(ctx.n_nodes, dtype=torch.uint8, device="cuda")
+        ctx.set_linearization(state["u"], state["phi"], state["phi_old"], zeros, state["phi_tilde"])
+        t_apply = time_apply(ctx)
+        byts = algorithmic_bytes_per_apply(cfg.dim, ctx.n_nodes, 8)
+        print(json.dumps({"apply_us": t_apply * 1e6, "GB/s": byts / t_apply / 1e9, "bytes_per_launch": byts}), flush=True)
+        ctx.close()
+        return
     sec, infos = time_newton(ctx, state, args.steps, args.warmup)
     print(f"[bench] newton step {sec * 1e3:.2f} ms, iters {[i['iterations'] for i in infos]}", file=sys.stderr,
           flush=True)
@@ -174,7 +187,9 @@ def main():
                    "levels": levels, "n_dofs": ctx.n_dofs, "vcycle_prec": cfg.vcycle_prec},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": f"cell_kernel<{cfg.dim},{cfg.k},double,APPLY> on the finest level",
+                     "kernel": ((f"regcell_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>" if cfg.k <= 2 else
+                                 f"tile_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>") if cfg.dim == 2 else
+                                f"cell_kernel<{cfg.dim},{cfg.k},double,APPLY>") + " on the finest level",
                      "bytes_per_launch": byts},
         "detail": detail,
     }

@@ -13,93 +13,21 @@
 // Cell contributions are scattered with hardware FP64/FP32 atomics.
 #include <type_traits>
 
-#include "internal.h"
+#include "cell_common.h"
 
 namespace mfpff {
-
-__host__ __device__ constexpr int ipow(int b, int e) { return e == 0 ? 1 : b * ipow(b, e - 1); }
-
-template <int DIM, int K>
-struct Shape {
-  static constexpr int NP = K + 1;
-  static constexpr int P = ipow(NP, DIM);
-  static constexpr int CPB = kThreads / P;
-  static constexpr int NPTS = CPB * P;
-  static constexpr int NBUF = DIM * DIM + DIM + 1;
-};
-
-template <typename T>
-__device__ __forceinline__ void atomic_add(T* p, T v) {
-  unsafeAtomicAdd(p, v);
-}
-
-// out[f][c][p] = sum_r mat[digit_dir(p)][r] * in[f][c][p with digit_dir = r]
-template <int NP, int P, int NPTS, typename T>
-__device__ __forceinline__ void sweep(const T* __restrict__ in, T* __restrict__ out, int nf,
-                                      const T* __restrict__ mat, int dir, int tid) {
-  if (tid >= NPTS) return;
-  const int c = tid / P, p = tid - (tid / P) * P;
-  const int st = dir == 0 ? 1 : (dir == 1 ? NP : NP * NP);
-  const int dg = (p / st) % NP;
-  const int base = c * P + p - dg * st;
-  const T* m = mat + dg * NP;
-  for (int f = 0; f < nf; ++f) {
-    const T* src = in + f * NPTS + base;
-    T acc = 0;
-#pragma unroll
-    for (int r = 0; r < NP; ++r) acc += m[r] * src[r * st];
-    out[f * NPTS + c * P + p] = acc;
-  }
-}
-
-// Derivative along dir at own point from a value tensor (collocation matrix C).
-template <int NP, int P, int NPTS, typename T>
-__device__ __forceinline__ T coll_deriv(const T* __restrict__ V, const T* __restrict__ C, int dir, int c, int p) {
-  const int st = dir == 0 ? 1 : (dir == 1 ? NP : NP * NP);
-  const int dg = (p / st) % NP;
-  const T* src = V + c * P + p - dg * st;
-  const T* m = C + dg * NP;
-  T acc = 0;
-#pragma unroll
-  for (int r = 0; r < NP; ++r) acc += m[r] * src[r * st];
-  return acc;
-}
-
-template <int DIM, int K>
-__device__ __forceinline__ long long node_of(const Geom& g, long long cell, int p) {
-  constexpr int NP = K + 1;
-  const long long N = g.N, M = g.M;
-  const long long cx = cell % N;
-  const long long cy = (cell / N) % N;
-  const int i0 = p % NP, i1 = (p / NP) % NP;
-  long long node = (K * cx + i0) + M * (K * cy + i1);
-  if (DIM == 3) {
-    const long long cz = cell / (N * N);
-    const int i2 = p / (NP * NP);
-    node += M * M * (K * cz + i2);
-  }
-  return node;
-}
 
 template <int DIM, int K, typename T, int MODE>
 __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tables<T>* __restrict__ tab) {
   using S = Shape<DIM, K>;
   constexpr int NP = S::NP, P = S::P, CPB = S::CPB, NPTS = S::NPTS, NBUF = S::NBUF;
   constexpr bool XMODE = (MODE == MODE_APPLY || MODE == MODE_APPLY_T || MODE == MODE_BLOCK || MODE == MODE_ELEM);
-  __shared__ T sB[NP * NP], sBt[NP * NP], sC[NP * NP], sCt[NP * NP], sW[NP];
+  __shared__ SharedTables<NP, T> st;
   __shared__ T buf0[NBUF * NPTS];
   __shared__ T buf1[NBUF * NPTS];
-  __shared__ double sred[2 * kThreads];
 
   const int tid = threadIdx.x;
-  if (tid < NP * NP) {
-    const int q = tid / NP, i = tid % NP;
-    sB[tid] = tab->B[q][i];
-    sBt[i * NP + q] = tab->B[q][i];
-    sC[tid] = tab->C[q][i];
-    sCt[i * NP + q] = tab->C[q][i];
-  }
-  if (tid < NP) sW[tid] = tab->w[tid];
+  st.load(tab, tid);
 
   const Geom g = a.g;
   const long long nn = g.n_nodes;
@@ -125,7 +53,6 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
   // field order: XMODE: x_0..x_d, u_0..u_{d-1}, phi, phit
   //              RESIDUAL: u_0..u_{d-1}, phi, phit
   //              PVJP: phi, v_phi
-  int nf = 0;
   if (inb) {
     const int o = c * P + p;
     if (XMODE) {
@@ -163,42 +90,33 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
       buf0[NPTS + o] = valid ? a.x[DIM * nn + node] : T(0);
     }
   }
-  nf = XMODE ? (2 * DIM + 3) : (MODE == MODE_RESIDUAL ? DIM + 2 : 2);
   __syncthreads();
 
-  // ---------------- values at quadrature points: d sweeps with B
-  sweep<NP, P, NPTS, T>(buf0, buf1, nf, sB, 0, tid);
-  __syncthreads();
-  sweep<NP, P, NPTS, T>(buf1, buf0, nf, sB, 1, tid);
-  __syncthreads();
-  if (DIM == 3) {
-    sweep<NP, P, NPTS, T>(buf0, buf1, nf, sB, 2, tid);
+  if constexpr (MODE == MODE_PVJP) {
+    // values and gradients of phi and v_phi; per-block sums of
+    // (1-phi, v) and (grad phi, grad v) weighted for dGc and deps
+    __shared__ double sred[2 * kThreads];
+    sweep<NP, P, NPTS, T>(buf0, buf1, 2, st.B, 0, tid);
     __syncthreads();
-  }
-  T* V = DIM == 2 ? buf0 : buf1;
-  T* W = DIM == 2 ? buf1 : buf0;
-
-  const T h = (T)g.h;
-  const T ih = T(1) / h;
-  T jxw = 0;
-  if (inb) {
-    const int q0 = p % NP, q1 = (p / NP) % NP;
-    jxw = sW[q0] * sW[q1] * h * h;
-    if (DIM == 3) jxw *= sW[p / (NP * NP)] * h;
-  }
-  const T lam = (T)a.m.lam, mu = (T)a.m.mu, Gc = (T)a.m.Gc, eps = (T)a.m.eps, kap = (T)a.m.kappa;
-  const T Kb = lam + T(2) * mu / T(DIM);
-
-  if (MODE == MODE_PVJP) {
+    sweep<NP, P, NPTS, T>(buf1, buf0, 2, st.B, 1, tid);
+    __syncthreads();
+    if (DIM == 3) {
+      sweep<NP, P, NPTS, T>(buf0, buf1, 2, st.B, 2, tid);
+      __syncthreads();
+    }
+    const T* V = DIM == 2 ? buf0 : buf1;
+    const T h = (T)g.h, ih = T(1) / h, Gc = (T)a.m.Gc, eps = (T)a.m.eps;
     double s0 = 0, s1 = 0;
     if (valid) {
+      T jxw = st.W[p % NP] * st.W[(p / NP) % NP] * h * h;
+      if (DIM == 3) jxw *= st.W[p / (NP * NP)] * h;
       const T ph = V[c * P + p];
       const T vq = V[NPTS + c * P + p];
       T gpgv = 0;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) {
-        const T gp = coll_deriv<NP, P, NPTS, T>(V, sC, m, c, p) * ih;
-        const T gv = coll_deriv<NP, P, NPTS, T>(V + NPTS, sC, m, c, p) * ih;
+        const T gp = coll_deriv<NP, P, NPTS, T>(V, st.C, m, c, p) * ih;
+        const T gv = coll_deriv<NP, P, NPTS, T>(V + NPTS, st.C, m, c, p) * ih;
         gpgv += gp * gv;
       }
       const T om = (T(1) - ph) * vq;
@@ -219,157 +137,31 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
       a.partials[2 * blockIdx.x] = sred[0];
       a.partials[2 * blockIdx.x + 1] = sred[kThreads];
     }
-    return;
-  }
+  } else {
+    const T* R = cell_compute<DIM, K, T, MODE>(buf0, buf1, st, a.m, (T)g.h, tid);
 
-  // ---------------- quadrature-point physics -> fluxes in W
-  // flux tensors: [cc*DIM + m] u-test component cc, direction m; [DIM*DIM + m] phi gradient; [DIM*DIM+DIM] phi value
-  if (inb) {
-    const int o = c * P + p;
-    const int fu = XMODE ? DIM + 1 : 0;  // first u field
-    const int fph = fu + DIM, fpt = fu + DIM + 1;
-    T gu[DIM][DIM];
+    // ---------------- scatter
+    if (valid) {
+      const int o = c * P + p;
+      if (MODE == MODE_ELEM) {
+        const long long jnode = node_of<DIM, K>(g, cell, jp);
+        const uint8_t jm = a.mask ? a.mask[jnode] : (uint8_t)0;
+        const bool colfixed = (jcomp < DIM) ? (jm & kMaskU) : (jm & kMaskPhi);
+        if (!colfixed) {
+          const long long col = jcomp * nn + jnode;
 #pragma unroll
-    for (int cc = 0; cc < DIM; ++cc)
-#pragma unroll
-      for (int m = 0; m < DIM; ++m) gu[cc][m] = coll_deriv<NP, P, NPTS, T>(V + (fu + cc) * NPTS, sC, m, c, p) * ih;
-    const T ph = V[fph * NPTS + o];
-    const T pt = V[fpt * NPTS + o];
-    T e[DIM][DIM];
-    T t = 0;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i) {
-#pragma unroll
-      for (int j = 0; j < DIM; ++j) e[i][j] = T(0.5) * (gu[i][j] + gu[j][i]);
-      t += e[i][i];
-    }
-    const bool H = t >= T(0);
-    const T tp = H ? t : T(0);
-    const T tm = H ? T(0) : t;
-    T devdev = 0;
-#pragma unroll
-    for (int i = 0; i < DIM; ++i)
-#pragma unroll
-      for (int j = 0; j < DIM; ++j) {
-        const T dv = e[i][j] - (i == j ? t / T(DIM) : T(0));
-        devdev += dv * dv;
-      }
-    const T Ep = T(0.5) * Kb * tp * tp + mu * devdev;
-    const T gt = (T(1) - kap) * pt * pt + kap;
-    const T dg = T(2) * (T(1) - kap) * ph;
-    const T ddg = T(2) * (T(1) - kap);
-    // sigma^+ (symmetric)
-    T sp[DIM][DIM];
-#pragma unroll
-    for (int i = 0; i < DIM; ++i)
-#pragma unroll
-      for (int j = 0; j < DIM; ++j)
-        sp[i][j] = T(2) * mu * (e[i][j] - (i == j ? t / T(DIM) : T(0))) + (i == j ? Kb * tp : T(0));
-
-    T Su[DIM][DIM];
-    T fval = 0, fgrad[DIM];
-    if (XMODE) {
-      T gx[DIM][DIM];
-#pragma unroll
-      for (int cc = 0; cc < DIM; ++cc)
-#pragma unroll
-        for (int m = 0; m < DIM; ++m) gx[cc][m] = coll_deriv<NP, P, NPTS, T>(V + cc * NPTS, sC, m, c, p) * ih;
-      const T dph = V[DIM * NPTS + o];
-      T de[DIM][DIM];
-      T dt = 0;
-#pragma unroll
-      for (int i = 0; i < DIM; ++i) {
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) de[i][j] = T(0.5) * (gx[i][j] + gx[j][i]);
-        dt += de[i][i];
-      }
-      // delta sigma = g~ [K H dt I + 2 mu dev de] + K (1-H) dt I
-      const T vol = (H ? gt * Kb * dt : Kb * dt);
-      T spde = 0;
-#pragma unroll
-      for (int i = 0; i < DIM; ++i)
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) {
-          Su[i][j] = gt * T(2) * mu * (de[i][j] - (i == j ? dt / T(DIM) : T(0))) + (i == j ? vol : T(0));
-          spde += sp[i][j] * de[i][j];
+          for (int cc = 0; cc <= DIM; ++cc) {
+            const bool fixed = (cc < DIM) ? (mk & kMaskU) : (mk & kMaskPhi);
+            if (!fixed) atomic_add(a.dense + (cc * nn + node) * a.ld + col, (double)R[cc * NPTS + o]);
+          }
         }
-      if (MODE == MODE_APPLY_T) {
-#pragma unroll
-        for (int i = 0; i < DIM; ++i)
-#pragma unroll
-          for (int j = 0; j < DIM; ++j) Su[i][j] += dg * dph * sp[i][j];
-      }
-      fval = (ddg * Ep + Gc / eps) * dph;
-      if (MODE == MODE_APPLY || MODE == MODE_ELEM) fval += dg * spde;
-#pragma unroll
-      for (int m = 0; m < DIM; ++m) fgrad[m] = Gc * eps * coll_deriv<NP, P, NPTS, T>(V + DIM * NPTS, sC, m, c, p) * ih;
-    } else {  // RESIDUAL
-#pragma unroll
-      for (int i = 0; i < DIM; ++i)
-#pragma unroll
-        for (int j = 0; j < DIM; ++j) Su[i][j] = gt * sp[i][j] + (i == j ? Kb * tm : T(0));
-      fval = dg * Ep - Gc * (T(1) - ph) / eps;
-#pragma unroll
-      for (int m = 0; m < DIM; ++m) fgrad[m] = Gc * eps * coll_deriv<NP, P, NPTS, T>(V + fph * NPTS, sC, m, c, p) * ih;
-    }
-    // scale by JxW and the 1/h of the test gradient
-    const T jg = jxw * ih;
-#pragma unroll
-    for (int cc = 0; cc < DIM; ++cc)
-#pragma unroll
-      for (int m = 0; m < DIM; ++m) W[(cc * DIM + m) * NPTS + o] = jg * Su[cc][m];
-#pragma unroll
-    for (int m = 0; m < DIM; ++m) W[(DIM * DIM + m) * NPTS + o] = jg * fgrad[m];
-    W[(DIM * DIM + DIM) * NPTS + o] = jxw * fval;
-  }
-  __syncthreads();
-
-  // ---------------- collocation transpose: s_t(q') = value flux + sum_m C^T along m of grad flux
-  if (inb) {
-    const int o = c * P + p;
-#pragma unroll
-    for (int tcomp = 0; tcomp <= DIM; ++tcomp) {
-      T s = (tcomp == DIM) ? W[(DIM * DIM + DIM) * NPTS + o] : T(0);
-#pragma unroll
-      for (int m = 0; m < DIM; ++m) s += coll_deriv<NP, P, NPTS, T>(W + (tcomp * DIM + m) * NPTS, sCt, m, c, p);
-      V[tcomp * NPTS + o] = s;
-    }
-  }
-  __syncthreads();
-
-  // ---------------- integrate: d sweeps with B^T
-  sweep<NP, P, NPTS, T>(V, W, DIM + 1, sBt, 0, tid);
-  __syncthreads();
-  sweep<NP, P, NPTS, T>(W, V, DIM + 1, sBt, 1, tid);
-  __syncthreads();
-  const T* R = V;
-  if (DIM == 3) {
-    sweep<NP, P, NPTS, T>(V, W, DIM + 1, sBt, 2, tid);
-    __syncthreads();
-    R = W;
-  }
-
-  // ---------------- scatter
-  if (valid) {
-    const int o = c * P + p;
-    if (MODE == MODE_ELEM) {
-      const long long jnode = node_of<DIM, K>(g, cell, jp);
-      const uint8_t jm = a.mask ? a.mask[jnode] : (uint8_t)0;
-      const bool colfixed = (jcomp < DIM) ? (jm & kMaskU) : (jm & kMaskPhi);
-      if (!colfixed) {
-        const long long col = jcomp * nn + jnode;
+      } else {
+        const bool resmode = (MODE == MODE_RESIDUAL);
 #pragma unroll
         for (int cc = 0; cc <= DIM; ++cc) {
-          const bool fixed = (cc < DIM) ? (mk & kMaskU) : (mk & kMaskPhi);
-          if (!fixed) atomic_add(a.dense + (cc * nn + node) * a.ld + col, (double)R[cc * NPTS + o]);
+          const bool fixed = resmode ? false : ((cc < DIM) ? (mk & kMaskU) : (mk & kMaskPhi));
+          if (!fixed) atomic_add(a.y + cc * nn + node, a.scale * R[cc * NPTS + o]);
         }
-      }
-    } else {
-      const bool resmode = (MODE == MODE_RESIDUAL);
-#pragma unroll
-      for (int cc = 0; cc <= DIM; ++cc) {
-        const bool fixed = resmode ? false : ((cc < DIM) ? (mk & kMaskU) : (mk & kMaskPhi));
-        if (!fixed) atomic_add(a.y + cc * nn + node, a.scale * R[cc * NPTS + o]);
       }
     }
   }
@@ -384,7 +176,7 @@ template <int DIM, int K, typename T>
 __global__ __launch_bounds__(kThreads) void diag_kernel(CellArgs<T> a, const Tables<T>* __restrict__ tab) {
   using S = Shape<DIM, K>;
   constexpr int NP = S::NP, P = S::P, CPB = S::CPB, NPTS = S::NPTS, NBUF = S::NBUF;
-  __shared__ T sB[NP * NP], sC[NP * NP], sB2t[NP * NP], sD2t[NP * NP], sW[NP];
+  __shared__ T sB[NP * NP], sC[NP * NP], sB2t[NP * NP], sD2t[NP * NP], sW[NP];  // basis, collocation, squared tables
   __shared__ T buf0[NBUF * NPTS];
   __shared__ T buf1[NBUF * NPTS];
   const int tid = threadIdx.x;

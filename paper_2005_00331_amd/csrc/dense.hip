@@ -50,7 +50,7 @@ void k_extract_block(double* dst, long long ldd, const double* src, long long ld
 // writes L11 to `diag` (copied into A by the next kernel, so that no block
 // reads a half-written diagonal block), block b >= 1 solves
 // X L11^T = A[rows of b][k0:k0+TB] in place.
-__global__ void potrf_panel_kernel(double* A, int n, int k0, int* info, double* diag) {
+__global__ __launch_bounds__(kThreads) void potrf_panel_kernel(double* A, int n, int k0, int* info, double* diag) {
   __shared__ double L[TB][TB + 1];
   __shared__ double X[TB][TB + 1];
   const int tid = threadIdx.x;
@@ -90,12 +90,21 @@ __global__ void potrf_panel_kernel(double* A, int n, int k0, int* info, double* 
   }
   __syncthreads();
   if (tid < TB) {
+    // row tid of X L11^T = A_panel, unrolled so the row stays in registers
     const int i = tid;
+    double xr[TB];
+#pragma clang loop unroll(full)
+    for (int j = 0; j < TB; ++j) xr[j] = X[i][j];
+#pragma clang loop unroll(full)
     for (int j = 0; j < TB; ++j) {
-      double v = X[i][j];
-      for (int l = 0; l < j; ++l) v -= X[i][l] * L[j][l];
-      X[i][j] = v / L[j][j];
+      const double xj = xr[j] / L[j][j];
+      xr[j] = xj;
+#pragma clang loop unroll(full)
+      for (int l = 0; l < TB; ++l)
+        if (l > j) xr[l] -= xj * L[l][j];
     }
+#pragma clang loop unroll(full)
+    for (int j = 0; j < TB; ++j) X[i][j] = xr[j];
   }
   __syncthreads();
   for (int e = tid; e < TB * TB; e += blockDim.x) {
@@ -114,7 +123,7 @@ __global__ void copy_diag_kernel(double* A, int n, int k0, const double* diag) {
 }
 
 // Trailing update A[i][j] -= sum_l L[i][l] L[j][l], l in the panel, for tiles bi >= bj.
-__global__ void syrk_update_kernel(double* A, int n, int k0) {
+__global__ __launch_bounds__(kThreads) void syrk_update_kernel(double* A, int n, int k0) {
   __shared__ double Li[TB][TB + 1];
   __shared__ double Lj[TB][TB + 1];
   const int k1 = k0 + TB;
@@ -165,33 +174,33 @@ __global__ void eye_kernel(double* W, int n) {
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x)
     W[e] = (e / n == e % n) ? 1.0 : 0.0;
 }
-// W[k0:k0+TB, 0:ncols] = L11^-1 W[k0:k0+TB, 0:ncols]   (thread per column)
-__global__ void trsm_diag_kernel(double* W, const double* L, int n, int k0, int ncols) {
+// W[k0:k0+TB, 0:ncols] = L11^-1 W[k0:k0+TB, 0:ncols]: one wave per block, one
+// column per lane, the column held in LDS (registers would spill the triangle)
+constexpr int kTrsmLanes = 64;
+__global__ __launch_bounds__(kTrsmLanes) void trsm_diag_kernel(double* W, const double* L, int n, int k0, int ncols) {
   __shared__ double L11[TB][TB + 1];
+  __shared__ double xs[TB][kTrsmLanes];
   const int tid = threadIdx.x;
   for (int e = tid; e < TB * TB; e += blockDim.x) {
     const int i = e / TB, j = e % TB;
     const int gi = k0 + i, gj = k0 + j;
     L11[i][j] = (gi < n && gj < n) ? L[(long long)gi * n + gj] : (i == j ? 1.0 : 0.0);
   }
+  const int col = blockIdx.x * kTrsmLanes + tid;
+  const bool ok = col < ncols;
+  for (int i = 0; i < TB; ++i) xs[i][tid] = (ok && k0 + i < n) ? W[(long long)(k0 + i) * n + col] : 0.0;
   __syncthreads();
-  const int col = blockIdx.x * blockDim.x + tid;
-  if (col >= ncols) return;
-  double x[TB];
-#pragma unroll
-  for (int i = 0; i < TB; ++i) x[i] = (k0 + i < n) ? W[(long long)(k0 + i) * n + col] : 0.0;
-#pragma unroll
-  for (int i = 0; i < TB; ++i) {
-    double v = x[i];
-    for (int l = 0; l < i; ++l) v -= L11[i][l] * x[l];
-    x[i] = v / L11[i][i];
+  for (int j = 0; j < TB; ++j) {
+    const double xj = xs[j][tid] / L11[j][j];
+    xs[j][tid] = xj;
+    for (int i = j + 1; i < TB; ++i) xs[i][tid] -= L11[i][j] * xj;
   }
-#pragma unroll
+  if (!ok) return;
   for (int i = 0; i < TB; ++i)
-    if (k0 + i < n) W[(long long)(k0 + i) * n + col] = x[i];
+    if (k0 + i < n) W[(long long)(k0 + i) * n + col] = xs[i][tid];
 }
 // W[r][c] -= sum_l L[r][k0+l] W[k0+l][c] for r >= k0+TB, c < ncols
-__global__ void trsm_update_kernel(double* W, const double* L, int n, int k0, int ncols) {
+__global__ __launch_bounds__(kThreads) void trsm_update_kernel(double* W, const double* L, int n, int k0, int ncols) {
   __shared__ double Ls[TB][TB + 1];
   __shared__ double Ws[TB][TB + 1];
   const int r0 = k0 + TB + blockIdx.y * TB;
@@ -221,7 +230,8 @@ hipError_t tri_inverse_lower(double* W, const double* L, int n, hipStream_t s) {
   hipLaunchKernelGGL(eye_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, W, n);
   for (int k0 = 0; k0 < n; k0 += TB) {
     const int ncols = k0 + TB < n ? k0 + TB : n;
-    hipLaunchKernelGGL(trsm_diag_kernel, dim3((ncols + kThreads - 1) / kThreads), dim3(kThreads), 0, s, W, L, n, k0, ncols);
+    hipLaunchKernelGGL(trsm_diag_kernel, dim3((ncols + kTrsmLanes - 1) / kTrsmLanes), dim3(kTrsmLanes), 0, s, W, L, n, k0,
+                       ncols);
     const int rows = n - (k0 + TB);
     if (rows > 0) {
       dim3 grid((ncols + TB - 1) / TB, (rows + TB - 1) / TB);

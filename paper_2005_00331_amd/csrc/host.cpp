@@ -10,6 +10,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <functional>
 #include <string>
@@ -75,10 +76,10 @@ struct Level {
   int lsteps[2] = {0, 0};
   std::vector<double> c1u, c2u, c1p, c2p;  // Chebyshev step coefficients, index i = 1..s-1
   double ith_u = 1.0, ith_p = 1.0;
-  void* w[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};  // V-cycle vectors b, x, r, t, d, z
+  void* w[7] = {};  // V-cycle vectors b, x, r, t, d, z, z2
   DevSparse P1, R1;  // transfer from level-1 to this level
 };
-enum { WB = 0, WX = 1, WR = 2, WT = 3, WD = 4, WZ = 5 };
+enum { WB = 0, WX = 1, WR = 2, WT = 3, WD = 4, WZ = 5, WZ2 = 6, NW = 7 };
 
 }  // namespace
 
@@ -90,6 +91,7 @@ struct mfpff_ctx {
   std::vector<Level> lv;
   Tables<double>* tab64[kMaxDeg + 1] = {};
   Tables<float>* tab32[kMaxDeg + 1] = {};
+  Tables<double> tabh[kMaxDeg + 1] = {};  // host copies (by-value kernel arguments)
   double* w1d = nullptr;  // integrals of the finest-degree 1D basis functions
   double* ml = nullptr;   // lumped phi mass on the finest level
   // transfer temporaries (finest-level size)
@@ -133,6 +135,10 @@ struct mfpff_ctx {
   double* pvjp_part = nullptr;
   double* pvjp_out = nullptr;
   bool linearized = false;
+  // V-cycle captured as a graph after each linearisation (replayed per GMRES iteration)
+  hipStream_t cap_s = nullptr;
+  hipGraphExec_t vgraph = nullptr;
+  bool graph_ok = true;
   std::string err;
 };
 
@@ -275,71 +281,139 @@ const Tables<double>* tab<double>(mfpff_ctx* c, int k) { return c->tab64[k]; }
 template <>
 const Tables<float>* tab<float>(mfpff_ctx* c, int k) { return c->tab32[k]; }
 
+// 2D owner-computes launch: register-resident kernel for Q1/Q2, LDS tile kernel otherwise
+template <typename T>
+void launch_2d(mfpff_ctx* c, const Level& L, int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e) {
+  if (L.g.k <= 2) HIPCHK(launch_regcell_2d<T>(mode, epi, a, e, c->tabh[L.g.k], c->s));
+  else HIPCHK(launch_tile_2d<T>(mode, epi, a, e, tab<T>(c, L.g.k), c->s));
+}
+
 // y = op(G^) x on level l, or y = b - G^ x when b != null (op = G);
-// accumulate: y += P op(G) P x without initialising y
+// accumulate: y += P op(G) P x without initialising y (atomic cell kernel)
 template <typename T>
 void apply_op(mfpff_ctx* c, int l, int mode, const T* x, T* y, const T* b, bool accumulate = false) {
   Level& L = c->lv[l];
   const T scale = b ? T(-1) : T(1);
+  CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), x, y, scale);
+  if (c->dim == 2 && !accumulate) {
+    Epilogue<T> e{};
+    e.y = y;
+    e.b = b;
+    launch_2d<T>(c, L, mode, b ? EPI_RESID : EPI_APPLY, a, e);
+    return;
+  }
   if (!accumulate) {
     k_mask_init<T>(y, b, x, L.mask, L.nn, c->dim, scale, c->s);
     LAUNCHCHK();
   }
-  CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), x, y, scale);
   HIPCHK(launch_cell<T>(mode, a, tab<T>(c, L.g.k), c->s));
 }
 
-// z = diag(C_u, C_phi) r (Chebyshev from zero), work vectors d, t
+// r = b - G^ x; with z0 != null also the Chebyshev start z0 = D^-1 r / theta, d0 = z0
 template <typename T>
-void chebyshev(mfpff_ctx* c, int l, const T* r, T* z, T* d, T* t) {
+void op_resid(mfpff_ctx* c, int l, const T* b, const T* x, T* r, T* z0, T* d0) {
   Level& L = c->lv[l];
-  const T* dinv = level_dinv<T>(L);
-  k_cheb_init<T>(z, d, r, dinv, L.nn, c->dim, (T)L.ith_u, (T)L.ith_p, c->s);
-  LAUNCHCHK();
-  for (size_t i = 0; i < L.c1u.size(); ++i) {
-    apply_op<T>(c, l, MODE_BLOCK, z, t, nullptr);
-    k_cheb_step<T>(z, d, r, t, dinv, L.nn, c->dim, (T)L.c1u[i], (T)L.c2u[i], (T)L.c1p[i], (T)L.c2p[i], c->s);
+  if (c->dim == 2) {
+    CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), x, r, T(-1));
+    Epilogue<T> e{};
+    e.y = r;
+    e.b = b;
+    e.z0 = z0;
+    e.d0 = d0;
+    e.dinv = level_dinv<T>(L);
+    e.ith_u = (T)L.ith_u;
+    e.ith_p = (T)L.ith_p;
+    launch_2d<T>(c, L, MODE_APPLY, EPI_RESID, a, e);
+    return;
+  }
+  apply_op<T>(c, l, MODE_APPLY, x, r, b);
+  if (z0) {
+    k_cheb_init<T>(z0, d0, r, level_dinv<T>(L), L.nn, c->dim, (T)L.ith_u, (T)L.ith_p, c->s);
     LAUNCHCHK();
   }
 }
 
-// separable masked transfer; dir 0: out(level l) = P~ in(level l-1) [add to out if add];
-// dir 1: out(level l-1) = R~ in(level l)
+// Chebyshev step i (1-based): zout = zin + d', d' = c1 d + c2 D^-1 (r - A_blk zin); optional xout = xacc + zout
+template <typename T>
+void op_cheb_step(mfpff_ctx* c, int l, int i, const T* zin, T* zout, const T* r, T* d, T* t, const T* xacc, T* xout) {
+  Level& L = c->lv[l];
+  const T c1u = (T)L.c1u[i - 1], c2u = (T)L.c2u[i - 1], c1p = (T)L.c1p[i - 1], c2p = (T)L.c2p[i - 1];
+  if (c->dim == 2) {
+    CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), zin, zout, T(1));
+    Epilogue<T> e{};
+    e.y = zout;
+    e.dinv = level_dinv<T>(L);
+    e.r = r;
+    e.d = d;
+    e.c1u = c1u;
+    e.c2u = c2u;
+    e.c1p = c1p;
+    e.c2p = c2p;
+    e.xacc = xacc;
+    e.xout = xout;
+    launch_2d<T>(c, L, MODE_BLOCK, EPI_CHEB, a, e);
+    return;
+  }
+  apply_op<T>(c, l, MODE_BLOCK, zin, t, nullptr);
+  k_cheb_update<T>(zout, d, zin, r, t, level_dinv<T>(L), L.nn, c->dim, c1u, c2u, c1p, c2p, xacc, xout, c->s);
+  LAUNCHCHK();
+}
+
+// x = diag(C_u, C_phi) r (Chebyshev from zero); work vectors zA, zB, d, t (x distinct from them)
+template <typename T>
+void chebyshev(mfpff_ctx* c, int l, const T* r, T* x, T* zA, T* zB, T* d, T* t) {
+  Level& L = c->lv[l];
+  const int s = c->prob.cheb_degree;
+  T* zc = (s == 1) ? x : zA;
+  k_cheb_init<T>(zc, d, r, level_dinv<T>(L), L.nn, c->dim, (T)L.ith_u, (T)L.ith_p, c->s);
+  LAUNCHCHK();
+  for (int i = 1; i < s; ++i) {
+    T* zn = (i == s - 1) ? x : (zc == zA ? zB : zA);
+    op_cheb_step<T>(c, l, i, zc, zn, r, d, t, nullptr, nullptr);
+    zc = zn;
+  }
+}
+
+// x += diag(C_u, C_phi)(b - G^ x): residual with the fused Chebyshev start, then s-1 steps
+template <typename T>
+void post_smooth(mfpff_ctx* c, int l, const T* b, T* x, T* r, T* zA, T* zB, T* d, T* t) {
+  Level& L = c->lv[l];
+  const int s = c->prob.cheb_degree;
+  op_resid<T>(c, l, b, x, r, zA, d);
+  if (s == 1) {
+    k_axpy<T>(x, T(1), zA, L.n, c->s);
+    LAUNCHCHK();
+    return;
+  }
+  T* zc = zA;
+  for (int i = 1; i < s; ++i) {
+    T* zn = zc == zA ? zB : zA;
+    const bool last = i == s - 1;
+    op_cheb_step<T>(c, l, i, zc, zn, r, d, t, last ? x : nullptr, last ? x : nullptr);
+    zc = zn;
+  }
+}
+
+// masked transfer between level l-1 and l; dir 0: out(level l) = P~ in (or += when add);
+// dir 1: out(level l-1) = R~ in (axis passes, masks fused into the first and last pass)
 template <typename T>
 void transfer(mfpff_ctx* c, int l, int dir, const T* in, T* out, bool add, T* ta, T* tb) {
   Level& F = c->lv[l];
   Level& C = c->lv[l - 1];
   const int d = c->dim, nc = d + 1;
   if (dir == 0) {
-    k_copy<T>(ta, in, C.n, c->s);
-    k_mask_comp<T>(ta, C.mask, C.nn, d, c->s);
-    long long dims[3] = {C.g.M, C.g.M, C.g.M};
-    T* src = ta;
-    T* dst = tb;
-    for (int ax = 0; ax < d; ++ax) {
-      const bool last = ax == d - 1;
-      T* o = (last && !add) ? out : dst;
-      k_axis_apply<T>(o, src, F.P1.s, ax, d, dims, nc, c->s);
-      dims[ax] = F.g.M;
-      if (!last) std::swap(src, dst);
-      else src = o;
-    }
-    if (add) k_add_masked<T>(out, src, F.mask, F.nn, d, c->s);
-    else k_mask_comp<T>(out, F.mask, F.nn, d, c->s);
+    k_prolong<T>(out, in, F.P1.s, C.mask, F.mask, F.g, C.g, add, c->s);
   } else {
-    k_copy<T>(ta, in, F.n, c->s);
-    k_mask_comp<T>(ta, F.mask, F.nn, d, c->s);
     long long dims[3] = {F.g.M, F.g.M, F.g.M};
-    T* src = ta;
-    T* dst = tb;
+    const T* src = in;
+    T* bufs[2] = {ta, tb};
     for (int ax = 0; ax < d; ++ax) {
-      const bool last = ax == d - 1;
-      T* o = last ? out : dst;
-      k_axis_apply<T>(o, src, F.R1.s, ax, d, dims, nc, c->s);
+      const bool first = ax == 0, last = ax == d - 1;
+      T* o = last ? out : bufs[ax & 1];
+      k_axis_apply<T>(o, src, F.R1.s, ax, d, dims, nc, first ? F.mask : nullptr, last ? C.mask : nullptr, c->s);
       dims[ax] = C.g.M;
-      std::swap(src, dst);
+      src = o;
     }
-    k_mask_comp<T>(out, C.mask, C.nn, d, c->s);
   }
   LAUNCHCHK();
 }
@@ -380,32 +454,73 @@ void vcycle_rec(mfpff_ctx* c, int l) {
   T* r = (T*)L.w[WR];
   T* t = (T*)L.w[WT];
   T* d = (T*)L.w[WD];
-  T* z = (T*)L.w[WZ];
+  T* zA = (T*)L.w[WZ];
+  T* zB = (T*)L.w[WZ2];
   T* ta = std::is_same<T, double>::value ? (T*)c->t64a : (T*)c->t32a;
   T* tb = std::is_same<T, double>::value ? (T*)c->t64b : (T*)c->t32b;
-  chebyshev<T>(c, l, b, x, d, t);
-  apply_op<T>(c, l, MODE_APPLY, x, r, b);
+  chebyshev<T>(c, l, b, x, zA, zB, d, t);
+  op_resid<T>(c, l, b, x, r, (T*)nullptr, (T*)nullptr);
   transfer<T>(c, l, 1, r, (T*)c->lv[l - 1].w[WB], false, ta, tb);
   vcycle_rec<T>(c, l - 1);
   transfer<T>(c, l, 0, (const T*)c->lv[l - 1].w[WX], x, true, ta, tb);
-  apply_op<T>(c, l, MODE_APPLY, x, r, b);
-  chebyshev<T>(c, l, r, z, d, t);
-  k_axpy<T>(x, T(1), z, L.n, c->s);
-  LAUNCHCHK();
+  post_smooth<T>(c, l, b, x, r, zA, zB, d, t);
+}
+
+void vcycle_body(mfpff_ctx* c) {
+  if (c->f32) vcycle_rec<float>(c, c->L);
+  else vcycle_rec<double>(c, c->L);
+}
+
+// Record the V-cycle (finest WB -> WX) into a graph on a private stream.  The
+// launches only read level buffers, tables and coefficients that stay fixed
+// until the next linearisation.  Any failure leaves the direct launch path.
+void capture_vcycle(mfpff_ctx* c) {
+  if (c->vgraph) {
+    hipGraphExecDestroy(c->vgraph);
+    c->vgraph = nullptr;
+  }
+  if (!c->graph_ok) return;
+  if (!c->cap_s && hipStreamCreateWithFlags(&c->cap_s, hipStreamNonBlocking) != hipSuccess) {
+    c->graph_ok = false;
+    return;
+  }
+  hipStream_t user = c->s;
+  hipGraph_t g = nullptr;
+  if (hipStreamBeginCapture(c->cap_s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    c->graph_ok = false;
+    return;
+  }
+  c->s = c->cap_s;
+  bool ok = true;
+  try {
+    vcycle_body(c);
+  } catch (...) {
+    ok = false;
+  }
+  c->s = user;
+  if (hipStreamEndCapture(c->cap_s, &g) != hipSuccess || !g) ok = false;
+  if (ok && hipGraphInstantiate(&c->vgraph, g, nullptr, nullptr, 0) != hipSuccess) {
+    c->vgraph = nullptr;
+    ok = false;
+  }
+  if (g) hipGraphDestroy(g);
+  (void)hipGetLastError();
+  if (!ok) {
+    c->graph_ok = false;
+    c->vgraph = nullptr;
+  }
 }
 
 // z = V(r) on the finest level, FP64 in/out
 void precondition(mfpff_ctx* c, const double* r, double* z) {
   Level& F = c->lv[c->L];
-  if (c->f32) {
-    k_cast_d2f((float*)F.w[WB], r, F.n, c->s);
-    vcycle_rec<float>(c, c->L);
-    k_cast_f2d(z, (const float*)F.w[WX], F.n, c->s);
-  } else {
-    k_copy<double>((double*)F.w[WB], r, F.n, c->s);
-    vcycle_rec<double>(c, c->L);
-    k_copy<double>(z, (const double*)F.w[WX], F.n, c->s);
-  }
+  if (c->f32) k_cast_d2f((float*)F.w[WB], r, F.n, c->s);
+  else k_copy<double>((double*)F.w[WB], r, F.n, c->s);
+  LAUNCHCHK();
+  if (c->vgraph) HIPCHK(hipGraphLaunch(c->vgraph, c->s));
+  else vcycle_body(c);
+  if (c->f32) k_cast_f2d(z, (const float*)F.w[WX], F.n, c->s);
+  else k_copy<double>(z, (const double*)F.w[WX], F.n, c->s);
   LAUNCHCHK();
 }
 
@@ -665,6 +780,7 @@ void set_linearization(mfpff_ctx* c, const double* u, const double* phi, const d
     }
     cheb_coefficients(c, L);
   }
+  capture_vcycle(c);
   c->linearized = true;
 }
 
@@ -716,6 +832,7 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
   c->dim = p.dim;
   c->L = p.n_levels - 1;
   c->f32 = p.vcycle_prec == MFPFF_F32;
+  if (const char* ev = getenv("MFPFF_NO_GRAPH")) c->graph_ok = !(ev[0] == '1');
   mfpff_status st = run(c, [&]() -> mfpff_status {
     const int d = c->dim;
     c->lv.resize(p.n_levels);
@@ -733,7 +850,7 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
         L.dinv32 = dalloc<float>(L.n);
       }
       const size_t es = c->f32 ? sizeof(float) : sizeof(double);
-      for (int w = 0; w < 6; ++w) {
+      for (int w = 0; w < NW; ++w) {
         void* ptr = nullptr;
         if (hipMalloc(&ptr, (size_t)L.n * es) != hipSuccess) throw StatusError{MFPFF_ERR_OOM, "device allocation failed"};
         L.w[w] = ptr;
@@ -757,6 +874,7 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
             tf.C[i][j] = (float)t.C[i][j];
           }
         }
+        c->tabh[k] = t;
         c->tab64[k] = dalloc<Tables<double>>(1);
         c->tab32[k] = dalloc<Tables<float>>(1);
         HIPCHK(hipMemcpy(c->tab64[k], &t, sizeof(t), hipMemcpyHostToDevice));
@@ -855,6 +973,8 @@ void mfpff_destroy(mfpff_ctx* c) {
   for (void* p : ps) F(p);
   for (int i = 0; i < 5; ++i) F(c->s64[i]);
   if (c->hhost) hipHostFree(c->hhost);
+  if (c->vgraph) hipGraphExecDestroy(c->vgraph);
+  if (c->cap_s) hipStreamDestroy(c->cap_s);
   delete c;
 }
 
@@ -935,7 +1055,7 @@ mfpff_status mfpff_smooth(mfpff_ctx* c, int level, const double* r, double* z) {
     require_ptr(r, "r");
     require_ptr(z, "z");
     if (r == z) throw StatusError{MFPFF_ERR_ARG, "r and z alias"};
-    chebyshev<double>(c, level, r, z, c->s64[0], c->s64[1]);
+    chebyshev<double>(c, level, r, z, c->s64[0], c->s64[1], c->s64[2], c->s64[3]);
     return MFPFF_OK;
   });
 }

@@ -65,6 +65,30 @@ struct CellArgs {
   long long ld;        // ELEM: leading dimension
 };
 
+// Fused vector epilogues of the owner-computes kernels (tile_kernel.hip)
+enum EpiKind : int { EPI_APPLY = 0, EPI_RESID = 1, EPI_CHEB = 2 };
+template <typename T>
+struct Epilogue {
+  T* y;                 // apply: y; resid: r; cheb: new iterate z'
+  const T* b;           // resid: right-hand side
+  T* z0;                // resid: optional Chebyshev start z = D^-1 r / theta
+  T* d0;                //        and d = z
+  const T* dinv;        // inverse diagonal
+  T ith_u, ith_p;       // 1/theta per block
+  const T* r;           // cheb: smoother right-hand side
+  T* d;                 // cheb: direction, updated in place
+  T c1u, c2u, c1p, c2p; // cheb: d = c1 d + c2 D^-1 (r - t)
+  const T* xacc;        // cheb: optional xout = xacc + z'
+  T* xout;
+};
+template <typename T>
+hipError_t launch_tile_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<T>* tab, hipStream_t s);
+long long tile_blocks_2d(const Geom& g);
+template <typename T>
+hipError_t launch_regcell_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<double>& t64,
+                             hipStream_t s);
+long long regcell_blocks_2d(const Geom& g);
+
 // ---- launchers (cell_kernel.hip)
 template <typename T>
 hipError_t launch_cell(int mode, const CellArgs<T>& a, const Tables<T>* tab_dev, hipStream_t s);
@@ -88,6 +112,9 @@ void k_cheb_init(T* z, T* d, const T* r, const T* dinv, long long nn, int dim, T
 template <typename T>
 void k_cheb_step(T* z, T* d, const T* r, const T* t, const T* dinv, long long nn, int dim,
                  T c1u, T c2u, T c1p, T c2p, hipStream_t s);
+template <typename T>
+void k_cheb_update(T* zout, T* d, const T* zin, const T* r, const T* t, const T* dinv, long long nn, int dim,
+                   T c1u, T c2u, T c1p, T c2p, const T* xacc, T* xout, hipStream_t s);
 void k_cast_d2f(float* y, const double* x, long long n, hipStream_t s);
 void k_cast_f2d(double* y, const float* x, long long n, hipStream_t s);
 void k_mask_vec(double* y, const uint8_t* mask, long long nn, int dim, double scale, hipStream_t s);
@@ -131,9 +158,15 @@ struct Sparse1D {
   const double* val;        // n_out*width
   const float* valf;
 };
+// in_mask: zero inputs at fixed dofs (input must be a whole level vector);
+// out_mask: zero outputs at fixed dofs (output must be a whole level vector)
 template <typename T>
 void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, const long long* dims_in,
-                  int ncomp, hipStream_t s);
+                  int ncomp, const uint8_t* in_mask, const uint8_t* out_mask, hipStream_t s);
+// out (fine level) = / += P~ xc: single pass, (kc+1)^d coarse terms per fine node
+template <typename T>
+void k_prolong(T* out, const T* xc, const Sparse1D& P, const uint8_t* mask_c, const uint8_t* mask_f, const Geom& gf,
+               const Geom& gc, bool add, hipStream_t s);
 template <typename T>
 void k_mask_comp(T* y, const uint8_t* mask, long long nn, int dim, hipStream_t s);
 template <typename T>

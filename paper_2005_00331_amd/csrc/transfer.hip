@@ -13,9 +13,15 @@ struct Dims3 {
   long long n[3];
 };
 
+__device__ __forceinline__ bool comp_fixed(const uint8_t* mask, long long node, long long comp, int dim) {
+  const uint8_t m = mask[node];
+  return comp < dim ? (m & kMaskU) : (m & kMaskPhi);
+}
+
 template <typename T>
 __global__ void axis_apply_kernel(T* out, const T* in, const int* col, const double* val, const float* valf, int width,
-                                  int axis, int dim, Dims3 din, int nout_axis, int ncomp) {
+                                  int axis, int dim, Dims3 din, int nout_axis, int ncomp, const uint8_t* in_mask,
+                                  const uint8_t* out_mask) {
   long long nin[3] = {din.n[0], din.n[1], din.n[2]};
   long long no[3] = {nin[0], nin[1], nin[2]};
   no[axis] = nout_axis;
@@ -39,18 +45,23 @@ __global__ void axis_apply_kernel(T* out, const T* in, const int* col, const dou
       if (a != axis) base += o[a] * sin[a];
     const int row = (int)o[axis];
     T acc = 0;
-    for (int j = 0; j < width; ++j) {
-      const int ci = col[row * width + j];
-      if (ci < 0) break;
-      const T w = sizeof(T) == 8 ? (T)val[row * width + j] : (T)valf[row * width + j];
-      acc += w * in[base + (long long)ci * sin[axis]];
+    if (!(out_mask && comp_fixed(out_mask, (idx - comp * per_out), comp, dim))) {
+      for (int j = 0; j < width; ++j) {
+        const int ci = col[row * width + j];
+        if (ci < 0) break;
+        const T w = sizeof(T) == 8 ? (T)val[row * width + j] : (T)valf[row * width + j];
+        const long long ii = base + (long long)ci * sin[axis];
+        if (in_mask && comp_fixed(in_mask, ii - comp * per_in, comp, dim)) continue;
+        acc += w * in[ii];
+      }
     }
     out[idx] = acc;
   }
 }
 
 template <typename T>
-void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, const long long* dims_in, int ncomp, hipStream_t s) {
+void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, const long long* dims_in, int ncomp,
+                  const uint8_t* in_mask, const uint8_t* out_mask, hipStream_t s) {
   Dims3 d{{dims_in[0], dims_in[1], dim == 3 ? dims_in[2] : 1}};
   long long total = ncomp;
   for (int a = 0; a < dim; ++a) total *= (a == axis ? A.n_out : d.n[a]);
@@ -58,7 +69,69 @@ void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, con
   if (nb > 65536) nb = 65536;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(axis_apply_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, out, in, A.col, A.val, A.valf, A.width,
-                     axis, dim, d, A.n_out, ncomp);
+                     axis, dim, d, A.n_out, ncomp, in_mask, out_mask);
+}
+
+// out = / += P~ xc on the fine level: gather of (kc+1)^d coarse values per fine node
+template <typename T>
+__global__ void prolong_kernel(T* out, const T* xc, const int* col, const double* val, const float* valf, int width,
+                               const uint8_t* mask_c, const uint8_t* mask_f, Geom gf, Geom gc, int add) {
+  const long long nnf = gf.n_nodes, nnc = gc.n_nodes;
+  const int dim = gf.dim;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nnf; i += (long long)gridDim.x * blockDim.x) {
+    int f[3] = {0, 0, 0};
+    long long rem = i;
+    for (int a = 0; a < dim; ++a) {
+      f[a] = (int)(rem % gf.M);
+      rem /= gf.M;
+    }
+    T v[4] = {T(0), T(0), T(0), T(0)};
+    const int w2 = dim == 3 ? width : 1;
+    for (int j2 = 0; j2 < w2; ++j2) {
+      int c2 = 0;
+      T wz = T(1);
+      if (dim == 3) {
+        c2 = col[f[2] * width + j2];
+        if (c2 < 0) break;
+        wz = sizeof(T) == 8 ? (T)val[f[2] * width + j2] : (T)valf[f[2] * width + j2];
+      }
+      for (int j1 = 0; j1 < width; ++j1) {
+        const int c1 = col[f[1] * width + j1];
+        if (c1 < 0) break;
+        const T wy = wz * (sizeof(T) == 8 ? (T)val[f[1] * width + j1] : (T)valf[f[1] * width + j1]);
+        for (int j0 = 0; j0 < width; ++j0) {
+          const int c0 = col[f[0] * width + j0];
+          if (c0 < 0) break;
+          const T w = wy * (sizeof(T) == 8 ? (T)val[f[0] * width + j0] : (T)valf[f[0] * width + j0]);
+          const long long nc = c0 + (long long)gc.M * (c1 + (long long)gc.M * c2);
+          const uint8_t mc = mask_c[nc];
+          for (int cc = 0; cc <= dim; ++cc) {
+            const bool fx = cc < dim ? (mc & kMaskU) : (mc & kMaskPhi);
+            if (!fx) v[cc] += w * xc[cc * nnc + nc];
+          }
+        }
+      }
+    }
+    const uint8_t mf = mask_f[i];
+    for (int cc = 0; cc <= dim; ++cc) {
+      const bool fx = cc < dim ? (mf & kMaskU) : (mf & kMaskPhi);
+      const long long idx = cc * nnf + i;
+      if (add) {
+        if (!fx) out[idx] += v[cc];
+      } else {
+        out[idx] = fx ? T(0) : v[cc];
+      }
+    }
+  }
+}
+
+template <typename T>
+void k_prolong(T* out, const T* xc, const Sparse1D& P, const uint8_t* mask_c, const uint8_t* mask_f, const Geom& gf,
+               const Geom& gc, bool add, hipStream_t s) {
+  long long nb = (gf.n_nodes + kThreads - 1) / kThreads;
+  if (nb > 65536) nb = 65536;
+  hipLaunchKernelGGL(prolong_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, out, xc, P.col, P.val, P.valf, P.width,
+                     mask_c, mask_f, gf, gc, add ? 1 : 0);
 }
 
 // zero the fixed dofs of a level vector
@@ -96,8 +169,14 @@ void k_add_masked(T* y, const T* x, const uint8_t* mask, long long nn, int dim, 
   hipLaunchKernelGGL(add_masked_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, y, x, mask, nn, dim);
 }
 
-template void k_axis_apply<double>(double*, const double*, const Sparse1D&, int, int, const long long*, int, hipStream_t);
-template void k_axis_apply<float>(float*, const float*, const Sparse1D&, int, int, const long long*, int, hipStream_t);
+template void k_axis_apply<double>(double*, const double*, const Sparse1D&, int, int, const long long*, int, const uint8_t*,
+                                   const uint8_t*, hipStream_t);
+template void k_axis_apply<float>(float*, const float*, const Sparse1D&, int, int, const long long*, int, const uint8_t*,
+                                  const uint8_t*, hipStream_t);
+template void k_prolong<double>(double*, const double*, const Sparse1D&, const uint8_t*, const uint8_t*, const Geom&,
+                                const Geom&, bool, hipStream_t);
+template void k_prolong<float>(float*, const float*, const Sparse1D&, const uint8_t*, const uint8_t*, const Geom&, const Geom&,
+                               bool, hipStream_t);
 template void k_mask_comp<double>(double*, const uint8_t*, long long, int, hipStream_t);
 template void k_mask_comp<float>(float*, const uint8_t*, long long, int, hipStream_t);
 template void k_add_masked<double>(double*, const double*, const uint8_t*, long long, int, hipStream_t);

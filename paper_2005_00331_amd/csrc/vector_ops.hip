@@ -107,6 +107,28 @@ void k_cheb_step(T* z, T* d, const T* r, const T* t, const T* dinv, long long nn
                      c1u, c2u, c1p, c2p);
 }
 
+// one Chebyshev step after t = A_blk z: d = c1 d + c2 D^-1 (r - t); z' = z + d; optional x' = x + z'
+template <typename T>
+__global__ void cheb_update_kernel(T* zout, T* d, const T* zin, const T* r, const T* t, const T* dinv, long long nn, int dim,
+                                   T c1u, T c2u, T c1p, T c2p, const T* xacc, T* xout) {
+  const long long n = (long long)(dim + 1) * nn;
+  const long long nu = (long long)dim * nn;
+  GSTRIDE(i, n) {
+    const bool isu = i < nu;
+    const T dn = (isu ? c1u : c1p) * d[i] + (isu ? c2u : c2p) * dinv[i] * (r[i] - t[i]);
+    d[i] = dn;
+    const T zn = zin[i] + dn;
+    zout[i] = zn;
+    if (xout) xout[i] = xacc[i] + zn;
+  }
+}
+template <typename T>
+void k_cheb_update(T* zout, T* d, const T* zin, const T* r, const T* t, const T* dinv, long long nn, int dim, T c1u, T c2u,
+                   T c1p, T c2p, const T* xacc, T* xout, hipStream_t s) {
+  hipLaunchKernelGGL(cheb_update_kernel<T>, dim3(grid_for((dim + 1) * nn)), dim3(kThreads), 0, s, zout, d, zin, r, t, dinv, nn,
+                     dim, c1u, c2u, c1p, c2p, xacc, xout);
+}
+
 __global__ void d2f_kernel(float* y, const double* x, long long n) { GSTRIDE(i, n) y[i] = (float)x[i]; }
 __global__ void f2d_kernel(double* y, const float* x, long long n) { GSTRIDE(i, n) y[i] = (double)x[i]; }
 void k_cast_d2f(float* y, const double* x, long long n, hipStream_t s) {
@@ -479,7 +501,9 @@ void k_lanczos_update_p(double* p, const double* z, const LanczosState* st, long
   template void k_axpy<T>(T*, T, const T*, long long, hipStream_t);                                                \
   template void k_diag_finish<T>(T*, double*, const T*, const uint8_t*, long long, int, hipStream_t);              \
   template void k_cheb_init<T>(T*, T*, const T*, const T*, long long, int, T, T, hipStream_t);                     \
-  template void k_cheb_step<T>(T*, T*, const T*, const T*, const T*, long long, int, T, T, T, T, hipStream_t);
+  template void k_cheb_step<T>(T*, T*, const T*, const T*, const T*, long long, int, T, T, T, T, hipStream_t);     \
+  template void k_cheb_update<T>(T*, T*, const T*, const T*, const T*, const T*, long long, int, T, T, T, T,      \
+                                 const T*, T*, hipStream_t);
 INST(double)
 INST(float)
 #undef INST

@@ -33,6 +33,24 @@ def ctx_for(name):
 NAMES = [n for n in CASES if not n.endswith("f32")]
 
 
+@pytest.mark.parametrize("name", ["2d_q2", "3d_q2"])
+def test_accumulate_flag_is_masked_product_without_identity(name):
+    # y += P G P x on free rows, y left alone elsewhere
+    from paper_2005_00331_amd import OP_ACCUMULATE, OP_G
+    cfg, levels, inp, H = oracle_case(name)
+    ctx = ctx_for(name)
+    lev = H.levels[-1]
+    x = np.random.default_rng(12).standard_normal(lev.mesh.n_dofs)
+    y0 = np.random.default_rng(13).standard_normal(lev.mesh.n_dofs)
+    say(name, "accumulate")
+    import torch
+    y = dev(y0)
+    ctx.apply_jacobian(-1, dev(x), y, op=OP_G | OP_ACCUMULATE)
+    p = lev.pvec
+    ref = y0 + p * (lev.G @ (p * x))
+    assert rel_err(host(y), ref) <= 1e-12
+
+
 @pytest.mark.parametrize("name", NAMES)
 def test_operator_products_every_level(name):
     cfg, levels, inp, H = oracle_case(name)
@@ -102,10 +120,10 @@ def test_coarse_solve_and_vcycle(name):
     assert e <= 1e-10, (name, e)
 
 
-def test_fp32_level_products():
+@pytest.mark.parametrize("name", ["3d_q2_f32", "2d_q2_f32"])
+def test_fp32_level_products(name):
     import torch
     from paper_2005_00331_amd import F32, OP_BLOCKDIAG, OP_G
-    name = "3d_q2_f32"
     cfg, levels, inp, H = oracle_case(name)
     ctx = ctx_for(name)
     rng = np.random.default_rng(11)
