@@ -119,17 +119,31 @@ void mfpff_destroy(mfpff_ctx* ctx);
 /* Message describing the last failure on this context ("" if none). */
 const char* mfpff_last_error(const mfpff_ctx* ctx);
 
-/* Sizes and smoother data of one level. Synchronises. */
+/* Sizes and smoother data of one level (synchronises).  Before any
+ * linearisation lambda_u = lambda_phi = 1 and the step counts are 0. */
 mfpff_status mfpff_level_info(mfpff_ctx* ctx, int level, mfpff_level_desc* out);
 
 /* Freeze the linearisation point of eq. (G): u (dim*n_nodes), phi, phi_old
  * and phi_tilde (n_nodes each; phi_tilde NULL means phi_old) and the active
  * set (n_nodes bytes) on the finest level.  Injects fields and masks to every
  * coarser level, builds the diagonals, the Chebyshev intervals (CG-Lanczos
- * estimates) and the factorised coarse blocks. */
+ * estimates) and the factorised coarse blocks.  Fails with MFPFF_ERR_NUMERIC
+ * when an input field holds a non-finite value or a coarse block is not
+ * positive definite, and with MFPFF_ERR_ARG when the coarsest level has more
+ * than 16384 dofs (its dense factorisation is allocated on first use). */
 mfpff_status mfpff_set_linearization(mfpff_ctx* ctx, const double* u, const double* phi,
                                      const double* phi_old, const uint8_t* active,
                                      const double* phi_tilde);
+
+/* Product-only linearisation: the same fields, active set and Dirichlet rows
+ * as mfpff_set_linearization, injected to every level, but no diagonals,
+ * smoother intervals or coarse factorisation.  Enough for
+ * mfpff_apply_jacobian (any op) on every level; mfpff_vcycle, mfpff_smooth,
+ * mfpff_diagonal, mfpff_coarse_solve and mfpff_gmres_solve still need
+ * mfpff_set_linearization (MFPFF_ERR_STATE otherwise).  Used by the backward
+ * of the residual, where only the transposed product is needed. */
+mfpff_status mfpff_set_point(mfpff_ctx* ctx, const double* u, const double* phi, const double* phi_old,
+                             const uint8_t* active, const double* phi_tilde);
 
 /* y = op(G^_level) x on one level.  x, y: n_dofs of that level, FP64 or FP32
  * per `prec` (FP32 uses the FP32 copy of the level data).  x and y must not

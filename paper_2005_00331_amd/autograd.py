@@ -5,8 +5,8 @@ replaces phi in the degradation of the displacement equation, Section
 3.2).  Backward, written by hand: the transposed Jacobian of eq. (G)
 applied to the cotangent (unconstrained, since the residual itself has no
 constraints) and the two parameter cotangents <v, dR/dGc>, <v, dR/deps>.
-The context must be created without Dirichlet rows and linearised with an
-empty active set, so that its operator is the plain Jacobian.
+The context must be created without Dirichlet rows; the backward sets its
+point with an empty active set, so that its operator is the plain Jacobian.
 """
 import torch
 
@@ -32,7 +32,7 @@ class ResidualFn(torch.autograd.Function):
         s = ctx.solver
         v = v.contiguous()
         zeros = torch.zeros(s.n_nodes, dtype=torch.uint8, device=u.device)
-        s.set_linearization(u, phi, phi, zeros, phit)
+        s.set_point(u, phi, phi, zeros, phit)
         gT = s.apply_jacobian(-1, v, prec=F64, op=OP_GT)
         dGc, deps = s.residual_param_vjp(u, phi, phit, v)
         nu = s.dim * s.n_nodes

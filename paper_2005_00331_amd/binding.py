@@ -81,6 +81,7 @@ class LevelDesc(ctypes.Structure):
 
 EXPORTS = [
     "mfpff_create", "mfpff_destroy", "mfpff_last_error", "mfpff_level_info", "mfpff_set_linearization",
+    "mfpff_set_point",
     "mfpff_apply_jacobian", "mfpff_diagonal", "mfpff_smooth", "mfpff_transfer", "mfpff_coarse_solve",
     "mfpff_vcycle", "mfpff_gmres_solve", "mfpff_residual", "mfpff_residual_param_vjp", "mfpff_active_set",
     "mfpff_newton_step",
@@ -104,6 +105,7 @@ def load_library(path=LIB_PATH):
         "mfpff_last_error": ([VP], ctypes.c_char_p),
         "mfpff_level_info": ([VP, I, ctypes.POINTER(LevelDesc)], I),
         "mfpff_set_linearization": ([VP, P, P, P, P, P], I),
+        "mfpff_set_point": ([VP, P, P, P, P, P], I),
         "mfpff_apply_jacobian": ([VP, I, P, P, I, I], I),
         "mfpff_diagonal": ([VP, I, P], I),
         "mfpff_smooth": ([VP, I, P, P], I),
@@ -212,6 +214,13 @@ class Context:
             _ptr(phi_old, torch.float64, nn, "phi_old"), _ptr(active, torch.uint8, nn, "active"),
             _ptr(phi_tilde, torch.float64, nn, "phi_tilde", allow_none=True)))
         self.levels = [self.level_info(l) for l in range(len(self.levels))]
+
+    def set_point(self, u, phi, phi_old, active, phi_tilde=None):
+        nn = self.n_nodes
+        self._check(self.lib.mfpff_set_point(
+            self.h, _ptr(u, torch.float64, self.dim * nn, "u"), _ptr(phi, torch.float64, nn, "phi"),
+            _ptr(phi_old, torch.float64, nn, "phi_old"), _ptr(active, torch.uint8, nn, "active"),
+            _ptr(phi_tilde, torch.float64, nn, "phi_tilde", allow_none=True)))
 
     def apply_jacobian(self, level, x, y=None, prec=F64, op=OP_G):
         lv = self._lvl(level)

@@ -134,7 +134,10 @@ struct mfpff_ctx {
   double* dU = nullptr;
   double* pvjp_part = nullptr;
   double* pvjp_out = nullptr;
-  bool linearized = false;
+  bool linearized = false;  // full linearisation (smoothers, coarse solve)
+  bool has_point = false;   // fields and masks injected (products allowed)
+  double* finite_flag = nullptr;
+  double hhost_scalar = 0.0;
   // V-cycle captured as a graph after each linearisation (replayed per GMRES iteration)
   hipStream_t cap_s = nullptr;
   hipGraphExec_t vgraph = nullptr;
@@ -577,7 +580,29 @@ void lanczos_level(mfpff_ctx* c, int l) {
   LAUNCHCHK();
 }
 
+constexpr long long kMaxCoarseDofs = 16384;
+
+void coarse_alloc(mfpff_ctx* c) {
+  if (c->dense) return;
+  Level& C = c->lv[0];
+  if (C.n > kMaxCoarseDofs)
+    throw StatusError{MFPFF_ERR_ARG, "coarsest level too large for the dense coarse solve (more than 16384 dofs)"};
+  const size_t n0 = (size_t)C.n;
+  c->dense = dalloc<double>(n0 * n0);
+  c->Auu = dalloc<double>((size_t)c->nu0 * c->nu0);
+  c->App = dalloc<double>((size_t)c->np0 * c->np0);
+  c->Wu = dalloc<double>((size_t)c->nu0 * c->nu0);
+  c->WuT = dalloc<double>((size_t)c->nu0 * c->nu0);
+  c->Wp = dalloc<double>((size_t)c->np0 * c->np0);
+  c->WpT = dalloc<double>((size_t)c->np0 * c->np0);
+  c->Gpu = dalloc<double>((size_t)c->np0 * c->nu0);
+  c->cs_in = dalloc<double>(n0);
+  c->cs_out = dalloc<double>(n0);
+  c->cs_t = dalloc<double>(n0);
+}
+
 void coarse_setup(mfpff_ctx* c) {
+  coarse_alloc(c);
   Level& C = c->lv[0];
   const long long n = C.n;
   HIPCHK(hipMemsetAsync(c->dense, 0, (size_t)n * n * sizeof(double), c->s));
@@ -602,6 +627,9 @@ void coarse_setup(mfpff_ctx* c) {
 
 void require_state(mfpff_ctx* c) {
   if (!c->linearized) throw StatusError{MFPFF_ERR_STATE, "set_linearization has not been called"};
+}
+void require_point(mfpff_ctx* c) {
+  if (!c->has_point) throw StatusError{MFPFF_ERR_STATE, "neither set_point nor set_linearization has been called"};
 }
 void require_level(mfpff_ctx* c, int l) {
   if (l < 0 || l > c->L) throw StatusError{MFPFF_ERR_ARG, "level index out of range"};
@@ -733,10 +761,13 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
   return conv ? MFPFF_OK : MFPFF_ERR_NOCONV;
 }
 
-void set_linearization(mfpff_ctx* c, const double* u, const double* phi, const double* phi_old, const uint8_t* active,
-                       const double* phit) {
+// fields and masks on every level (FP32 copies too); checks the inputs are finite
+void set_point(mfpff_ctx* c, const double* u, const double* phi, const double* phi_old, const uint8_t* active,
+               const double* phit) {
   const int d = c->dim;
   Level& F = c->lv[c->L];
+  c->has_point = false;
+  c->linearized = false;
   k_fine_fields(F.lin, F.mask, u, phi, phit ? phit : phi_old, active, F.g, c->prob.dirichlet, c->s);
   LAUNCHCHK();
   for (int l = c->L - 1; l >= 0; --l) {
@@ -744,9 +775,27 @@ void set_linearization(mfpff_ctx* c, const double* u, const double* phi, const d
              c->prob.dirichlet, c->s);
     LAUNCHCHK();
   }
+  if (c->f32)
+    for (int l = 0; l <= c->L; ++l) k_cast_d2f(c->lv[l].lin32, c->lv[l].lin, (long long)(d + 2) * c->lv[l].nn, c->s);
+  // finite check of the finest fields: sum of squares is finite unless some entry is inf or nan
+  const long long nf = (long long)(d + 2) * F.nn;
+  const int nb = dot_blocks(nf);
+  k_multidot_partials(c->part, F.lin, nf, 1, F.lin, nf, c->s);
+  k_multidot_finish(c->finite_flag, c->part, nb, 1, c->s);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(&c->hhost_scalar, c->finite_flag, sizeof(double), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  const double fl = c->hhost_scalar;
+  if (!std::isfinite(fl)) throw StatusError{MFPFF_ERR_NUMERIC, "non-finite value in u, phi or phi_tilde"};
+  c->has_point = true;
+}
+
+void set_linearization(mfpff_ctx* c, const double* u, const double* phi, const double* phi_old, const uint8_t* active,
+                       const double* phit) {
+  const int d = c->dim;
+  set_point(c, u, phi, phi_old, active, phit);
   for (int l = 0; l <= c->L; ++l) {
     Level& L = c->lv[l];
-    if (c->f32) k_cast_d2f(L.lin32, L.lin, (long long)(d + 2) * L.nn, c->s);
     // diagonal
     double* tmp = c->s64[0];
     k_fill<double>(tmp, 0.0, L.n, c->s);
@@ -894,24 +943,13 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
     c->part = dalloc<double>(c->part_len);
     c->lst = dalloc<LanczosState>(c->L + 1);
     HIPCHK(hipMemset(c->lst, 0, (c->L + 1) * sizeof(LanczosState)));
-    // coarse storage
+    // coarse sizes (storage is allocated by the first full linearisation)
     Level& C = c->lv[0];
     c->nu0 = (int)(d * C.nn);
     c->np0 = (int)C.nn;
-    const size_t n0 = (size_t)C.n;
-    c->dense = dalloc<double>(n0 * n0);
-    c->Auu = dalloc<double>((size_t)c->nu0 * c->nu0);
-    c->App = dalloc<double>((size_t)c->np0 * c->np0);
-    c->Wu = dalloc<double>((size_t)c->nu0 * c->nu0);
-    c->WuT = dalloc<double>((size_t)c->nu0 * c->nu0);
-    c->Wp = dalloc<double>((size_t)c->np0 * c->np0);
-    c->WpT = dalloc<double>((size_t)c->np0 * c->np0);
-    c->Gpu = dalloc<double>((size_t)c->np0 * c->nu0);
-    c->cs_in = dalloc<double>(n0);
-    c->cs_out = dalloc<double>(n0);
-    c->cs_t = dalloc<double>(n0);
     c->info_dev = dalloc<int>(2);
     c->chol_scratch = dalloc<double>(32 * 32);
+    c->finite_flag = dalloc<double>(1);
     // lumped mass on the finest level: integrals of the 1D basis functions
     Tables<double> t{};
     make_tables(F.g.k, t);
@@ -967,7 +1005,7 @@ void mfpff_destroy(mfpff_ctx* c) {
     F(c->tab64[k]);
     F(c->tab32[k]);
   }
-  void* ps[] = {c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
+  void* ps[] = {c->finite_flag, c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
                 c->WpT, c->Gpu, c->cs_in, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lst, c->part, c->V,
                 c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out};
   for (void* p : ps) F(p);
@@ -1004,15 +1042,26 @@ mfpff_status mfpff_set_linearization(mfpff_ctx* c, const double* u, const double
     require_ptr(phi, "phi");
     require_ptr(phi_old, "phi_old");
     require_ptr(active, "active");
-    c->linearized = false;
     set_linearization(c, u, phi, phi_old, active, phi_tilde);
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_set_point(mfpff_ctx* c, const double* u, const double* phi, const double* phi_old,
+                             const uint8_t* active, const double* phi_tilde) {
+  return run(c, [&]() {
+    require_ptr(u, "u");
+    require_ptr(phi, "phi");
+    require_ptr(phi_old, "phi_old");
+    require_ptr(active, "active");
+    set_point(c, u, phi, phi_old, active, phi_tilde);
     return MFPFF_OK;
   });
 }
 
 mfpff_status mfpff_apply_jacobian(mfpff_ctx* c, int level, const void* x, void* y, int prec, int op) {
   return run(c, [&]() {
-    require_state(c);
+    require_point(c);
     require_level(c, level);
     require_ptr(x, "x");
     require_ptr(y, "y");
