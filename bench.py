@@ -138,7 +138,12 @@ def main():
     ctx, levels, state = build_context(cfg)
     if args.apply_only:
         zeros = torch.zeros(ctx.n_nodes, dtype=torch.uint8, device="cuda")
-        ctx.set_linearization(state["u"], state["phi"], state["phi_old"], zeros, state["phi_tilde"])
+        ctx.set_point(state["u"], state["phi"], state["phi_old"], zeros, state["phi_tilde"])
+        # calibration for the traffic counters: one plain device copy of 64 MiB
+        src = torch.ones(8 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
         t_apply = time_apply(ctx)
         byts = algorithmic_bytes_per_apply(cfg.dim, ctx.n_nodes, 8)
         print(json.dumps({"apply_us": t_apply * 1e6, "GB/s": byts / t_apply / 1e9, "bytes_per_launch": byts}), flush=True)
@@ -187,7 +192,7 @@ def main():
                    "levels": levels, "n_dofs": ctx.n_dofs, "vcycle_prec": cfg.vcycle_prec},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": ((f"regcell_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>" if cfg.k <= 2 else
+                     "kernel": ((f"rowcell_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>" if cfg.k <= 2 else
                                  f"tile_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>") if cfg.dim == 2 else
                                 f"cell_kernel<{cfg.dim},{cfg.k},double,APPLY>") + " on the finest level",
                      "bytes_per_launch": byts},

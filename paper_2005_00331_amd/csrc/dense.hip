@@ -260,21 +260,33 @@ void k_transpose(double* At, const double* A, int n, hipStream_t s) {
 }
 
 // y = alpha * A x + yin  (one wave per row)
+// one wave per row, four independent partial sums per lane (loads in flight)
 __global__ void gemv_kernel(double* y, const double* A, long long lda, const double* x, int rows, int cols, double alpha,
-                            const double* yin) {
+                            const double* yin, int shape) {
   const int lane = threadIdx.x & 63;
   const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
   if (row >= rows) return;
+  const int j0 = shape == GEMV_UPPER ? row : 0;
+  const int j1 = shape == GEMV_LOWER ? row + 1 : cols;
   const double* a = A + (long long)row * lda;
-  double acc = 0;
-  for (int j = lane; j < cols; j += 64) acc += a[j] * x[j];
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int j = j0 + lane;
+  for (; j + 192 < j1; j += 256) {
+    s0 += a[j] * x[j];
+    s1 += a[j + 64] * x[j + 64];
+    s2 += a[j + 128] * x[j + 128];
+    s3 += a[j + 192] * x[j + 192];
+  }
+  for (; j < j1; j += 64) s0 += a[j] * x[j];
+  double acc = (s0 + s1) + (s2 + s3);
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
   if (lane == 0) y[row] = alpha * acc + (yin ? yin[row] : 0.0);
 }
 void k_gemv(double* y, const double* A, long long lda, const double* x, int rows, int cols, double alpha, const double* yin,
-            hipStream_t s) {
+            int shape, hipStream_t s) {
   const int rpb = kThreads / 64;
-  hipLaunchKernelGGL(gemv_kernel, dim3((rows + rpb - 1) / rpb), dim3(kThreads), 0, s, y, A, lda, x, rows, cols, alpha, yin);
+  hipLaunchKernelGGL(gemv_kernel, dim3((rows + rpb - 1) / rpb), dim3(kThreads), 0, s, y, A, lda, x, rows, cols, alpha, yin,
+                     shape);
 }
 
 }  // namespace mfpff

@@ -128,6 +128,7 @@ struct mfpff_ctx {
   double* hdev = nullptr;
   double* hhost = nullptr;
   double* ycoef = nullptr;
+  unsigned* ticket = nullptr;  // arrival counter of the single-launch reductions (kept at zero between launches)
   // Newton
   double* R = nullptr;
   double* b = nullptr;
@@ -284,10 +285,10 @@ const Tables<double>* tab<double>(mfpff_ctx* c, int k) { return c->tab64[k]; }
 template <>
 const Tables<float>* tab<float>(mfpff_ctx* c, int k) { return c->tab32[k]; }
 
-// 2D owner-computes launch: register-resident kernel for Q1/Q2, LDS tile kernel otherwise
+// 2D owner-computes launch: row-shared cell kernel for Q1/Q2, LDS tile kernel otherwise
 template <typename T>
 void launch_2d(mfpff_ctx* c, const Level& L, int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e) {
-  if (L.g.k <= 2) HIPCHK(launch_regcell_2d<T>(mode, epi, a, e, c->tabh[L.g.k], c->s));
+  if (L.g.k <= 2) HIPCHK(launch_rowcell_2d<T>(mode, epi, a, e, c->tabh[L.g.k], tab<T>(c, L.g.k), c->s));
   else HIPCHK(launch_tile_2d<T>(mode, epi, a, e, tab<T>(c, L.g.k), c->s));
 }
 
@@ -423,11 +424,12 @@ void transfer(mfpff_ctx* c, int l, int dir, const T* in, T* out, bool add, T* ta
 
 void coarse_solve64(mfpff_ctx* c, const double* r, double* x) {
   const int nu = c->nu0, np = c->np0;
-  k_gemv(c->cs_t, c->Wu, nu, r, nu, nu, 1.0, nullptr, c->s);
-  k_gemv(x, c->WuT, nu, c->cs_t, nu, nu, 1.0, nullptr, c->s);
-  k_gemv(c->cs_t + nu, c->Gpu, nu, x, np, nu, -1.0, r + nu, c->s);
-  k_gemv(c->cs_t, c->Wp, np, c->cs_t + nu, np, np, 1.0, nullptr, c->s);
-  k_gemv(x + nu, c->WpT, np, c->cs_t, np, np, 1.0, nullptr, c->s);
+  // W = L^-1 is lower triangular and W^T upper: each product reads only the stored triangle
+  k_gemv(c->cs_t, c->Wu, nu, r, nu, nu, 1.0, nullptr, GEMV_LOWER, c->s);
+  k_gemv(x, c->WuT, nu, c->cs_t, nu, nu, 1.0, nullptr, GEMV_UPPER, c->s);
+  k_gemv(c->cs_t + nu, c->Gpu, nu, x, np, nu, -1.0, r + nu, GEMV_FULL, c->s);
+  k_gemv(c->cs_t, c->Wp, np, c->cs_t + nu, np, np, 1.0, nullptr, GEMV_LOWER, c->s);
+  k_gemv(x + nu, c->WpT, np, c->cs_t, np, np, 1.0, nullptr, GEMV_UPPER, c->s);
   LAUNCHCHK();
 }
 
@@ -648,6 +650,8 @@ void ensure_gmres(mfpff_ctx* c) {
   c->gr = dalloc<double>(n);
   c->hdev = dalloc<double>(4 * 80);
   c->ycoef = dalloc<double>(80);
+  c->ticket = dalloc<unsigned>(1);
+  HIPCHK(hipMemset(c->ticket, 0, sizeof(unsigned)));
   HIPCHK(hipHostMalloc((void**)&c->hhost, 4 * 80 * sizeof(double), hipHostMallocDefault));
 }
 
@@ -702,15 +706,22 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
       double* zj = c->Z + (size_t)j * n;
       precondition(c, vj, zj);
       apply_op<double>(c, c->L, MODE_APPLY, zj, c->gw, nullptr);
-      // CGS2
-      k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
-      k_multidot_finish(h1, c->part, nb, j + 1, c->s);
-      k_maxpy_dev(c->gw, c->V, n, j + 1, h1, -1.0, n, c->s);
-      k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
-      k_multidot_finish(h2, c->part, nb, j + 1, c->s);
-      k_maxpy_dev(c->gw, c->V, n, j + 1, h2, -1.0, n, c->s);
-      k_multidot_partials(c->part, c->gw, n, 1, c->gw, n, c->s);
-      k_multidot_finish(hn, c->part, nb, 1, c->s);
+      // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; |w|^2
+      if (j + 1 <= kOrthMax) {
+        // three passes over V, each reduction finished inside its launch
+        k_orth_pass(0, c->gw, c->V, n, j + 1, nullptr, c->part, h1, c->ticket, n, c->s);
+        k_orth_pass(1, c->gw, c->V, n, j + 1, h1, c->part, h2, c->ticket, n, c->s);
+        k_orth_pass(2, c->gw, c->V, n, j + 1, h2, c->part, hn, c->ticket, n, c->s);
+      } else {
+        k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
+        k_multidot_finish(h1, c->part, nb, j + 1, c->s);
+        k_maxpy_dev(c->gw, c->V, n, j + 1, h1, -1.0, n, c->s);
+        k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
+        k_multidot_finish(h2, c->part, nb, j + 1, c->s);
+        k_maxpy_dev(c->gw, c->V, n, j + 1, h2, -1.0, n, c->s);
+        k_multidot_partials(c->part, c->gw, n, 1, c->gw, n, c->s);
+        k_multidot_finish(hn, c->part, nb, 1, c->s);
+      }
       LAUNCHCHK();
       HIPCHK(hipMemcpyAsync(c->hhost, c->hdev, 3 * 80 * sizeof(double), hipMemcpyDeviceToHost, c->s));
       HIPCHK(hipStreamSynchronize(c->s));
@@ -1007,7 +1018,7 @@ void mfpff_destroy(mfpff_ctx* c) {
   }
   void* ps[] = {c->finite_flag, c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
                 c->WpT, c->Gpu, c->cs_in, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lst, c->part, c->V,
-                c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out};
+                c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->ticket, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out};
   for (void* p : ps) F(p);
   for (int i = 0; i < 5; ++i) F(c->s64[i]);
   if (c->hhost) hipHostFree(c->hhost);

@@ -85,9 +85,9 @@ template <typename T>
 hipError_t launch_tile_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<T>* tab, hipStream_t s);
 long long tile_blocks_2d(const Geom& g);
 template <typename T>
-hipError_t launch_regcell_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<double>& t64,
-                             hipStream_t s);
-long long regcell_blocks_2d(const Geom& g);
+hipError_t launch_rowcell_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<double>& t64,
+                             const Tables<T>* tabd, hipStream_t s);
+long long rowcell_blocks_2d(const Geom& g);
 
 // ---- launchers (cell_kernel.hip)
 template <typename T>
@@ -135,6 +135,13 @@ void k_multidot_finish(double* out, const double* part, int nblocks, int nvec, h
 void k_seg_dot_partials(double* part, const double* a, const double* b, long long nu, long long n, hipStream_t s);
 void k_maxpy_dev(double* w, const double* V, long long ldv, int nvec, const double* coef, double sign, long long n, hipStream_t s);
 void k_scale_dev(double* y, const double* x, const double* denom, long long n, hipStream_t s);
+// Arnoldi passes with the reduction finished in the launch (modes: 0 dots, 1 update + dots,
+// 2 update + squared norm); nvec <= kOrthMax; part holds orth_blocks(n) * nvec doubles; the
+// ticket counter starts at zero and is left at zero
+constexpr int kOrthMax = 32;
+int orth_blocks(long long n);
+void k_orth_pass(int mode, double* w, const double* V, long long ldv, int nvec, const double* coef, double* part,
+                 double* out, unsigned* ticket, long long n, hipStream_t s);
 void k_sum_pvjp(double* out2, const double* part, int nblocks, hipStream_t s);
 
 // CG-Lanczos device scalars
@@ -179,7 +186,9 @@ void k_extract_block(double* dst, long long ldd, const double* src, long long ld
 hipError_t cholesky_lower(double* A, int n, int* info_dev, double* scratch, hipStream_t s);  // info_dev zeroed by the caller
 hipError_t tri_inverse_lower(double* W, const double* L, int n, hipStream_t s);
 void k_transpose(double* At, const double* A, int n, hipStream_t s);
+// y = alpha A x (+ yin); GEMV_LOWER / GEMV_UPPER read only row i's entries j <= i / j >= i
+enum GemvShape : int { GEMV_FULL = 0, GEMV_LOWER = 1, GEMV_UPPER = 2 };
 void k_gemv(double* y, const double* A, long long lda, const double* x, int rows, int cols, double alpha,
-            const double* yin, hipStream_t s);
+            const double* yin, int shape, hipStream_t s);
 
 }  // namespace mfpff

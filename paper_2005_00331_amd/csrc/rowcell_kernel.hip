@@ -1,0 +1,411 @@
+// Cell kernel for 2D Q1/Q2 levels with fused epilogues (gfx950).
+//
+// Each cell is shared by k+1 threads, thread (cell, r) for r = 0..k.  The
+// threads are laid out r-major, so one wavefront holds one r for the 64 cells
+// of an 8 x 8 tile and nothing diverges:
+//  - thread r loads node row r of its cell and contracts it along x with the
+//    1D basis B and its derivative D at the Gauss points (Section 3.4: the
+//    element operator is applied through its tensor-product structure);
+//  - the x-contractions go through LDS, and thread r contracts along y for the
+//    Gauss-point row r, which gives values and gradients at its k+1 points;
+//  - it evaluates eq. (G) at those points (tangent of the split stress, the
+//    coupling g'(phi) sigma^+ and the phase-field terms);
+//  - the transposed contractions run the same way back: along x for its point
+//    row, through LDS, along y for its node row.
+// LDS exchanges are double-buffered (two field kinds per buffer), so each
+// exchange costs one barrier.  A workgroup computes 8 x 8 cells and owns the
+// nodes of the upper-right 7 x 7 (the first row and column are the halo that
+// completes the low-face nodes).  Results are added to an LDS node box in four
+// colour phases (cells of one colour share no node, and the k+1 threads of a
+// cell write different node rows), so the sum order is fixed; the owning
+// threads then apply the epilogue of the operation (product, residual with the
+// Chebyshev start, Chebyshev step).
+#include "internal.h"
+
+namespace mfpff {
+
+namespace {
+
+template <int NP, typename T>
+struct Tab2 {
+  T B[NP][NP];  // [q][i]
+  T D[NP][NP];
+  T w[NP];
+};
+
+}  // namespace
+
+constexpr int kRowTile = 8;              // computed cells per direction per workgroup
+constexpr int kRowOwn = kRowTile - 1;    // owned cells per direction
+constexpr int kRowCells = kRowTile * kRowTile;  // one wavefront per r
+
+long long rowcell_blocks_2d(const Geom& g) {
+  const long long nt = (g.N + kRowOwn - 1) / kRowOwn;
+  return nt * nt;
+}
+
+// at most 128 VGPRs: four wavefronts per SIMD (the FP64 products issue well below peak with one or two)
+template <int K, typename T, int MODE, int EPI>
+__global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_eu(4))) void rowcell_kernel_2d(CellArgs<T> a, Epilogue<T> e, Tab2<K + 1, T> tb,
+                                                                         const Tables<T>* __restrict__ tabd) {
+  constexpr int NP = K + 1;
+  constexpr int NT = kRowCells * NP;
+  constexpr int AN = K * kRowTile + 1;      // node box per direction
+  constexpr int KS = NP * NP * kRowCells;   // one field kind: [q or i][row][cell]
+  __shared__ T acc[3 * AN * AN];
+  __shared__ T xch[2][2 * KS];
+  const int tid = threadIdx.x;
+  const int r = __builtin_amdgcn_readfirstlane(tid / kRowCells);  // uniform per wavefront
+  const int cl = tid - r * kRowCells;
+  const int li = cl % kRowTile, lj = cl / kRowTile;
+  const Geom g = a.g;
+  const int N = g.N;
+  const long long M = g.M, nn = g.n_nodes;
+  const int ntx = (N + kRowOwn - 1) / kRowOwn;
+  const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  const int cx0 = tx * kRowOwn, cy0 = ty * kRowOwn;
+  const int cx1 = min(cx0 + kRowOwn, N), cy1 = min(cy0 + kRowOwn, N);
+  const int cx = cx0 - 1 + li, cy = cy0 - 1 + lj;
+  const bool valid = cx >= 0 && cy >= 0 && cx < cx1 && cy < cy1;
+  for (int i = tid; i < 3 * AN * AN; i += NT) acc[i] = T(0);
+
+  // table entries of row / column r (uniform loads from the device copy of the tables)
+  T Br[NP], Dr[NP], Bc[NP], Dc[NP];  // B[r][i], D[r][i], B[q][r], D[q][r]
+#pragma unroll
+  for (int i = 0; i < NP; ++i) {
+    Br[i] = tabd->B[r][i];
+    Dr[i] = tabd->D[r][i];
+    Bc[i] = tabd->B[i][r];
+    Dc[i] = tabd->D[i][r];
+  }
+  const T wr = tabd->w[r];
+
+  // ---- node row r of the cell: u_0, u_1, phi, phi~, x_0, x_1, x_phi (x zeroed at fixed dofs)
+  T f[7][NP];
+#pragma unroll
+  for (int i0 = 0; i0 < NP; ++i0) {
+#pragma unroll
+    for (int q = 0; q < 7; ++q) f[q][i0] = T(0);
+    if (valid) {
+      const long long nd = (long long)(K * cx + i0) + M * (K * cy + r);
+      const uint8_t mk = a.mask ? a.mask[nd] : (uint8_t)0;
+      f[0][i0] = a.u[nd];
+      f[1][i0] = a.u[nn + nd];
+      f[2][i0] = a.phi[nd];
+      f[3][i0] = a.phit[nd];
+      const T x0 = a.x[nd], x1 = a.x[nn + nd], x2 = a.x[2 * nn + nd];
+      f[4][i0] = (mk & kMaskU) ? T(0) : x0;
+      f[5][i0] = (mk & kMaskU) ? T(0) : x1;
+      f[6][i0] = (mk & kMaskPhi) ? T(0) : x2;
+    }
+  }
+
+  // ---- owned nodes and their epilogue operands (resid: b, dinv; cheb: r, d, dinv, x), loaded
+  // after the cell work so that they do not hold registers through it
+  const int nox = K * (cx1 - cx0) + (cx1 == N ? 1 : 0);
+  const int noy = K * (cy1 - cy0) + (cy1 == N ? 1 : 0);
+  const int nown = nox * noy;
+  constexpr int MAXO = ((K * kRowOwn + 1) * (K * kRowOwn + 1) + NT - 1) / NT;
+  struct Owned {
+    long long node;
+    int bo;
+    uint8_t m;
+    T ea[3], eb[3], ec[3], ex[3];
+  };
+  auto eload = [&](int j, Owned& o) {
+    const int id = tid + j * NT;
+    const bool ok = id < nown;
+    const int ox = ok ? id % nox : 0, oy = ok ? id / nox : 0;
+    o.node = ok ? (long long)(K * cx0 + ox) + M * (K * cy0 + oy) : -1;
+    o.bo = (K + oy) * AN + K + ox;
+    o.m = (ok && a.mask) ? a.mask[o.node] : (uint8_t)0;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const long long idx = cc * nn + o.node;
+      o.ea[cc] = o.eb[cc] = o.ec[cc] = o.ex[cc] = T(0);
+      if (ok && EPI == EPI_RESID) {
+        o.ea[cc] = e.b[idx];
+        if (e.z0) o.eb[cc] = e.dinv[idx];
+      } else if (ok && EPI == EPI_CHEB) {
+        o.ea[cc] = e.r[idx];
+        o.eb[cc] = e.d[idx];
+        o.ec[cc] = e.dinv[idx];
+        o.ex[cc] = a.x[idx];
+      }
+    }
+  };
+  auto efinish = [&](const Owned& o) {
+    if (o.node < 0) return;
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const long long idx = cc * nn + o.node;
+      const bool fixed = (cc < 2) ? (o.m & kMaskU) : (o.m & kMaskPhi);
+      const T xo = (EPI == EPI_CHEB) ? o.ex[cc] : (fixed ? a.x[idx] : T(0));
+      const T gx = fixed ? xo : acc[cc * AN * AN + o.bo];
+      if (EPI == EPI_APPLY) {
+        e.y[idx] = gx;
+      } else if (EPI == EPI_RESID) {
+        const T rv = o.ea[cc] - gx;
+        e.y[idx] = rv;
+        if (e.z0) {
+          const T zv = o.eb[cc] * rv * (cc < 2 ? e.ith_u : e.ith_p);
+          e.z0[idx] = zv;
+          e.d0[idx] = zv;
+        }
+      } else {
+        const bool isu = cc < 2;
+        const T dn = (isu ? e.c1u : e.c1p) * o.eb[cc] + (isu ? e.c2u : e.c2p) * o.ec[cc] * (o.ea[cc] - gx);
+        e.d[idx] = dn;
+        const T zn = xo + dn;
+        e.y[idx] = zn;
+        if (e.xout) e.xout[idx] = e.xacc[idx] + zn;
+      }
+    }
+  };
+
+  int slot = 0;
+  // publish two kinds of this thread's row (indexed [q][r]); after the barrier every
+  // thread reads the NP rows of its own cell
+  auto put = [&](const T (&k0)[NP], const T (&k1)[NP]) {
+    T* s = xch[slot];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      s[(q * NP + r) * kRowCells + cl] = k0[q];
+      s[KS + (q * NP + r) * kRowCells + cl] = k1[q];
+    }
+    __syncthreads();
+  };
+  auto get = [&](int kind, int q, int row) -> T { return xch[slot][kind * KS + (q * NP + row) * kRowCells + cl]; };
+  // x-contraction of node row r: t = B f, td = D f at the Gauss abscissae
+  auto xcon = [&](const T (&v)[NP], T (&t)[NP], T (&td)[NP]) {
+#pragma unroll
+    for (int q0 = 0; q0 < NP; ++q0) {
+      T s = 0, sd = 0;
+#pragma unroll
+      for (int i0 = 0; i0 < NP; ++i0) {
+        s += tb.B[q0][i0] * v[i0];
+        sd += tb.D[q0][i0] * v[i0];
+      }
+      t[q0] = s;
+      td[q0] = sd;
+    }
+  };
+  // gradient (d/dxi_0, d/dxi_1) at Gauss row r from the exchanged t (kind 0) and td (kind 1)
+  auto ygrad = [&](T (&g0)[NP], T (&g1)[NP]) {
+#pragma unroll
+    for (int q0 = 0; q0 < NP; ++q0) {
+      T s0 = 0, s1 = 0;
+#pragma unroll
+      for (int i1 = 0; i1 < NP; ++i1) {
+        s0 += Br[i1] * get(1, q0, i1);
+        s1 += Dr[i1] * get(0, q0, i1);
+      }
+      g0[q0] = s0;
+      g1[q0] = s1;
+    }
+  };
+
+  const T h = (T)g.h, ih = T(1) / h;
+  const T lam = (T)a.m.lam, mu = (T)a.m.mu, Gc = (T)a.m.Gc, eps = (T)a.m.eps, kap = (T)a.m.kappa;
+  const T Kb = lam + T(2) * mu / T(2);
+
+  // ---- linearisation at the Gauss points of row r
+  T gu00[NP], gu01[NP], gu10[NP], gu11[NP], phq[NP], ptq[NP];
+  {
+    T t[NP], td[NP];
+    xcon(f[0], t, td);
+    put(t, td);
+    ygrad(gu00, gu01);
+    slot ^= 1;
+    xcon(f[1], t, td);
+    put(t, td);
+    ygrad(gu10, gu11);
+    slot ^= 1;
+    T tp[NP], tt[NP];
+    xcon(f[2], tp, td);
+    xcon(f[3], tt, td);
+    put(tp, tt);
+#pragma unroll
+    for (int q0 = 0; q0 < NP; ++q0) {
+      T s0 = 0, s1 = 0;
+#pragma unroll
+      for (int i1 = 0; i1 < NP; ++i1) {
+        s0 += Br[i1] * get(0, q0, i1);
+        s1 += Br[i1] * get(1, q0, i1);
+      }
+      phq[q0] = s0;
+      ptq[q0] = s1;
+    }
+    slot ^= 1;
+  }
+  T cvol[NP], cdev[NP], sxx[NP], syy[NP], sxy[NP], cpp[NP];
+#pragma unroll
+  for (int q0 = 0; q0 < NP; ++q0) {
+    const T exx = gu00[q0] * ih, eyy = gu11[q0] * ih;
+    const T exy = T(0.5) * (gu01[q0] + gu10[q0]) * ih;
+    const T t = exx + eyy;
+    const bool H = t >= T(0);
+    const T tp = H ? t : T(0);
+    const T dxx = exx - T(0.5) * t, dyy = eyy - T(0.5) * t;
+    const T Ep = T(0.5) * Kb * tp * tp + mu * (dxx * dxx + dyy * dyy + T(2) * exy * exy);
+    const T pt = ptq[q0];
+    const T gt = (T(1) - kap) * pt * pt + kap;
+    const T dg = T(2) * (T(1) - kap) * phq[q0];
+    cvol[q0] = H ? gt * Kb : Kb;
+    cdev[q0] = T(2) * mu * gt;
+    sxx[q0] = dg * (T(2) * mu * dxx + Kb * tp);
+    syy[q0] = dg * (T(2) * mu * dyy + Kb * tp);
+    sxy[q0] = dg * (T(2) * mu * exy);
+    cpp[q0] = T(2) * (T(1) - kap) * Ep + Gc / eps;
+  }
+
+  // ---- trial functions at the Gauss points of row r
+  T gx00[NP], gx01[NP], gx10[NP], gx11[NP], pv[NP], pg0[NP], pg1[NP];
+  {
+    T t[NP], td[NP];
+    xcon(f[4], t, td);
+    put(t, td);
+    ygrad(gx00, gx01);
+    slot ^= 1;
+    xcon(f[5], t, td);
+    put(t, td);
+    ygrad(gx10, gx11);
+    slot ^= 1;
+    xcon(f[6], t, td);
+    put(t, td);
+    ygrad(pg0, pg1);
+#pragma unroll
+    for (int q0 = 0; q0 < NP; ++q0) {
+      T s = 0;
+#pragma unroll
+      for (int i1 = 0; i1 < NP; ++i1) s += Br[i1] * get(0, q0, i1);
+      pv[q0] = s;
+    }
+    slot ^= 1;
+  }
+
+  // ---- fluxes (quadrature weight and Jacobian factors included)
+  T F0x[NP], F1x[NP], F0y[NP], F1y[NP], Fv[NP], F0p[NP], F1p[NP];
+#pragma unroll
+  for (int q0 = 0; q0 < NP; ++q0) {
+    const T wq = tb.w[q0] * wr;  // JxW / h^2
+    const T dxx = gx00[q0] * ih, dyy = gx11[q0] * ih;
+    const T dxy = T(0.5) * (gx01[q0] + gx10[q0]) * ih;
+    const T dt = dxx + dyy;
+    const T vol = cvol[q0] * dt - cdev[q0] * T(0.5) * dt;
+    T Sxx = cdev[q0] * dxx + vol;
+    T Syy = cdev[q0] * dyy + vol;
+    T Sxy = cdev[q0] * dxy;
+    const T dph = pv[q0];
+    T fv = cpp[q0] * dph;
+    if (MODE == MODE_APPLY) fv += sxx[q0] * dxx + syy[q0] * dyy + T(2) * sxy[q0] * dxy;
+    if (MODE == MODE_APPLY_T) {
+      Sxx += dph * sxx[q0];
+      Syy += dph * syy[q0];
+      Sxy += dph * sxy[q0];
+    }
+    // gradient fluxes carry JxW / h = w h; the value flux JxW = w h^2
+    const T wg = wq * h;
+    F0x[q0] = wg * Sxx;
+    F1x[q0] = wg * Sxy;
+    F0y[q0] = wg * Sxy;
+    F1y[q0] = wg * Syy;
+    Fv[q0] = wq * h * h * fv;
+    F0p[q0] = wg * Gc * eps * pg0[q0] * ih;
+    F1p[q0] = wg * Gc * eps * pg1[q0] * ih;
+  }
+
+  // ---- test functions: along x for Gauss row r, then along y for node row r
+  // y[i1][i0] = sum_q1 B[q1][i1] (sum_q0 B[q0][i0] Fv + D[q0][i0] F0) + D[q1][i1] (sum_q0 B[q0][i0] F1)
+  T y[3][NP];
+  auto integ = [&](const T (&Fvv)[NP], const T (&F0)[NP], const T (&F1)[NP], bool has_v, T (&out)[NP]) {
+    T ka[NP], kb[NP];
+#pragma unroll
+    for (int i0 = 0; i0 < NP; ++i0) {
+      T sa = 0, sb = 0;
+#pragma unroll
+      for (int q0 = 0; q0 < NP; ++q0) {
+        sa += (has_v ? tb.B[q0][i0] * Fvv[q0] : T(0)) + tb.D[q0][i0] * F0[q0];
+        sb += tb.B[q0][i0] * F1[q0];
+      }
+      ka[i0] = sa;
+      kb[i0] = sb;
+    }
+    put(ka, kb);
+#pragma unroll
+    for (int i0 = 0; i0 < NP; ++i0) {
+      T s = 0;
+#pragma unroll
+      for (int q1 = 0; q1 < NP; ++q1) s += Bc[q1] * get(0, i0, q1) + Dc[q1] * get(1, i0, q1);
+      out[i0] = s;
+    }
+    slot ^= 1;
+  };
+  integ(Fv, F0x, F1x, false, y[0]);
+  integ(Fv, F0y, F1y, false, y[1]);
+  integ(Fv, F0p, F1p, true, y[2]);
+
+  // ---- colour-phased accumulation into the node box (fixed order)
+  const int colour = (cx & 1) + 2 * (cy & 1);
+  for (int ph = 0; ph < 4; ++ph) {
+    if (valid && colour == ph) {
+#pragma unroll
+      for (int i0 = 0; i0 < NP; ++i0) {
+        const int o = (K * lj + r) * AN + K * li + i0;
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) acc[cc * AN * AN + o] += y[cc][i0];
+      }
+    }
+    __syncthreads();
+  }
+  // ---- fused epilogue on the owned nodes
+#pragma unroll
+  for (int j = 0; j < MAXO; ++j) {
+    Owned on;
+    eload(j, on);
+    efinish(on);
+  }
+}
+
+template <int K, typename T>
+static hipError_t launch_row_k(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<double>& t64,
+                               const Tables<T>* tabd, hipStream_t s) {
+  Tab2<K + 1, T> tb;
+  for (int q = 0; q <= K; ++q) {
+    tb.w[q] = (T)t64.w[q];
+    for (int i = 0; i <= K; ++i) {
+      tb.B[q][i] = (T)t64.B[q][i];
+      tb.D[q][i] = (T)t64.D[q][i];
+    }
+  }
+  const long long nb = rowcell_blocks_2d(a.g);
+  dim3 grid((unsigned)nb), block(kRowCells * (K + 1));
+#define MFPFF_R(MD, EP)                                                                                 \
+  if (mode == MD && epi == EP) {                                                                        \
+    hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP>), grid, block, 0, s, a, e, tb, tabd);           \
+    return hipGetLastError();                                                                           \
+  }
+  MFPFF_R(MODE_APPLY, EPI_APPLY)
+  MFPFF_R(MODE_APPLY_T, EPI_APPLY)
+  MFPFF_R(MODE_BLOCK, EPI_APPLY)
+  MFPFF_R(MODE_APPLY, EPI_RESID)
+  MFPFF_R(MODE_BLOCK, EPI_CHEB)
+#undef MFPFF_R
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_rowcell_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<double>& t64,
+                             const Tables<T>* tabd, hipStream_t s) {
+  if (a.g.dim != 2) return hipErrorInvalidValue;
+  if (a.g.k == 1) return launch_row_k<1, T>(mode, epi, a, e, t64, tabd, s);
+  if (a.g.k == 2) return launch_row_k<2, T>(mode, epi, a, e, t64, tabd, s);
+  return hipErrorInvalidValue;
+}
+
+template hipError_t launch_rowcell_2d<double>(int, int, const CellArgs<double>&, const Epilogue<double>&, const Tables<double>&,
+                                              const Tables<double>*, hipStream_t);
+template hipError_t launch_rowcell_2d<float>(int, int, const CellArgs<float>&, const Epilogue<float>&, const Tables<double>&,
+                                             const Tables<float>*, hipStream_t);
+
+}  // namespace mfpff

@@ -337,6 +337,113 @@ __global__ void maxpy_dev_kernel(double* w, const double* V, long long ldv, int 
 void k_maxpy_dev(double* w, const double* V, long long ldv, int nvec, const double* coef, double sign, long long n, hipStream_t s) {
   hipLaunchKernelGGL(maxpy_dev_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, w, V, ldv, nvec, coef, sign, n);
 }
+// ---------------------------------------------------------------- Arnoldi passes
+// One pass over the Krylov basis V (nvec <= kOrthMax vectors) and the new
+// vector w, with the reduction finished in the same launch: every workgroup
+// writes its partial sums, and the workgroup that arrives last at the ticket
+// counter adds all partials in block order (so the result does not depend on
+// which workgroup is last) and resets the counter.
+//   ORTH_DOTS:       out[j] = V_j . w
+//   ORTH_UPDATE_DOTS: w <- w - V c;  out[j] = V_j . w        (c on the device)
+//   ORTH_UPDATE_NORM: w <- w - V c;  out[0] = w . w
+enum OrthMode : int { ORTH_DOTS = 0, ORTH_UPDATE_DOTS = 1, ORTH_UPDATE_NORM = 2 };
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+template <int MODE, int NV>
+__global__ __launch_bounds__(kThreads) void orth_pass_kernel(double* __restrict__ w, const double* __restrict__ V,
+                                                             long long ldv, const double* __restrict__ coef,
+                                                             double* __restrict__ part, double* __restrict__ out,
+                                                             unsigned* ticket, long long n) {
+  constexpr int NA = MODE == ORTH_UPDATE_NORM ? 1 : NV;  // accumulators per thread
+  constexpr int NW = kThreads / 64;
+  __shared__ double sh[NW][NA];
+  __shared__ bool last;
+  double c[NV];
+  if (MODE != ORTH_DOTS) {
+#pragma unroll
+    for (int j = 0; j < NV; ++j) c[j] = coef[j];
+  }
+  double acc[NA];
+#pragma unroll
+  for (int j = 0; j < NA; ++j) acc[j] = 0.0;
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    double v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = V[(long long)j * ldv + i];
+    double wi = w[i];
+    if (MODE != ORTH_DOTS) {
+      double t = 0.0;
+#pragma unroll
+      for (int j = 0; j < NV; ++j) t += c[j] * v[j];
+      wi -= t;
+      w[i] = wi;
+    }
+    if (MODE == ORTH_UPDATE_NORM) {
+      acc[0] += wi * wi;
+    } else {
+#pragma unroll
+      for (int j = 0; j < NA; ++j) acc[j] += v[j] * wi;
+    }
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int j = 0; j < NA; ++j) {
+    const double r = wave_sum(acc[j]);
+    if (lane == 0) sh[wid][j] = r;
+  }
+  __syncthreads();
+  if (threadIdx.x < NA) {
+    double r = 0.0;
+    for (int q = 0; q < NW; ++q) r += sh[q][threadIdx.x];
+    part[(long long)blockIdx.x * NA + threadIdx.x] = r;
+  }
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  const int nb = gridDim.x;
+  for (int j = wid; j < NA; j += NW) {
+    double r = 0.0;
+    for (int b = lane; b < nb; b += 64) r += part[(long long)b * NA + j];
+    r = wave_sum(r);
+    if (lane == 0) out[j] = r;
+  }
+  if (threadIdx.x == 0) *ticket = 0u;
+}
+
+int orth_blocks(long long n) { return dot_blocks(n); }
+
+// one instantiation per basis size, so that every load and accumulator is unconditional
+template <int MODE, int NV>
+static void launch_orth(int nvec, double* w, const double* V, long long ldv, const double* coef, double* part,
+                        double* out, unsigned* ticket, long long n, hipStream_t s) {
+  if constexpr (NV <= kOrthMax) {
+    if (nvec == NV) {
+      hipLaunchKernelGGL((orth_pass_kernel<MODE, NV>), dim3(orth_blocks(n)), dim3(kThreads), 0, s, w, V, ldv, coef, part,
+                         out, ticket, n);
+      return;
+    }
+    launch_orth<MODE, NV + 1>(nvec, w, V, ldv, coef, part, out, ticket, n, s);
+  }
+}
+
+void k_orth_pass(int mode, double* w, const double* V, long long ldv, int nvec, const double* coef, double* part,
+                 double* out, unsigned* ticket, long long n, hipStream_t s) {
+  if (mode == ORTH_DOTS)
+    launch_orth<ORTH_DOTS, 1>(nvec, w, V, ldv, coef, part, out, ticket, n, s);
+  else if (mode == ORTH_UPDATE_DOTS)
+    launch_orth<ORTH_UPDATE_DOTS, 1>(nvec, w, V, ldv, coef, part, out, ticket, n, s);
+  else
+    launch_orth<ORTH_UPDATE_NORM, 1>(nvec, w, V, ldv, coef, part, out, ticket, n, s);
+}
+
 // y = x / denom[0]
 __global__ void scale_dev_kernel(double* y, const double* x, const double* denom, long long n) {
   const double d = denom[0];
