@@ -125,10 +125,10 @@ struct mfpff_ctx {
   double* Z = nullptr;
   double* gw = nullptr;
   double* gr = nullptr;
-  double* hdev = nullptr;
-  double* hhost = nullptr;
+  double* hdev = nullptr;   // two Arnoldi result buffers (h1, h2, |w|^2), kHBuf doubles each
+  double* hhost = nullptr;  // pinned: mirrors of both buffers, then staging for y and beta
+  hipEvent_t hev[2] = {nullptr, nullptr};
   double* ycoef = nullptr;
-  unsigned* ticket = nullptr;  // arrival counter of the single-launch reductions (kept at zero between launches)
   // Newton
   double* R = nullptr;
   double* b = nullptr;
@@ -517,11 +517,14 @@ void capture_vcycle(mfpff_ctx* c) {
 }
 
 // z = V(r) on the finest level, FP64 in/out
-void precondition(mfpff_ctx* c, const double* r, double* z) {
+// z = V(r); b_ready: the caller has already written r into the finest level's right-hand side
+void precondition(mfpff_ctx* c, const double* r, double* z, bool b_ready = false) {
   Level& F = c->lv[c->L];
-  if (c->f32) k_cast_d2f((float*)F.w[WB], r, F.n, c->s);
-  else k_copy<double>((double*)F.w[WB], r, F.n, c->s);
-  LAUNCHCHK();
+  if (!b_ready) {
+    if (c->f32) k_cast_d2f((float*)F.w[WB], r, F.n, c->s);
+    else k_copy<double>((double*)F.w[WB], r, F.n, c->s);
+    LAUNCHCHK();
+  }
   if (c->vgraph) HIPCHK(hipGraphLaunch(c->vgraph, c->s));
   else vcycle_body(c);
   if (c->f32) k_cast_f2d(z, (const float*)F.w[WX], F.n, c->s);
@@ -640,6 +643,12 @@ void require_ptr(const void* p, const char* name) {
   if (!p) throw StatusError{MFPFF_ERR_ARG, std::string("null pointer: ") + name};
 }
 
+// Arnoldi result buffers: h1 at +0, h2 at +80, |w|^2 at +160 (restart <= 64)
+constexpr int kHBuf = 240;
+constexpr int kHostY = 2 * kHBuf;      // pinned staging of the least-squares solution
+constexpr int kHostBeta = kHostY + 80;  // pinned staging of the residual norm
+constexpr int kHostLen = kHostBeta + 8;
+
 void ensure_gmres(mfpff_ctx* c) {
   if (c->V) return;
   const long long n = c->lv[c->L].n;
@@ -648,11 +657,10 @@ void ensure_gmres(mfpff_ctx* c) {
   c->Z = dalloc<double>((size_t)c->m * n);
   c->gw = dalloc<double>(n);
   c->gr = dalloc<double>(n);
-  c->hdev = dalloc<double>(4 * 80);
+  c->hdev = dalloc<double>(2 * kHBuf);
   c->ycoef = dalloc<double>(80);
-  c->ticket = dalloc<unsigned>(1);
-  HIPCHK(hipMemset(c->ticket, 0, sizeof(unsigned)));
-  HIPCHK(hipHostMalloc((void**)&c->hhost, 4 * 80 * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostMalloc((void**)&c->hhost, kHostLen * sizeof(double), hipHostMallocDefault));
+  for (int b = 0; b < 2; ++b) HIPCHK(hipEventCreateWithFlags(&c->hev[b], hipEventDisableTiming));
 }
 
 double dev_norm(mfpff_ctx* c, const double* x, long long n, double* out_dev) {
@@ -666,16 +674,18 @@ double dev_norm(mfpff_ctx* c, const double* x, long long n, double* out_dev) {
 }
 
 // Right-preconditioned FGMRES(m), CGS2, x0 = 0.
+// The device work of Arnoldi step j+1 (normalisation, V-cycle, product,
+// orthogonalisation) is queued before the host waits for the results of step j,
+// so the GPU does not idle while the host applies the Givens rotations; when
+// step j ends the cycle, the queued step only overwrites basis columns that are
+// not used.
 mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* info) {
   ensure_gmres(c);
   const int m = c->m;
   const long long n = c->lv[c->L].n;
   const int nb = dot_blocks(n);
-  double* h1 = c->hdev;        // j+1 values
-  double* h2 = c->hdev + 80;   // j+1 values
-  double* hn = c->hdev + 160;  // norm^2 then norm
   k_fill<double>(x, 0.0, n, c->s);
-  const double bnorm = dev_norm(c, b, n, hn);
+  const double bnorm = dev_norm(c, b, n, c->hdev + 160);
   int it = 0;
   const double tol = c->prob.rtol * bnorm;
   std::vector<double> H((size_t)(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
@@ -684,10 +694,39 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
   if (bnorm == 0.0) {
     conv = true;
   }
+  // v_j is written together with the V-cycle's right-hand side (FP32 for the mixed V-cycle)
+  void* vb = c->lv[c->L].w[WB];
+  // step j: z_j = V(v_j), w = G^ z_j, CGS2 against v_0..v_j into buffer j % 2, copied to the host
+  auto arnoldi = [&](int j) {
+    double* vj = c->V + (size_t)j * n;
+    double* zj = c->Z + (size_t)j * n;
+    double* hb = c->hdev + (j & 1) * kHBuf;
+    double *h1 = hb, *h2 = hb + 80, *hn = hb + 160;
+    precondition(c, vj, zj, true);
+    apply_op<double>(c, c->L, MODE_APPLY, zj, c->gw, nullptr);
+    if (j + 1 <= kOrthMax) {
+      // three passes over V (each with all basis vectors at once)
+      k_orth_pass(0, c->gw, c->V, n, j + 1, nullptr, c->part, h1, n, c->s);
+      k_orth_pass(1, c->gw, c->V, n, j + 1, h1, c->part, h2, n, c->s);
+      k_orth_pass(2, c->gw, c->V, n, j + 1, h2, c->part, hn, n, c->s);
+    } else {
+      k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
+      k_multidot_finish(h1, c->part, nb, j + 1, c->s);
+      k_maxpy_dev(c->gw, c->V, n, j + 1, h1, -1.0, n, c->s);
+      k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
+      k_multidot_finish(h2, c->part, nb, j + 1, c->s);
+      k_maxpy_dev(c->gw, c->V, n, j + 1, h2, -1.0, n, c->s);
+      k_multidot_partials(c->part, c->gw, n, 1, c->gw, n, c->s);
+      k_multidot_finish(hn, c->part, nb, 1, c->s);
+    }
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(c->hhost + (j & 1) * kHBuf, hb, kHBuf * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipEventRecord(c->hev[j & 1], c->s));
+  };
   while (!conv) {
     // r = b - G^ x
     apply_op<double>(c, c->L, MODE_APPLY, x, c->gr, b);
-    const double beta = dev_norm(c, c->gr, n, hn);
+    const double beta = dev_norm(c, c->gr, n, c->hdev + 160);
     relres = beta / bnorm;
     if (beta <= tol) {
       conv = true;
@@ -697,36 +736,21 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
     std::fill(H.begin(), H.end(), 0.0);
     std::fill(g.begin(), g.end(), 0.0);
     g[0] = beta;
-    c->hhost[200] = beta;  // pinned staging; the stream orders it before later copies into hhost
-    HIPCHK(hipMemcpyAsync(c->ycoef, &c->hhost[200], sizeof(double), hipMemcpyHostToDevice, c->s));
-    k_scale_dev(c->V, c->gr, c->ycoef, n, c->s);
+    c->hhost[kHostBeta] = beta;  // pinned staging, not a target of any device-to-host copy
+    HIPCHK(hipMemcpyAsync(c->ycoef, &c->hhost[kHostBeta], sizeof(double), hipMemcpyHostToDevice, c->s));
+    k_scale_dev(c->V, c->gr, c->ycoef, n, c->s, vb, c->f32);
+    arnoldi(0);
     int jend = 0;
     for (int j = 0; j < m; ++j) {
-      double* vj = c->V + (size_t)j * n;
-      double* zj = c->Z + (size_t)j * n;
-      precondition(c, vj, zj);
-      apply_op<double>(c, c->L, MODE_APPLY, zj, c->gw, nullptr);
-      // CGS2: h1 = V^T w; w -= V h1; h2 = V^T w; w -= V h2; |w|^2
-      if (j + 1 <= kOrthMax) {
-        // three passes over V, each reduction finished inside its launch
-        k_orth_pass(0, c->gw, c->V, n, j + 1, nullptr, c->part, h1, c->ticket, n, c->s);
-        k_orth_pass(1, c->gw, c->V, n, j + 1, h1, c->part, h2, c->ticket, n, c->s);
-        k_orth_pass(2, c->gw, c->V, n, j + 1, h2, c->part, hn, c->ticket, n, c->s);
-      } else {
-        k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
-        k_multidot_finish(h1, c->part, nb, j + 1, c->s);
-        k_maxpy_dev(c->gw, c->V, n, j + 1, h1, -1.0, n, c->s);
-        k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
-        k_multidot_finish(h2, c->part, nb, j + 1, c->s);
-        k_maxpy_dev(c->gw, c->V, n, j + 1, h2, -1.0, n, c->s);
-        k_multidot_partials(c->part, c->gw, n, 1, c->gw, n, c->s);
-        k_multidot_finish(hn, c->part, nb, 1, c->s);
+      if (j + 1 < m) {
+        // queue step j+1: v_{j+1} = w / |w| with |w|^2 from buffer j % 2
+        k_scale_rsqrt_dev(c->V + (size_t)(j + 1) * n, c->gw, c->hdev + (j & 1) * kHBuf + 160, n, c->s, vb, c->f32);
+        arnoldi(j + 1);
       }
-      LAUNCHCHK();
-      HIPCHK(hipMemcpyAsync(c->hhost, c->hdev, 3 * 80 * sizeof(double), hipMemcpyDeviceToHost, c->s));
-      HIPCHK(hipStreamSynchronize(c->s));
-      const double hnorm = std::sqrt(c->hhost[160]);
-      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = c->hhost[i] + c->hhost[80 + i];
+      HIPCHK(hipEventSynchronize(c->hev[j & 1]));
+      const double* hh = c->hhost + (j & 1) * kHBuf;
+      const double hnorm = std::sqrt(hh[160]);
+      for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[80 + i];
       H[(size_t)(j + 1) * m + j] = hnorm;
       for (int i = 0; i < j; ++i) {
         const double tmp = cs[i] * H[(size_t)i * m + j] + sn[i] * H[(size_t)(i + 1) * m + j];
@@ -749,20 +773,17 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
       ++it;
       jend = j + 1;
       if (std::fabs(g[j + 1]) <= tol || it >= c->prob.max_iter || hnorm == 0.0) break;
-      c->hhost[200] = hnorm;
-      HIPCHK(hipMemcpyAsync(c->ycoef, &c->hhost[200], sizeof(double), hipMemcpyHostToDevice, c->s));
-      k_scale_dev(c->V + (size_t)(j + 1) * n, c->gw, c->ycoef, n, c->s);
     }
     for (int i = jend - 1; i >= 0; --i) {
       double sacc = g[i];
       for (int k = i + 1; k < jend; ++k) sacc -= H[(size_t)i * m + k] * y[k];
       y[i] = sacc / H[(size_t)i * m + i];
     }
-    for (int i = 0; i < jend; ++i) c->hhost[240 + i] = y[i];
-    HIPCHK(hipMemcpyAsync(c->ycoef, &c->hhost[240], jend * sizeof(double), hipMemcpyHostToDevice, c->s));
+    for (int i = 0; i < jend; ++i) c->hhost[kHostY + i] = y[i];
+    HIPCHK(hipMemcpyAsync(c->ycoef, &c->hhost[kHostY], jend * sizeof(double), hipMemcpyHostToDevice, c->s));
     k_maxpy_dev(x, c->Z, n, jend, c->ycoef, 1.0, n, c->s);
     LAUNCHCHK();
-    HIPCHK(hipStreamSynchronize(c->s));  // ycoef host staging is reused next cycle
+    HIPCHK(hipStreamSynchronize(c->s));  // staging buffers are reused next cycle
   }
   if (info) {
     info->iterations = it;
@@ -1018,10 +1039,12 @@ void mfpff_destroy(mfpff_ctx* c) {
   }
   void* ps[] = {c->finite_flag, c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
                 c->WpT, c->Gpu, c->cs_in, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lst, c->part, c->V,
-                c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->ticket, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out};
+                c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out};
   for (void* p : ps) F(p);
   for (int i = 0; i < 5; ++i) F(c->s64[i]);
   if (c->hhost) hipHostFree(c->hhost);
+  for (auto e : c->hev)
+    if (e) hipEventDestroy(e);
   if (c->vgraph) hipGraphExecDestroy(c->vgraph);
   if (c->cap_s) hipStreamDestroy(c->cap_s);
   delete c;

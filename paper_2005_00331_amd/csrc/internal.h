@@ -134,14 +134,18 @@ void k_multidot_partials(double* part, const double* V, long long ldv, int nvec,
 void k_multidot_finish(double* out, const double* part, int nblocks, int nvec, hipStream_t s);
 void k_seg_dot_partials(double* part, const double* a, const double* b, long long nu, long long n, hipStream_t s);
 void k_maxpy_dev(double* w, const double* V, long long ldv, int nvec, const double* coef, double sign, long long n, hipStream_t s);
-void k_scale_dev(double* y, const double* x, const double* denom, long long n, hipStream_t s);
-// Arnoldi passes with the reduction finished in the launch (modes: 0 dots, 1 update + dots,
-// 2 update + squared norm); nvec <= kOrthMax; part holds orth_blocks(n) * nvec doubles; the
-// ticket counter starts at zero and is left at zero
+// y = x / denom[0] (rsqrt: x / sqrt(denom[0])); y2, if given, receives a copy (FP32 when y2_f32)
+void k_scale_dev(double* y, const double* x, const double* denom, long long n, hipStream_t s, void* y2 = nullptr,
+                 bool y2_f32 = false);
+void k_scale_rsqrt_dev(double* y, const double* x, const double* sq, long long n, hipStream_t s, void* y2 = nullptr,
+                       bool y2_f32 = false);
+// Arnoldi passes (modes: 0 dots, 1 update + dots, 2 update + squared norm), each followed by
+// a one-workgroup launch that finishes the reduction into out; nvec <= kOrthMax; part holds
+// orth_blocks(n) * nvec doubles
 constexpr int kOrthMax = 32;
 int orth_blocks(long long n);
 void k_orth_pass(int mode, double* w, const double* V, long long ldv, int nvec, const double* coef, double* part,
-                 double* out, unsigned* ticket, long long n, hipStream_t s);
+                 double* out, long long n, hipStream_t s);
 void k_sum_pvjp(double* out2, const double* part, int nblocks, hipStream_t s);
 
 // CG-Lanczos device scalars

@@ -339,13 +339,12 @@ void k_maxpy_dev(double* w, const double* V, long long ldv, int nvec, const doub
 }
 // ---------------------------------------------------------------- Arnoldi passes
 // One pass over the Krylov basis V (nvec <= kOrthMax vectors) and the new
-// vector w, with the reduction finished in the same launch: every workgroup
-// writes its partial sums, and the workgroup that arrives last at the ticket
-// counter adds all partials in block order (so the result does not depend on
-// which workgroup is last) and resets the counter.
-//   ORTH_DOTS:       out[j] = V_j . w
-//   ORTH_UPDATE_DOTS: w <- w - V c;  out[j] = V_j . w        (c on the device)
-//   ORTH_UPDATE_NORM: w <- w - V c;  out[0] = w . w
+// vector w; every workgroup writes its partial sums, and orth_finish_kernel
+// adds them in block order (a device-wide fence inside the pass would write
+// back the whole L2 of every XCD once per workgroup).
+//   ORTH_DOTS:        part -> V_j . w
+//   ORTH_UPDATE_DOTS: w <- w - V c;  part -> V_j . w        (c on the device)
+//   ORTH_UPDATE_NORM: w <- w - V c;  part -> w . w
 enum OrthMode : int { ORTH_DOTS = 0, ORTH_UPDATE_DOTS = 1, ORTH_UPDATE_NORM = 2 };
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -356,12 +355,10 @@ __device__ __forceinline__ double wave_sum(double v) {
 template <int MODE, int NV>
 __global__ __launch_bounds__(kThreads) void orth_pass_kernel(double* __restrict__ w, const double* __restrict__ V,
                                                              long long ldv, const double* __restrict__ coef,
-                                                             double* __restrict__ part, double* __restrict__ out,
-                                                             unsigned* ticket, long long n) {
+                                                             double* __restrict__ part, long long n) {
   constexpr int NA = MODE == ORTH_UPDATE_NORM ? 1 : NV;  // accumulators per thread
   constexpr int NW = kThreads / 64;
   __shared__ double sh[NW][NA];
-  __shared__ bool last;
   double c[NV];
   if (MODE != ORTH_DOTS) {
 #pragma unroll
@@ -376,6 +373,9 @@ __global__ __launch_bounds__(kThreads) void orth_pass_kernel(double* __restrict_
 #pragma unroll
     for (int j = 0; j < NV; ++j) v[j] = V[(long long)j * ldv + i];
     double wi = w[i];
+    // keep every load of the element in flight before the arithmetic (the register
+    // allocator would otherwise interleave them to save registers)
+    __builtin_amdgcn_sched_barrier(0);
     if (MODE != ORTH_DOTS) {
       double t = 0.0;
 #pragma unroll
@@ -402,20 +402,19 @@ __global__ __launch_bounds__(kThreads) void orth_pass_kernel(double* __restrict_
     for (int q = 0; q < NW; ++q) r += sh[q][threadIdx.x];
     part[(long long)blockIdx.x * NA + threadIdx.x] = r;
   }
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) last = atomicAdd(ticket, 1u) == gridDim.x - 1;
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
-  const int nb = gridDim.x;
-  for (int j = wid; j < NA; j += NW) {
+}
+
+// out[j] = sum over blocks b (in order per lane, then a fixed tree) of part[b * nout + j]; one wave per j
+constexpr int kFinishThreads = 1024;
+__global__ __launch_bounds__(kFinishThreads) void orth_finish_kernel(double* __restrict__ out, const double* __restrict__ part,
+                                                                     int nb, int nout) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j = wid; j < nout; j += kFinishThreads / 64) {
     double r = 0.0;
-    for (int b = lane; b < nb; b += 64) r += part[(long long)b * NA + j];
+    for (int b = lane; b < nb; b += 64) r += part[(long long)b * nout + j];
     r = wave_sum(r);
     if (lane == 0) out[j] = r;
   }
-  if (threadIdx.x == 0) *ticket = 0u;
 }
 
 int orth_blocks(long long n) { return dot_blocks(n); }
@@ -423,34 +422,50 @@ int orth_blocks(long long n) { return dot_blocks(n); }
 // one instantiation per basis size, so that every load and accumulator is unconditional
 template <int MODE, int NV>
 static void launch_orth(int nvec, double* w, const double* V, long long ldv, const double* coef, double* part,
-                        double* out, unsigned* ticket, long long n, hipStream_t s) {
+                        long long n, hipStream_t s) {
   if constexpr (NV <= kOrthMax) {
     if (nvec == NV) {
-      hipLaunchKernelGGL((orth_pass_kernel<MODE, NV>), dim3(orth_blocks(n)), dim3(kThreads), 0, s, w, V, ldv, coef, part,
-                         out, ticket, n);
+      hipLaunchKernelGGL((orth_pass_kernel<MODE, NV>), dim3(orth_blocks(n)), dim3(kThreads), 0, s, w, V, ldv, coef, part, n);
       return;
     }
-    launch_orth<MODE, NV + 1>(nvec, w, V, ldv, coef, part, out, ticket, n, s);
+    launch_orth<MODE, NV + 1>(nvec, w, V, ldv, coef, part, n, s);
   }
 }
 
 void k_orth_pass(int mode, double* w, const double* V, long long ldv, int nvec, const double* coef, double* part,
-                 double* out, unsigned* ticket, long long n, hipStream_t s) {
+                 double* out, long long n, hipStream_t s) {
   if (mode == ORTH_DOTS)
-    launch_orth<ORTH_DOTS, 1>(nvec, w, V, ldv, coef, part, out, ticket, n, s);
+    launch_orth<ORTH_DOTS, 1>(nvec, w, V, ldv, coef, part, n, s);
   else if (mode == ORTH_UPDATE_DOTS)
-    launch_orth<ORTH_UPDATE_DOTS, 1>(nvec, w, V, ldv, coef, part, out, ticket, n, s);
+    launch_orth<ORTH_UPDATE_DOTS, 1>(nvec, w, V, ldv, coef, part, n, s);
   else
-    launch_orth<ORTH_UPDATE_NORM, 1>(nvec, w, V, ldv, coef, part, out, ticket, n, s);
+    launch_orth<ORTH_UPDATE_NORM, 1>(nvec, w, V, ldv, coef, part, n, s);
+  const int nout = mode == ORTH_UPDATE_NORM ? 1 : nvec;
+  hipLaunchKernelGGL(orth_finish_kernel, dim3(1), dim3(kFinishThreads), 0, s, out, part, orth_blocks(n), nout);
 }
 
-// y = x / denom[0]
-__global__ void scale_dev_kernel(double* y, const double* x, const double* denom, long long n) {
-  const double d = denom[0];
-  GSTRIDE(i, n) y[i] = x[i] / d;
+// y = x / d with d = denom[0], or d = sqrt(denom[0]) when SQ; optionally also y2 = y in the
+// precision of the V-cycle (the preconditioner's input)
+template <bool SQ, typename T2>
+__global__ void scale_dev_kernel(double* y, T2* y2, const double* x, const double* denom, long long n) {
+  const double d = SQ ? sqrt(denom[0]) : denom[0];
+  GSTRIDE(i, n) {
+    const double v = x[i] / d;
+    y[i] = v;
+    if (y2) y2[i] = (T2)v;
+  }
 }
-void k_scale_dev(double* y, const double* x, const double* denom, long long n, hipStream_t s) {
-  hipLaunchKernelGGL(scale_dev_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, y, x, denom, n);
+void k_scale_dev(double* y, const double* x, const double* denom, long long n, hipStream_t s, void* y2, bool y2_f32) {
+  if (y2_f32)
+    hipLaunchKernelGGL((scale_dev_kernel<false, float>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, (float*)y2, x, denom, n);
+  else
+    hipLaunchKernelGGL((scale_dev_kernel<false, double>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, (double*)y2, x, denom, n);
+}
+void k_scale_rsqrt_dev(double* y, const double* x, const double* sq, long long n, hipStream_t s, void* y2, bool y2_f32) {
+  if (y2_f32)
+    hipLaunchKernelGGL((scale_dev_kernel<true, float>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, (float*)y2, x, sq, n);
+  else
+    hipLaunchKernelGGL((scale_dev_kernel<true, double>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, (double*)y2, x, sq, n);
 }
 __global__ void sum_pvjp_kernel(double* out, const double* part, int nb) {
   __shared__ double sh[8];
