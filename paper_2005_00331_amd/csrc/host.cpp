@@ -72,6 +72,9 @@ struct Level {
   double* dinv = nullptr;
   float* dinv32 = nullptr;
   double* diag = nullptr;  // FP64 diagonal of G^ (1 at fixed dofs)
+  double* qd = nullptr;    // 2D Q1/Q2: tangent coefficients at the Gauss points (set with the point)
+  float* qd32 = nullptr;
+  bool qd_ok = false;
   double lam[2] = {1.0, 1.0};
   int lsteps[2] = {0, 0};
   std::vector<double> c1u, c2u, c1p, c2p;  // Chebyshev step coefficients, index i = 1..s-1
@@ -252,6 +255,13 @@ double tridiag_max_eig(const std::vector<double>& a, const std::vector<double>& 
 }
 
 template <typename T>
+const T* level_qd(const Level& L);
+template <>
+const double* level_qd<double>(const Level& L) { return L.qd_ok ? L.qd : nullptr; }
+template <>
+const float* level_qd<float>(const Level& L) { return L.qd_ok ? L.qd32 : nullptr; }
+
+template <typename T>
 CellArgs<T> cell_args(mfpff_ctx* c, const Level& L, const T* lin, const T* x, T* y, T scale) {
   CellArgs<T> a{};
   a.g = L.g;
@@ -263,6 +273,7 @@ CellArgs<T> cell_args(mfpff_ctx* c, const Level& L, const T* lin, const T* x, T*
   a.phit = lin + (size_t)(c->dim + 1) * L.nn;
   a.mask = L.mask;
   a.scale = scale;
+  a.qd = level_qd<T>(L);
   return a;
 }
 
@@ -809,6 +820,21 @@ void set_point(mfpff_ctx* c, const double* u, const double* phi, const double* p
   }
   if (c->f32)
     for (int l = 0; l <= c->L; ++l) k_cast_d2f(c->lv[l].lin32, c->lv[l].lin, (long long)(d + 2) * c->lv[l].nn, c->s);
+  // tangent coefficients at the Gauss points of the 2D Q1/Q2 levels
+  for (int l = 0; l <= c->L; ++l) {
+    Level& L = c->lv[l];
+    L.qd_ok = false;
+    if (!L.qd) continue;
+    CellArgs<double> a = cell_args<double>(c, L, L.lin, nullptr, nullptr, 1.0);
+    a.qd_out = L.qd;
+    launch_2d<double>(c, L, MODE_QDATA, EPI_APPLY, a, Epilogue<double>{});
+    if (L.qd32) {
+      CellArgs<float> a32 = cell_args<float>(c, L, L.lin32, nullptr, nullptr, 1.0f);
+      a32.qd_out = L.qd32;
+      launch_2d<float>(c, L, MODE_QDATA, EPI_APPLY, a32, Epilogue<float>{});
+    }
+    L.qd_ok = true;
+  }
   // finite check of the finest fields: sum of squares is finite unless some entry is inf or nan
   const long long nf = (long long)(d + 2) * F.nn;
   const int nb = dot_blocks(nf);
@@ -930,6 +956,11 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
         L.lin32 = dalloc<float>((size_t)(d + 2) * L.nn);
         L.dinv32 = dalloc<float>(L.n);
       }
+      if (d == 2 && L.g.k <= 2) {
+        const size_t nq = (size_t)rowcell_qdata_len(L.g);
+        L.qd = dalloc<double>(nq);
+        if (c->f32) L.qd32 = dalloc<float>(nq);
+      }
       const size_t es = c->f32 ? sizeof(float) : sizeof(double);
       for (int w = 0; w < NW; ++w) {
         void* ptr = nullptr;
@@ -1021,6 +1052,8 @@ void mfpff_destroy(mfpff_ctx* c) {
   for (auto& L : c->lv) {
     F(L.lin);
     F(L.lin32);
+    F(L.qd);
+    F(L.qd32);
     F(L.mask);
     F(L.dinv);
     F(L.dinv32);

@@ -46,8 +46,16 @@ enum CellMode : int {
   MODE_BLOCK = 2,     // diag(G_uu, G_phiphi)
   MODE_RESIDUAL = 3,  // residual (no x)
   MODE_PVJP = 4,      // parameter cotangents (x = v)
-  MODE_ELEM = 5       // element columns of G scattered into a dense matrix
+  MODE_ELEM = 5,      // element columns of G scattered into a dense matrix
+  MODE_QDATA = 6      // 2D Q1/Q2: tangent coefficients at the Gauss points (written to qd_out)
 };
+
+// Tangent coefficients of eq. (G) cached per Gauss point for the 2D row kernel:
+// g(phi~) K or K (volumetric, by the sign of tr e), 2 mu g(phi~), g'(phi) sigma^+ (xx, yy, xy),
+// g''(phi) E^+ + Gc/eps; layout [tile][coefficient][Gauss row][Gauss column][cell of the tile],
+// rowcell_qdata_len values per level
+constexpr int kQCoef = 6;
+long long rowcell_qdata_len(const Geom& g);
 
 template <typename T>
 struct CellArgs {
@@ -63,6 +71,8 @@ struct CellArgs {
   double* partials;    // PVJP: 2 doubles per block
   double* dense;       // ELEM: row-major (d+1)*n_nodes square matrix
   long long ld;        // ELEM: leading dimension
+  const T* qd;         // 2D Q1/Q2: cached tangent coefficients (null: computed from u, phi, phi~)
+  T* qd_out;           // MODE_QDATA: where the coefficients go
 };
 
 // Fused vector epilogues of the owner-computes kernels (tile_kernel.hip)

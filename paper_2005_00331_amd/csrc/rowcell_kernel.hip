@@ -43,9 +43,13 @@ long long rowcell_blocks_2d(const Geom& g) {
   const long long nt = (g.N + kRowOwn - 1) / kRowOwn;
   return nt * nt;
 }
+long long rowcell_qdata_len(const Geom& g) {
+  return rowcell_blocks_2d(g) * kQCoef * (g.k + 1) * (g.k + 1) * kRowCells;
+}
 
 // at most 128 VGPRs: four wavefronts per SIMD (the FP64 products issue well below peak with one or two)
-template <int K, typename T, int MODE, int EPI>
+// QD: the tangent coefficients come from a.qd instead of being computed from u, phi, phi~
+template <int K, typename T, int MODE, int EPI, bool QD>
 __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_eu(4))) void rowcell_kernel_2d(CellArgs<T> a, Epilogue<T> e, Tab2<K + 1, T> tb,
                                                                          const Tables<T>* __restrict__ tabd) {
   constexpr int NP = K + 1;
@@ -81,6 +85,8 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   const T wr = tabd->w[r];
 
   // ---- node row r of the cell: u_0, u_1, phi, phi~, x_0, x_1, x_phi (x zeroed at fixed dofs)
+  constexpr bool LIN = !QD;                // linearisation computed here
+  constexpr bool XIN = MODE != MODE_QDATA;  // a trial vector is applied
   T f[7][NP];
 #pragma unroll
   for (int i0 = 0; i0 < NP; ++i0) {
@@ -88,16 +94,30 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
     for (int q = 0; q < 7; ++q) f[q][i0] = T(0);
     if (valid) {
       const long long nd = (long long)(K * cx + i0) + M * (K * cy + r);
-      const uint8_t mk = a.mask ? a.mask[nd] : (uint8_t)0;
-      f[0][i0] = a.u[nd];
-      f[1][i0] = a.u[nn + nd];
-      f[2][i0] = a.phi[nd];
-      f[3][i0] = a.phit[nd];
-      const T x0 = a.x[nd], x1 = a.x[nn + nd], x2 = a.x[2 * nn + nd];
-      f[4][i0] = (mk & kMaskU) ? T(0) : x0;
-      f[5][i0] = (mk & kMaskU) ? T(0) : x1;
-      f[6][i0] = (mk & kMaskPhi) ? T(0) : x2;
+      if (LIN) {
+        f[0][i0] = a.u[nd];
+        f[1][i0] = a.u[nn + nd];
+        f[2][i0] = a.phi[nd];
+        f[3][i0] = a.phit[nd];
+      }
+      if (XIN) {
+        const uint8_t mk = a.mask ? a.mask[nd] : (uint8_t)0;
+        const T x0 = a.x[nd], x1 = a.x[nn + nd], x2 = a.x[2 * nn + nd];
+        f[4][i0] = (mk & kMaskU) ? T(0) : x0;
+        f[5][i0] = (mk & kMaskU) ? T(0) : x1;
+        f[6][i0] = (mk & kMaskPhi) ? T(0) : x2;
+      }
     }
+  }
+  // cached tangent coefficients of the Gauss row r, stored per tile (halo cells included) so
+  // that every load of a wavefront reads 64 consecutive values
+  const T* qtile = a.qd + (long long)blockIdx.x * kQCoef * NP * NP * kRowCells + (r * NP) * kRowCells + cl;
+  T qc[kQCoef][NP];
+  if (QD) {
+#pragma unroll
+    for (int c = 0; c < kQCoef; ++c)
+#pragma unroll
+      for (int q0 = 0; q0 < NP; ++q0) qc[c][q0] = valid ? qtile[(c * NP * NP + q0) * kRowCells] : T(0);
   }
 
   // ---- owned nodes and their epilogue operands (resid: b, dinv; cheb: r, d, dinv, x), loaded
@@ -211,7 +231,7 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
 
   // ---- linearisation at the Gauss points of row r
   T gu00[NP], gu01[NP], gu10[NP], gu11[NP], phq[NP], ptq[NP];
-  {
+  if (LIN) {
     T t[NP], td[NP];
     xcon(f[0], t, td);
     put(t, td);
@@ -241,6 +261,15 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   T cvol[NP], cdev[NP], sxx[NP], syy[NP], sxy[NP], cpp[NP];
 #pragma unroll
   for (int q0 = 0; q0 < NP; ++q0) {
+    if (QD) {
+      cvol[q0] = qc[0][q0];
+      cdev[q0] = qc[1][q0];
+      sxx[q0] = qc[2][q0];
+      syy[q0] = qc[3][q0];
+      sxy[q0] = qc[4][q0];
+      cpp[q0] = qc[5][q0];
+      continue;
+    }
     const T exx = gu00[q0] * ih, eyy = gu11[q0] * ih;
     const T exy = T(0.5) * (gu01[q0] + gu10[q0]) * ih;
     const T t = exx + eyy;
@@ -257,6 +286,23 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
     syy[q0] = dg * (T(2) * mu * dyy + Kb * tp);
     sxy[q0] = dg * (T(2) * mu * exy);
     cpp[q0] = T(2) * (T(1) - kap) * Ep + Gc / eps;
+  }
+
+  if (MODE == MODE_QDATA) {
+    if (valid) {
+      T* o = a.qd_out + (long long)blockIdx.x * kQCoef * NP * NP * kRowCells + (r * NP) * kRowCells + cl;
+      constexpr int cs = NP * NP * kRowCells;  // coefficient stride
+#pragma unroll
+      for (int q0 = 0; q0 < NP; ++q0) {
+        o[q0 * kRowCells] = cvol[q0];
+        o[cs + q0 * kRowCells] = cdev[q0];
+        o[2 * cs + q0 * kRowCells] = sxx[q0];
+        o[3 * cs + q0 * kRowCells] = syy[q0];
+        o[4 * cs + q0 * kRowCells] = sxy[q0];
+        o[5 * cs + q0 * kRowCells] = cpp[q0];
+      }
+    }
+    return;
   }
 
   // ---- trial functions at the Gauss points of row r
@@ -382,8 +428,15 @@ static hipError_t launch_row_k(int mode, int epi, const CellArgs<T>& a, const Ep
   dim3 grid((unsigned)nb), block(kRowCells * (K + 1));
 #define MFPFF_R(MD, EP)                                                                                 \
   if (mode == MD && epi == EP) {                                                                        \
-    hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP>), grid, block, 0, s, a, e, tb, tabd);           \
+    if (a.qd)                                                                                           \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true>), grid, block, 0, s, a, e, tb, tabd);   \
+    else                                                                                                \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, false>), grid, block, 0, s, a, e, tb, tabd);  \
     return hipGetLastError();                                                                           \
+  }
+  if (mode == MODE_QDATA) {
+    hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MODE_QDATA, EPI_APPLY, false>), grid, block, 0, s, a, e, tb, tabd);
+    return hipGetLastError();
   }
   MFPFF_R(MODE_APPLY, EPI_APPLY)
   MFPFF_R(MODE_APPLY_T, EPI_APPLY)
