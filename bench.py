@@ -13,6 +13,7 @@ timed with HIP events on the library's stream) and the oracle timed on the
 host cores on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -23,6 +24,27 @@ sys.path.insert(0, ROOT)
 
 METRIC = "Jacobian-apply DoFs/s and GMG-GMRES time per Newton step, FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
+COUNTERS = os.path.join(ROOT, "profiles", "rowcell_apply_c2_f64_counters.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2005_00331_amd", "csrc", "rowcell_kernel.hip")
+
+
+def measured_traffic(cfg):
+    """HBM bytes per launch of the finest-level product, from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary (scaled by a 64 MiB copy); None for another workload
+    or when the kernel source has changed since the counters were taken."""
+    if cfg.name != "C2" or not os.path.exists(COUNTERS):
+        return None
+    kv = {}
+    with open(COUNTERS) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, v = line.split(None, 1)
+                kv[k] = v.strip()
+    with open(KERNEL_SRC, "rb") as f:
+        src_hash = hashlib.sha256(f.read()).hexdigest()
+    if kv.get("kernel_source_sha256") != src_hash:
+        return None
+    return float(kv["apply_traffic_bytes"])
 
 
 def algorithmic_bytes_per_apply(dim, n_nodes, elem):
@@ -191,7 +213,7 @@ def main():
                                f"semi-smooth Newton step, {len(levels)}-level GMG-GMRES({cfg.restart}), rtol {cfg.rtol}",
                    "levels": levels, "n_dofs": ctx.n_dofs, "vcycle_prec": cfg.vcycle_prec},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg),
                      "kernel": ((f"rowcell_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>" if cfg.k <= 2 else
                                  f"tile_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>") if cfg.dim == 2 else
                                 f"cell_kernel<{cfg.dim},{cfg.k},double,APPLY>") + " on the finest level",
