@@ -113,6 +113,30 @@ def time_apply(ctx, n_launch=50):
     return e0.elapsed_time(e1) / 1e3 / n_launch
 
 
+def time_solve(cfg, prec):
+    """One linear solve of the workload's seeded right-hand side: set_linearization, then
+    FGMRES to the workload's rtol (after one untimed warm-up solve). FP64 GMRES either way;
+    prec selects the V-cycle precision."""
+    import torch
+    from synth import make_inputs
+    ctx, levels, state = build_context(cfg, prec=prec)
+    rhs = torch.from_numpy(make_inputs(cfg, ("rhs",))["rhs"]).cuda()
+    args = (state["u"], state["phi"], state["phi_old"], state["active"], state["phi_tilde"])
+    ctx.set_linearization(*args)
+    ctx.gmres_solve(rhs, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.set_linearization(*args)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    _, st = ctx.gmres_solve(rhs, raise_on_noconv=False)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ctx.close()
+    return {"ms_setup": (t1 - t0) * 1e3, "ms_solve": (t2 - t1) * 1e3, "ms_total": (t2 - t0) * 1e3,
+            "gmres_iterations": st["iterations"], "converged": st["converged"], "rel_residual": st["rel_residual"]}
+
+
 def cpu_baseline(cfg_name):
     """Oracle Newton step on a bounded sample of the same workload family."""
     import numpy as np
@@ -145,6 +169,7 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison step")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D FP32-vs-FP64 V-cycle solve comparison")
     ap.add_argument("--apply-only", action="store_true",
                     help="only time the finest-level cell kernel (for kernel-trace and counter runs)")
     args = ap.parse_args()
@@ -196,6 +221,15 @@ def main():
                                       "rel_residual": minfos[-1]["rel_residual"]}
         print(f"[bench] mixed newton step {msec * 1e3:.2f} ms", file=sys.stderr, flush=True)
         mctx.close()
+    if not args.no_3d:
+        c3 = CONFIGS["C3"]
+        res = {"workload": f"C3: 3D {c3.N}^3 cells Q{c3.k}, {c3.n_dofs} dofs, seeded random right-hand side, "
+                           f"Chebyshev degree {c3.cheb_degree}, {c3.n_h_levels}-level GMG-GMRES({c3.restart}), "
+                           f"rtol {c3.rtol}"}
+        for prec in ("f64", "f32"):
+            res[prec + "_vcycle"] = time_solve(c3, prec)
+            print(f"[bench] C3 solve, {prec} V-cycle: {res[prec + '_vcycle']}", file=sys.stderr, flush=True)
+        detail["c3_solve"] = res
     out = {
         "metric": METRIC,
         "value": ctx.n_dofs / sec,

@@ -81,8 +81,9 @@ CONFIGS = {
     "C1": Config("C1", 2, 32, 1, 2, active_p=0.10, phi_mode="ones", u_mode="iid", seed_index=1),
     # 2D 256x256 Q2, five-level GMG, full Newton step
     "C2": Config("C2", 2, 256, 2, 5, active_p=0.05, seed_index=2),
-    # 3D 64^3 Q2, FP32 V-cycle with Chebyshev degree 4 inside FP64 GMRES
-    "C3": Config("C3", 3, 64, 2, 5, cheb_degree=4, vcycle_prec="f32", active_p=0.05, seed_index=3),
+    # 3D 64^3 Q2, FP32 V-cycle with Chebyshev degree 4 inside FP64 GMRES; the workload names only
+    # the notch plane, so phi = 1 off the notch (as in C1)
+    "C3": Config("C3", 3, 64, 2, 5, cheb_degree=4, vcycle_prec="f32", active_p=0.05, phi_mode="ones", seed_index=3),
     # 3D 32^3 Q4, four h-levels plus p-coarsening to Q1 on 4^3 (taken as Q4 -> Q2 -> Q1)
     "C4": Config("C4", 3, 32, 4, 4, p_coarse=(2, 1), active_p=0.05, seed_index=4),
     # 3D 48^3 Q2, residual and its hand-written backward (no constraints)
