@@ -92,13 +92,13 @@ def time_newton(ctx, state, steps, warmup):
 
 
 def time_apply(ctx, n_launch=50):
-    """Average duration of one finest-level cell-kernel launch (FP64, full operator).
-    2D: the owner-computes kernel (one launch per product); 3D: the atomic
-    cell kernel alone (accumulate flag, no output initialisation)."""
+    """Average duration of one finest-level product (FP64, full operator), timed with
+    HIP events on the stream the library launches on. 2D: one owner-computes kernel;
+    3D: the cell kernel (element results) plus the node gather."""
     import torch
-    from paper_2005_00331_amd import OP_ACCUMULATE, OP_G
+    from paper_2005_00331_amd import OP_G
     n = ctx.n_dofs
-    op = OP_G if ctx.dim == 2 else (OP_G | OP_ACCUMULATE)
+    op = OP_G
     x = torch.randn(n, dtype=torch.float64, device="cuda")
     y = torch.zeros(n, dtype=torch.float64, device="cuda")
     for _ in range(5):
@@ -250,7 +250,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg),
                      "kernel": ((f"rowcell_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>" if cfg.k <= 2 else
                                  f"tile_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>") if cfg.dim == 2 else
-                                f"cell_kernel<{cfg.dim},{cfg.k},double,APPLY>") + " on the finest level",
+                                f"cell_kernel<{cfg.dim},{cfg.k},double,APPLY> + gather3d_kernel") + " on the finest level",
                      "bytes_per_launch": byts},
         "detail": detail,
     }

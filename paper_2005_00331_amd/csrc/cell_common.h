@@ -98,13 +98,24 @@ struct SharedTables {
 // (or eq. (residual)), and the test integration; returns the LDS tensor of
 // the d+1 cell-local results [comp][cell][node].  All threads of the block
 // must call it (it contains barriers); the caller has synchronised buf0.
-template <int DIM, int K, typename T, int MODE, int NT = kThreads>
+// Tangent coefficients per Gauss point (MODE_QDATA writes them, QD products read them):
+// [0] g(phi~) K or K (by the sign of tr e), [1] 2 mu g(phi~), [2 ..] g'(phi) sigma^+ (00, 11, (22),
+// 01, (02, 12)), [last] g''(phi) E^+ + Gc/eps; qcf points at this block's [coefficient][point][cell]
+template <int DIM>
+__host__ __device__ constexpr int n_qcoef() { return 3 + DIM * (DIM + 1) / 2; }
+
+template <int DIM, int K, typename T, int MODE, int NT = kThreads, bool QD = false>
 __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>& st, const MatParams& mp, T h,
-                                 int tid) {
+                                 int tid, const T* qcf = nullptr, T* qcf_out = nullptr) {
   using S = Shape<DIM, K, NT>;
-  constexpr int NP = S::NP, P = S::P, NPTS = S::NPTS;
+  constexpr int NP = S::NP, P = S::P, NPTS = S::NPTS, CPB = S::CPB;
   constexpr bool XMODE = (MODE == MODE_APPLY || MODE == MODE_APPLY_T || MODE == MODE_BLOCK || MODE == MODE_ELEM);
-  const int nf = XMODE ? (2 * DIM + 3) : DIM + 2;
+  constexpr int NQ = n_qcoef<DIM>();
+  // symmetric index pairs of the stored g'(phi) sigma^+ components
+  constexpr int SI[6] = {0, 1, DIM == 3 ? 2 : 0, 0, 0, 1};
+  constexpr int SJ[6] = {0, 1, DIM == 3 ? 2 : 1, 1, 2, 2};
+  constexpr int NS = DIM * (DIM + 1) / 2;
+  const int nf = (XMODE && QD) ? DIM + 1 : (XMODE ? (2 * DIM + 3) : DIM + 2);
   const bool inb = tid < NPTS;
   const int c = inb ? tid / P : 0;
   const int p = inb ? tid % P : 0;
@@ -126,7 +137,131 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
 
   // ---- quadrature-point physics -> flux tensors in W:
   // [cc*DIM + m] u-test component cc along m; [DIM*DIM + m] phi gradient; [DIM*DIM + DIM] phi value
-  if (inb) {
+  if constexpr (MODE == MODE_QDATA) {
+    // fields u_0..u_{d-1}, phi, phi~ interpolated in V: store the tangent coefficients
+    if (inb) {
+      const int o = c * P + p;
+      T gu[DIM][DIM];
+#pragma unroll
+      for (int cc = 0; cc < DIM; ++cc)
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) gu[cc][m] = coll_deriv<NP, P, NPTS, T>(V + cc * NPTS, st.C, m, c, p) * ih;
+      const T ph = V[DIM * NPTS + o];
+      const T pt = V[(DIM + 1) * NPTS + o];
+      T e[DIM][DIM];
+      T t = 0;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i) {
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) e[i][j] = T(0.5) * (gu[i][j] + gu[j][i]);
+        t += e[i][i];
+      }
+      const bool H = t >= T(0);
+      const T tp = H ? t : T(0);
+      T devdev = 0;
+#pragma unroll
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) {
+          const T dv = e[i][j] - (i == j ? t / T(DIM) : T(0));
+          devdev += dv * dv;
+        }
+      const T Ep = T(0.5) * Kb * tp * tp + mu * devdev;
+      const T gt = (T(1) - kap) * pt * pt + kap;
+      const T dg = T(2) * (T(1) - kap) * ph;
+      const T ddg = T(2) * (T(1) - kap);
+      T* q = qcf_out + (long long)p * CPB + c;
+      constexpr int QS = P * CPB;  // coefficient stride
+      q[0] = H ? gt * Kb : Kb;
+      q[QS] = gt * T(2) * mu;
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const int i = SI[k], j = SJ[k];
+        const T spij = T(2) * mu * (e[i][j] - (i == j ? t / T(DIM) : T(0))) + (i == j ? Kb * tp : T(0));
+        q[(2 + k) * QS] = dg * spij;
+      }
+      q[(NQ - 1) * QS] = ddg * Ep + Gc / eps;
+    }
+    return V;
+  }
+
+  if constexpr (XMODE && QD) {
+    // products from the cached tangent coefficients: only x is interpolated (fields x_0..x_d);
+    // the fluxes stay in registers and pass through LDS one test component at a time, so the
+    // block needs d+1 field slots per buffer instead of d^2+d+1
+    T flux[DIM + 1][DIM + 1] = {};  // [test component][direction]; [d][d] = phi value flux
+    const int o = c * P + p;
+    if (inb) {
+    T jxw = st.W[p % NP] * st.W[(p / NP) % NP] * h * h;
+    if (DIM == 3) jxw *= st.W[p / (NP * NP)] * h;
+    const T* q = qcf + (long long)p * CPB + c;
+    constexpr int QS = P * CPB;
+    const T cvol = q[0], cdev = q[QS], cpp = q[(NQ - 1) * QS];
+    T gsp[DIM][DIM];
+    if (MODE != MODE_BLOCK) {
+#pragma unroll
+      for (int k = 0; k < NS; ++k) {
+        const T v = q[(2 + k) * QS];
+        gsp[SI[k]][SJ[k]] = v;
+        gsp[SJ[k]][SI[k]] = v;
+      }
+    }
+    T gx[DIM][DIM];
+#pragma unroll
+    for (int cc = 0; cc < DIM; ++cc)
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) gx[cc][m] = coll_deriv<NP, P, NPTS, T>(V + cc * NPTS, st.C, m, c, p) * ih;
+    const T dph = V[DIM * NPTS + o];
+    T de[DIM][DIM];
+    T dt = 0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i) {
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) de[i][j] = T(0.5) * (gx[i][j] + gx[j][i]);
+      dt += de[i][i];
+    }
+    const T vol = cvol * dt;
+    T Su[DIM][DIM];
+    T spde = 0;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j) {
+        Su[i][j] = cdev * (de[i][j] - (i == j ? dt / T(DIM) : T(0))) + (i == j ? vol : T(0));
+        if (MODE == MODE_APPLY || MODE == MODE_ELEM) spde += gsp[i][j] * de[i][j];
+        if (MODE == MODE_APPLY_T) Su[i][j] += dph * gsp[i][j];
+      }
+    const T fval = cpp * dph + spde;
+    T fgrad[DIM];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) fgrad[m] = Gc * eps * coll_deriv<NP, P, NPTS, T>(V + DIM * NPTS, st.C, m, c, p) * ih;
+    const T jg = jxw * ih;
+#pragma unroll
+    for (int cc = 0; cc < DIM; ++cc)
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) flux[cc][m] = jg * Su[cc][m];
+#pragma unroll
+    for (int m = 0; m < DIM; ++m) flux[DIM][m] = jg * fgrad[m];
+    flux[DIM][DIM] = jxw * fval;
+    }
+    __syncthreads();  // every read of V is done
+#pragma unroll
+    for (int tc = 0; tc <= DIM; ++tc) {
+      if (inb) {
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) W[m * NPTS + o] = flux[tc][m];
+      }
+      __syncthreads();
+      if (inb) {
+        T sv = (tc == DIM) ? flux[DIM][DIM] : T(0);
+#pragma unroll
+        for (int m = 0; m < DIM; ++m) sv += coll_deriv<NP, P, NPTS, T>(W + m * NPTS, st.Ct, m, c, p);
+        V[tc * NPTS + o] = sv;
+      }
+      __syncthreads();
+    }
+  }
+  if (inb && !(XMODE && QD)) {
     const int o = c * P + p;
     T jxw = st.W[p % NP] * st.W[(p / NP) % NP] * h * h;
     if (DIM == 3) jxw *= st.W[p / (NP * NP)] * h;
@@ -225,6 +360,7 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
     for (int m = 0; m < DIM; ++m) W[(DIM * DIM + m) * NPTS + o] = jg * fgrad[m];
     W[(DIM * DIM + DIM) * NPTS + o] = jxw * fval;
   }
+  if constexpr (!(XMODE && QD)) {
   __syncthreads();
 
   // ---- transposed collocation: s_t(q') = value flux + sum_m C^T along m of the grad flux
@@ -239,6 +375,7 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
     }
   }
   __syncthreads();
+  }
 
   // ---- integrate: d sweeps with B^T
   sweep<NP, P, NPTS, T>(V, W, DIM + 1, st.Bt, 0, tid);

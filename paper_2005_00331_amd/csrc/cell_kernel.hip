@@ -17,11 +17,14 @@
 
 namespace mfpff {
 
-template <int DIM, int K, typename T, int MODE>
+// QD: products from the cached tangent coefficients (a.qd), so only x is gathered;
+// MODE_QDATA writes those coefficients (a.qd_out) from u, phi, phi~
+template <int DIM, int K, typename T, int MODE, bool QD = false>
 __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tables<T>* __restrict__ tab) {
   using S = Shape<DIM, K>;
-  constexpr int NP = S::NP, P = S::P, CPB = S::CPB, NPTS = S::NPTS, NBUF = S::NBUF;
+  constexpr int NP = S::NP, P = S::P, CPB = S::CPB, NPTS = S::NPTS;
   constexpr bool XMODE = (MODE == MODE_APPLY || MODE == MODE_APPLY_T || MODE == MODE_BLOCK || MODE == MODE_ELEM);
+  constexpr int NBUF = (XMODE && QD) ? DIM + 1 : S::NBUF;  // field slots per LDS buffer
   __shared__ SharedTables<NP, T> st;
   __shared__ T buf0[NBUF * NPTS];
   __shared__ T buf1[NBUF * NPTS];
@@ -76,11 +79,13 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
         }
         buf0[cc * NPTS + o] = v;
       }
+      if (!QD) {
 #pragma unroll
-      for (int cc = 0; cc < DIM; ++cc) buf0[(DIM + 1 + cc) * NPTS + o] = valid ? a.u[cc * nn + node] : T(0);
-      buf0[(2 * DIM + 1) * NPTS + o] = valid ? a.phi[node] : T(0);
-      buf0[(2 * DIM + 2) * NPTS + o] = valid ? a.phit[node] : T(0);
-    } else if (MODE == MODE_RESIDUAL) {
+        for (int cc = 0; cc < DIM; ++cc) buf0[(DIM + 1 + cc) * NPTS + o] = valid ? a.u[cc * nn + node] : T(0);
+        buf0[(2 * DIM + 1) * NPTS + o] = valid ? a.phi[node] : T(0);
+        buf0[(2 * DIM + 2) * NPTS + o] = valid ? a.phit[node] : T(0);
+      }
+    } else if (MODE == MODE_RESIDUAL || MODE == MODE_QDATA) {
 #pragma unroll
       for (int cc = 0; cc < DIM; ++cc) buf0[cc * NPTS + o] = valid ? a.u[cc * nn + node] : T(0);
       buf0[DIM * NPTS + o] = valid ? a.phi[node] : T(0);
@@ -138,7 +143,27 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
       a.partials[2 * blockIdx.x + 1] = sred[kThreads];
     }
   } else {
-    const T* R = cell_compute<DIM, K, T, MODE>(buf0, buf1, st, a.m, (T)g.h, tid);
+    constexpr int NQ = n_qcoef<DIM>();
+    const long long qoff = (long long)blockIdx.x * NQ * P * CPB;
+    const T* R = cell_compute<DIM, K, T, MODE, kThreads, QD>(buf0, buf1, st, a.m, (T)g.h, tid, QD ? a.qd + qoff : nullptr,
+                                                             MODE == MODE_QDATA ? a.qd_out + qoff : nullptr);
+    if constexpr (MODE == MODE_QDATA) return;
+
+    if constexpr (MODE == MODE_APPLY || MODE == MODE_APPLY_T || MODE == MODE_BLOCK) {
+      if (a.elem) {
+        // one coalesced copy of the block's results, laid out [block][component][point][cell of
+        // the block] so that the node gather reads runs of consecutive cells
+        constexpr int NC = DIM + 1;
+        const long long cell0 = (long long)blockIdx.x * CPB;
+        T* eb = a.elem + cell0 * NC * P;
+        for (int idx = tid; idx < CPB * NC * P; idx += blockDim.x) {
+          const int rem = idx / CPB, c2 = idx - rem * CPB;
+          const int cc = rem / P;
+          if (cell0 + c2 < ncells) eb[idx] = R[cc * NPTS + c2 * P + (rem - cc * P)];
+        }
+        return;
+      }
+    }
 
     // ---------------- scatter
     if (valid) {
@@ -320,10 +345,24 @@ static hipError_t launch_dk(int mode, const CellArgs<T>& a, const Tables<T>* tab
   if (nb <= 0) return hipSuccess;
   if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid((unsigned)nb), block(kThreads);
+  const bool qd = DIM == 3 && a.qd != nullptr;
   switch (mode) {
-    case MODE_APPLY: hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_APPLY>), grid, block, 0, s, a, tab); break;
-    case MODE_APPLY_T: hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_APPLY_T>), grid, block, 0, s, a, tab); break;
-    case MODE_BLOCK: hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_BLOCK>), grid, block, 0, s, a, tab); break;
+    case MODE_APPLY:
+      if (qd) hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_APPLY, true>), grid, block, 0, s, a, tab);
+      else hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_APPLY>), grid, block, 0, s, a, tab);
+      break;
+    case MODE_APPLY_T:
+      if (qd) hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_APPLY_T, true>), grid, block, 0, s, a, tab);
+      else hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_APPLY_T>), grid, block, 0, s, a, tab);
+      break;
+    case MODE_BLOCK:
+      if (qd) hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_BLOCK, true>), grid, block, 0, s, a, tab);
+      else hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_BLOCK>), grid, block, 0, s, a, tab);
+      break;
+    case MODE_QDATA:
+      if (DIM != 3 || !a.qd_out) return hipErrorInvalidValue;
+      hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_QDATA>), grid, block, 0, s, a, tab);
+      break;
     default:
       if constexpr (std::is_same<T, double>::value) {
         if (mode == MODE_RESIDUAL) hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_RESIDUAL>), grid, block, 0, s, a, tab);
@@ -361,6 +400,122 @@ hipError_t launch_diag(const CellArgs<T>& a, const Tables<T>* tab, hipStream_t s
 #undef MFPFF_CASE
   return hipErrorInvalidValue;
 }
+
+// ---------------------------------------------------------------- node gather (3D)
+// Every node adds the results of the (at most 8) cells that contain it, in a fixed order
+// (z, then y, then x neighbour), and applies the epilogue of the operation:
+//   EPI_APPLY: y = G^ x;  EPI_RESID: r = b - G^ x (optional Chebyshev start);
+//   EPI_CHEB:  d = c1 d + c2 D^-1 (r - G^_blk z), z' = z + d (optional xout = xacc + z').
+// Fixed rows take the identity.  Workgroups are mapped so that each XCD works on one
+// contiguous range of nodes (its L2 then holds the element lines its nodes share).
+long long cell_qdata_len(const Geom& g) {
+  const long long P = (long long)(g.k + 1) * (g.k + 1) * (g.k + 1);
+  return cell_blocks(g, MODE_APPLY) * cpb_of(g.dim, g.k) * P * n_qcoef<3>();
+}
+
+long long elem_len(const Geom& g) {
+  const long long P = (long long)(g.k + 1) * (g.k + 1) * (g.k + 1);
+  return cell_blocks(g, MODE_APPLY) * cpb_of(g.dim, g.k) * (g.dim + 1) * P;
+}
+
+template <int K, typename T, int EPI>
+__global__ __launch_bounds__(kThreads) void gather3d_kernel(const T* __restrict__ E, CellArgs<T> a, Epilogue<T> e) {
+  constexpr int NP = K + 1, P = NP * NP * NP, NC = 4, CPB = kThreads / P;
+  const Geom g = a.g;
+  const int N = g.N;
+  const long long M = g.M, nn = g.n_nodes;
+  // XCD-aware block order: hardware block b runs on XCD b % 8
+  const unsigned G = gridDim.x, b = blockIdx.x, x = b % 8, q = G / 8, rem = G % 8;
+  const unsigned lb = x * q + min(x, rem) + b / 8;
+  const long long node = (long long)lb * blockDim.x + threadIdx.x;
+  if (node >= nn) return;
+  const int ix = (int)(node % M), iy = (int)((node / M) % M), iz = (int)(node / (M * M));
+  int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
+  auto axis = [&](int i, int (&cc)[2], int (&li)[2]) -> int {
+    const int c = i / K, r = i - c * K;
+    if (r != 0) {
+      cc[0] = c;
+      li[0] = r;
+      return 1;
+    }
+    int n = 0;
+    if (c - 1 >= 0) {
+      cc[n] = c - 1;
+      li[n] = K;
+      ++n;
+    }
+    if (c < N) {
+      cc[n] = c;
+      li[n] = 0;
+      ++n;
+    }
+    return n;
+  };
+  const int nx = axis(ix, cx, lx), ny = axis(iy, cy, ly), nz = axis(iz, cz, lz);
+  T sum[NC] = {T(0), T(0), T(0), T(0)};
+  for (int kz = 0; kz < nz; ++kz)
+    for (int ky = 0; ky < ny; ++ky)
+      for (int kx = 0; kx < nx; ++kx) {
+        const long long cell = cx[kx] + (long long)N * (cy[ky] + (long long)N * cz[kz]);
+        const int p = lx[kx] + NP * (ly[ky] + NP * lz[kz]);
+        const long long blk = cell / CPB;
+        const T* src = E + (blk * NC * P + p) * CPB + (cell - blk * CPB);
+#pragma unroll
+        for (int cc = 0; cc < NC; ++cc) sum[cc] += src[cc * P * CPB];
+      }
+  const uint8_t m = a.mask ? a.mask[node] : (uint8_t)0;
+#pragma unroll
+  for (int cc = 0; cc < NC; ++cc) {
+    const long long idx = cc * nn + node;
+    const bool fixed = (cc < 3) ? (m & kMaskU) : (m & kMaskPhi);
+    const T xo = (EPI == EPI_CHEB || fixed) ? a.x[idx] : T(0);
+    const T gx = fixed ? xo : sum[cc];
+    if (EPI == EPI_APPLY) {
+      e.y[idx] = gx;
+    } else if (EPI == EPI_RESID) {
+      const T rv = e.b[idx] - gx;
+      e.y[idx] = rv;
+      if (e.z0) {
+        const T zv = e.dinv[idx] * rv * (cc < 3 ? e.ith_u : e.ith_p);
+        e.z0[idx] = zv;
+        e.d0[idx] = zv;
+      }
+    } else {
+      const bool isu = cc < 3;
+      const T dn = (isu ? e.c1u : e.c1p) * e.d[idx] + (isu ? e.c2u : e.c2p) * e.dinv[idx] * (e.r[idx] - gx);
+      e.d[idx] = dn;
+      const T zn = xo + dn;
+      e.y[idx] = zn;
+      if (e.xout) e.xout[idx] = e.xacc[idx] + zn;
+    }
+  }
+}
+
+template <int K, typename T>
+static hipError_t launch_gk(int epi, const T* elem, const CellArgs<T>& a, const Epilogue<T>& e, hipStream_t s) {
+  const long long nb = (a.g.n_nodes + kThreads - 1) / kThreads;
+  if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
+  dim3 grid((unsigned)nb), block(kThreads);
+  if (epi == EPI_APPLY) hipLaunchKernelGGL((gather3d_kernel<K, T, EPI_APPLY>), grid, block, 0, s, elem, a, e);
+  else if (epi == EPI_RESID) hipLaunchKernelGGL((gather3d_kernel<K, T, EPI_RESID>), grid, block, 0, s, elem, a, e);
+  else if (epi == EPI_CHEB) hipLaunchKernelGGL((gather3d_kernel<K, T, EPI_CHEB>), grid, block, 0, s, elem, a, e);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_gather_3d(int epi, const T* elem, const CellArgs<T>& a, const Epilogue<T>& e, hipStream_t s) {
+  if (a.g.dim != 3) return hipErrorInvalidValue;
+  switch (a.g.k) {
+    case 1: return launch_gk<1, T>(epi, elem, a, e, s);
+    case 2: return launch_gk<2, T>(epi, elem, a, e, s);
+    case 3: return launch_gk<3, T>(epi, elem, a, e, s);
+    case 4: return launch_gk<4, T>(epi, elem, a, e, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_gather_3d<double>(int, const double*, const CellArgs<double>&, const Epilogue<double>&, hipStream_t);
+template hipError_t launch_gather_3d<float>(int, const float*, const CellArgs<float>&, const Epilogue<float>&, hipStream_t);
 
 template hipError_t launch_cell<double>(int, const CellArgs<double>&, const Tables<double>*, hipStream_t);
 template hipError_t launch_cell<float>(int, const CellArgs<float>&, const Tables<float>*, hipStream_t);

@@ -102,6 +102,8 @@ struct mfpff_ctx {
   double* t64b = nullptr;
   float* t32a = nullptr;
   float* t32b = nullptr;
+  // 3D: cell results of one product, gathered per node (element buffer, sized for the largest level)
+  void* elem = nullptr;
   // coarse solve
   int nu0 = 0, np0 = 0;
   double* dense = nullptr;
@@ -303,6 +305,19 @@ void launch_2d(mfpff_ctx* c, const Level& L, int mode, int epi, const CellArgs<T
   else HIPCHK(launch_tile_2d<T>(mode, epi, a, e, tab<T>(c, L.g.k), c->s));
 }
 
+// one product with its epilogue: 2D owner-computes kernels; 3D cell kernel into the element
+// buffer, then the node gather
+template <typename T>
+void launch_fused(mfpff_ctx* c, const Level& L, int mode, int epi, CellArgs<T> a, const Epilogue<T>& e) {
+  if (c->dim == 2) {
+    launch_2d<T>(c, L, mode, epi, a, e);
+    return;
+  }
+  a.elem = (T*)c->elem;
+  HIPCHK(launch_cell<T>(mode, a, tab<T>(c, L.g.k), c->s));
+  HIPCHK(launch_gather_3d<T>(epi, (const T*)c->elem, a, e, c->s));
+}
+
 // y = op(G^) x on level l, or y = b - G^ x when b != null (op = G);
 // accumulate: y += P op(G) P x without initialising y (atomic cell kernel)
 template <typename T>
@@ -310,16 +325,12 @@ void apply_op(mfpff_ctx* c, int l, int mode, const T* x, T* y, const T* b, bool 
   Level& L = c->lv[l];
   const T scale = b ? T(-1) : T(1);
   CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), x, y, scale);
-  if (c->dim == 2 && !accumulate) {
+  if (!accumulate) {
     Epilogue<T> e{};
     e.y = y;
     e.b = b;
-    launch_2d<T>(c, L, mode, b ? EPI_RESID : EPI_APPLY, a, e);
+    launch_fused<T>(c, L, mode, b ? EPI_RESID : EPI_APPLY, a, e);
     return;
-  }
-  if (!accumulate) {
-    k_mask_init<T>(y, b, x, L.mask, L.nn, c->dim, scale, c->s);
-    LAUNCHCHK();
   }
   HIPCHK(launch_cell<T>(mode, a, tab<T>(c, L.g.k), c->s));
 }
@@ -328,24 +339,16 @@ void apply_op(mfpff_ctx* c, int l, int mode, const T* x, T* y, const T* b, bool 
 template <typename T>
 void op_resid(mfpff_ctx* c, int l, const T* b, const T* x, T* r, T* z0, T* d0) {
   Level& L = c->lv[l];
-  if (c->dim == 2) {
-    CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), x, r, T(-1));
-    Epilogue<T> e{};
-    e.y = r;
-    e.b = b;
-    e.z0 = z0;
-    e.d0 = d0;
-    e.dinv = level_dinv<T>(L);
-    e.ith_u = (T)L.ith_u;
-    e.ith_p = (T)L.ith_p;
-    launch_2d<T>(c, L, MODE_APPLY, EPI_RESID, a, e);
-    return;
-  }
-  apply_op<T>(c, l, MODE_APPLY, x, r, b);
-  if (z0) {
-    k_cheb_init<T>(z0, d0, r, level_dinv<T>(L), L.nn, c->dim, (T)L.ith_u, (T)L.ith_p, c->s);
-    LAUNCHCHK();
-  }
+  CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), x, r, T(-1));
+  Epilogue<T> e{};
+  e.y = r;
+  e.b = b;
+  e.z0 = z0;
+  e.d0 = d0;
+  e.dinv = level_dinv<T>(L);
+  e.ith_u = (T)L.ith_u;
+  e.ith_p = (T)L.ith_p;
+  launch_fused<T>(c, L, MODE_APPLY, EPI_RESID, a, e);
 }
 
 // Chebyshev step i (1-based): zout = zin + d', d' = c1 d + c2 D^-1 (r - A_blk zin); optional xout = xacc + zout
@@ -353,25 +356,19 @@ template <typename T>
 void op_cheb_step(mfpff_ctx* c, int l, int i, const T* zin, T* zout, const T* r, T* d, T* t, const T* xacc, T* xout) {
   Level& L = c->lv[l];
   const T c1u = (T)L.c1u[i - 1], c2u = (T)L.c2u[i - 1], c1p = (T)L.c1p[i - 1], c2p = (T)L.c2p[i - 1];
-  if (c->dim == 2) {
-    CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), zin, zout, T(1));
-    Epilogue<T> e{};
-    e.y = zout;
-    e.dinv = level_dinv<T>(L);
-    e.r = r;
-    e.d = d;
-    e.c1u = c1u;
-    e.c2u = c2u;
-    e.c1p = c1p;
-    e.c2p = c2p;
-    e.xacc = xacc;
-    e.xout = xout;
-    launch_2d<T>(c, L, MODE_BLOCK, EPI_CHEB, a, e);
-    return;
-  }
-  apply_op<T>(c, l, MODE_BLOCK, zin, t, nullptr);
-  k_cheb_update<T>(zout, d, zin, r, t, level_dinv<T>(L), L.nn, c->dim, c1u, c2u, c1p, c2p, xacc, xout, c->s);
-  LAUNCHCHK();
+  CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), zin, zout, T(1));
+  Epilogue<T> e{};
+  e.y = zout;
+  e.dinv = level_dinv<T>(L);
+  e.r = r;
+  e.d = d;
+  e.c1u = c1u;
+  e.c2u = c2u;
+  e.c1p = c1p;
+  e.c2p = c2p;
+  e.xacc = xacc;
+  e.xout = xout;
+  launch_fused<T>(c, L, MODE_BLOCK, EPI_CHEB, a, e);
 }
 
 // x = diag(C_u, C_phi) r (Chebyshev from zero); work vectors zA, zB, d, t (x distinct from them)
@@ -827,11 +824,13 @@ void set_point(mfpff_ctx* c, const double* u, const double* phi, const double* p
     if (!L.qd) continue;
     CellArgs<double> a = cell_args<double>(c, L, L.lin, nullptr, nullptr, 1.0);
     a.qd_out = L.qd;
-    launch_2d<double>(c, L, MODE_QDATA, EPI_APPLY, a, Epilogue<double>{});
+    if (d == 2) launch_2d<double>(c, L, MODE_QDATA, EPI_APPLY, a, Epilogue<double>{});
+    else HIPCHK(launch_cell<double>(MODE_QDATA, a, c->tab64[L.g.k], c->s));
     if (L.qd32) {
       CellArgs<float> a32 = cell_args<float>(c, L, L.lin32, nullptr, nullptr, 1.0f);
       a32.qd_out = L.qd32;
-      launch_2d<float>(c, L, MODE_QDATA, EPI_APPLY, a32, Epilogue<float>{});
+      if (d == 2) launch_2d<float>(c, L, MODE_QDATA, EPI_APPLY, a32, Epilogue<float>{});
+      else HIPCHK(launch_cell<float>(MODE_QDATA, a32, c->tab32[L.g.k], c->s));
     }
     L.qd_ok = true;
   }
@@ -943,6 +942,7 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
   mfpff_status st = run(c, [&]() -> mfpff_status {
     const int d = c->dim;
     c->lv.resize(p.n_levels);
+    size_t elem_bytes = 0;
     for (int l = 0; l < p.n_levels; ++l) {
       Level& L = c->lv[l];
       L.g = make_geom(d, p.level_N[l], p.level_k[l]);
@@ -956,8 +956,12 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
         L.lin32 = dalloc<float>((size_t)(d + 2) * L.nn);
         L.dinv32 = dalloc<float>(L.n);
       }
-      if (d == 2 && L.g.k <= 2) {
-        const size_t nq = (size_t)rowcell_qdata_len(L.g);
+      if (d == 3) {
+        const size_t eb = (size_t)elem_len(L.g) * sizeof(double);
+        if (eb > elem_bytes) elem_bytes = eb;
+      }
+      if ((d == 2 && L.g.k <= 2) || d == 3) {
+        const size_t nq = (size_t)(d == 2 ? rowcell_qdata_len(L.g) : cell_qdata_len(L.g));
         L.qd = dalloc<double>(nq);
         if (c->f32) L.qd32 = dalloc<float>(nq);
       }
@@ -993,6 +997,7 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
         HIPCHK(hipMemcpy(c->tab32[k], &tf, sizeof(tf), hipMemcpyHostToDevice));
       }
     }
+    if (elem_bytes) c->elem = dalloc<char>(elem_bytes);
     Level& F = c->lv[c->L];
     const long long nF = F.n;
     c->t64a = dalloc<double>(nF);
@@ -1070,7 +1075,7 @@ void mfpff_destroy(mfpff_ctx* c) {
     F(c->tab64[k]);
     F(c->tab32[k]);
   }
-  void* ps[] = {c->finite_flag, c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
+  void* ps[] = {c->elem, c->finite_flag, c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
                 c->WpT, c->Gpu, c->cs_in, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lst, c->part, c->V,
                 c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out};
   for (void* p : ps) F(p);

@@ -47,7 +47,7 @@ enum CellMode : int {
   MODE_RESIDUAL = 3,  // residual (no x)
   MODE_PVJP = 4,      // parameter cotangents (x = v)
   MODE_ELEM = 5,      // element columns of G scattered into a dense matrix
-  MODE_QDATA = 6      // 2D Q1/Q2: tangent coefficients at the Gauss points (written to qd_out)
+  MODE_QDATA = 6      // tangent coefficients at the Gauss points (written to qd_out): 2D Q1/Q2, 3D
 };
 
 // Tangent coefficients of eq. (G) cached per Gauss point for the 2D row kernel:
@@ -73,6 +73,7 @@ struct CellArgs {
   long long ld;        // ELEM: leading dimension
   const T* qd;         // 2D Q1/Q2: cached tangent coefficients (null: computed from u, phi, phi~)
   T* qd_out;           // MODE_QDATA: where the coefficients go
+  T* elem;             // 3D operator modes: cell results [cell][component][point] instead of atomics
 };
 
 // Fused vector epilogues of the owner-computes kernels (tile_kernel.hip)
@@ -91,6 +92,11 @@ struct Epilogue {
   const T* xacc;        // cheb: optional xout = xacc + z'
   T* xout;
 };
+// node gather of the 3D element results (cell_kernel with a.elem) with a fused epilogue
+template <typename T>
+hipError_t launch_gather_3d(int epi, const T* elem, const CellArgs<T>& a, const Epilogue<T>& e, hipStream_t s);
+long long elem_len(const Geom& g);  // values in the element buffer of one level
+long long cell_qdata_len(const Geom& g);  // 3D: values of the cached tangent coefficients of one level
 template <typename T>
 hipError_t launch_tile_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<T>* tab, hipStream_t s);
 long long tile_blocks_2d(const Geom& g);
