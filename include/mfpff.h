@@ -110,7 +110,9 @@ typedef struct {
 
 /* Build the level hierarchy, 1D tables and all device storage for a problem
  * (the mesh set-up of the solver).  `hip_stream` is a hipStream_t (NULL:
- * the default stream).  On success *out owns every device allocation. */
+ * the default stream).  On success *out owns every device allocation.
+ * MFPFF_ERR_ARG for an invalid description, including a level with 2^31 or
+ * more dofs; MFPFF_ERR_OOM when device memory runs out. */
 mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx** out);
 
 /* Release a context and everything it owns.  NULL is ignored. */

@@ -64,12 +64,13 @@ template <int DIM, int K>
 __device__ __forceinline__ long long node_of(const Geom& g, long long cell, int p) {
   constexpr int NP = K + 1;
   const long long N = g.N, M = g.M;
-  const long long cx = cell % N;
-  const long long cy = (cell / N) % N;
+  const unsigned uc = (unsigned)cell, un = (unsigned)N, q1 = uc / un;
+  const long long cx = uc - q1 * un;
+  const long long cy = q1 % un;
   const int i0 = p % NP, i1 = (p / NP) % NP;
   long long node = (K * cx + i0) + M * (K * cy + i1);
   if (DIM == 3) {
-    const long long cz = cell / (N * N);
+    const long long cz = q1 / un;
     const int i2 = p / (NP * NP);
     node += M * M * (K * cz + i2);
   }

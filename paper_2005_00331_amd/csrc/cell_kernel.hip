@@ -429,7 +429,8 @@ __global__ __launch_bounds__(kThreads) void gather3d_kernel(const T* __restrict_
   const unsigned lb = x * q + min(x, rem) + b / 8;
   const long long node = (long long)lb * blockDim.x + threadIdx.x;
   if (node >= nn) return;
-  const int ix = (int)(node % M), iy = (int)((node / M) % M), iz = (int)(node / (M * M));
+  const unsigned um = (unsigned)M, q1 = (unsigned)node / um, q2 = q1 / um;
+  const int ix = (int)((unsigned)node - q1 * um), iy = (int)(q1 - q2 * um), iz = (int)q2;
   int cx[2], lx[2], cy[2], ly[2], cz[2], lz[2];
   auto axis = [&](int i, int (&cc)[2], int (&li)[2]) -> int {
     const int c = i / K, r = i - c * K;

@@ -19,7 +19,7 @@ constexpr int TB = 32;
 __global__ void set_fixed_diag_kernel(double* A, long long ld, const uint8_t* mask, long long nn, int dim) {
   const long long n = (long long)(dim + 1) * nn;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const long long comp = i / nn;
+    const long long comp = udiv(i, nn);
     const uint8_t m = mask[i - comp * nn];
     const bool f = comp < dim ? (m & kMaskU) : (m & kMaskPhi);
     if (f) A[i * ld + i] = 1.0;

@@ -413,8 +413,21 @@ void transfer(mfpff_ctx* c, int l, int dir, const T* in, T* out, bool add, T* ta
   Level& F = c->lv[l];
   Level& C = c->lv[l - 1];
   const int d = c->dim, nc = d + 1;
-  if (dir == 0) {
+  if (dir == 0 && d == 2) {
     k_prolong<T>(out, in, F.P1.s, C.mask, F.mask, F.g, C.g, add, c->s);
+  } else if (dir == 0) {
+    // 3D: axis passes (coarse mask on the first, fine mask and accumulation on the last)
+    long long dims[3] = {C.g.M, C.g.M, C.g.M};
+    const T* src = in;
+    T* bufs[2] = {ta, tb};
+    for (int ax = 0; ax < d; ++ax) {
+      const bool first = ax == 0, last = ax == d - 1;
+      T* o = last ? out : bufs[ax & 1];
+      k_axis_apply<T>(o, src, F.P1.s, ax, d, dims, nc, first ? C.mask : nullptr, last ? F.mask : nullptr, c->s,
+                      last && add);
+      dims[ax] = F.g.M;
+      src = o;
+    }
   } else {
     long long dims[3] = {F.g.M, F.g.M, F.g.M};
     const T* src = in;
@@ -948,6 +961,7 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
       L.g = make_geom(d, p.level_N[l], p.level_k[l]);
       L.nn = L.g.n_nodes;
       L.n = (long long)(d + 1) * L.nn;
+      if (L.n >= (1LL << 31)) throw StatusError{MFPFF_ERR_ARG, "a level with 2^31 or more dofs is not supported"};
       L.lin = dalloc<double>((size_t)(d + 2) * L.nn);
       L.mask = dalloc<uint8_t>(L.nn);
       L.dinv = dalloc<double>(L.n);

@@ -7,6 +7,11 @@ namespace mfpff {
 
 constexpr int kMaxDeg = 4;
 constexpr int kThreads = 256;
+// Index arithmetic in the kernels divides in 32 bits (a 64-bit division by a runtime value costs
+// ~100 instructions on gfx950); mfpff_create rejects levels with 2^31 or more dofs.
+__host__ __device__ __forceinline__ unsigned udiv(unsigned long long a, unsigned long long b) {
+  return (unsigned)a / (unsigned)b;
+}
 
 // Geometry of one structured level: unit square/cube, N cells per direction,
 // Q_k with equispaced nodes, M = k*N + 1 nodes per direction.
@@ -186,10 +191,11 @@ struct Sparse1D {
   const float* valf;
 };
 // in_mask: zero inputs at fixed dofs (input must be a whole level vector);
-// out_mask: zero outputs at fixed dofs (output must be a whole level vector)
+// out_mask: zero outputs at fixed dofs (output must be a whole level vector);
+// add: out += result instead (fixed outputs left unchanged)
 template <typename T>
 void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, const long long* dims_in,
-                  int ncomp, const uint8_t* in_mask, const uint8_t* out_mask, hipStream_t s);
+                  int ncomp, const uint8_t* in_mask, const uint8_t* out_mask, hipStream_t s, bool add = false);
 // out (fine level) = / += P~ xc: single pass, (kc+1)^d coarse terms per fine node
 template <typename T>
 void k_prolong(T* out, const T* xc, const Sparse1D& P, const uint8_t* mask_c, const uint8_t* mask_f, const Geom& gf,

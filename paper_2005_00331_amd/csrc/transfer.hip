@@ -1,10 +1,12 @@
 // Level transfers (gfx950).  The prolongation between nested structured
 // levels is the Kronecker product over axes of one 1D interpolation matrix
 // (coarse basis functions evaluated at fine nodes), applied per component;
-// restriction is its transpose.  Both are applied axis by axis: each pass
+// restriction is its transpose.  Both can be applied axis by axis: each pass
 // maps one axis through a padded row-sparse 1D matrix (thread per output
 // entry, gather, no atomics), so a 3D transfer reads each input a few times
-// instead of (2k+1)^3 times.
+// instead of (k+1)^3 times; the masks are fused into the first and last pass.
+// In 2D the prolongation is one gather pass (prolong_kernel), which saves a
+// launch on the small levels.
 #include "internal.h"
 
 namespace mfpff {
@@ -21,7 +23,7 @@ __device__ __forceinline__ bool comp_fixed(const uint8_t* mask, long long node, 
 template <typename T>
 __global__ void axis_apply_kernel(T* out, const T* in, const int* col, const double* val, const float* valf, int width,
                                   int axis, int dim, Dims3 din, int nout_axis, int ncomp, const uint8_t* in_mask,
-                                  const uint8_t* out_mask) {
+                                  const uint8_t* out_mask, int add) {
   long long nin[3] = {din.n[0], din.n[1], din.n[2]};
   long long no[3] = {nin[0], nin[1], nin[2]};
   no[axis] = nout_axis;
@@ -33,19 +35,21 @@ __global__ void axis_apply_kernel(T* out, const T* in, const int* col, const dou
   const long long total = per_out * ncomp;
   long long sin[3] = {1, nin[0], nin[0] * nin[1]};
   for (long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (long long)gridDim.x * blockDim.x) {
-    const long long comp = idx / per_out;
-    long long rem = idx - comp * per_out;
+    const unsigned comp = udiv(idx, per_out);
+    unsigned rem = (unsigned)(idx - (long long)comp * per_out);
     long long o[3] = {0, 0, 0};
     for (int a = 0; a < dim; ++a) {
-      o[a] = rem % no[a];
-      rem /= no[a];
+      const unsigned q = rem / (unsigned)no[a];
+      o[a] = rem - q * (unsigned)no[a];
+      rem = q;
     }
     long long base = comp * per_in;
     for (int a = 0; a < dim; ++a)
       if (a != axis) base += o[a] * sin[a];
     const int row = (int)o[axis];
     T acc = 0;
-    if (!(out_mask && comp_fixed(out_mask, (idx - comp * per_out), comp, dim))) {
+    const bool ofix = out_mask && comp_fixed(out_mask, (idx - comp * per_out), comp, dim);
+    if (!ofix) {
       for (int j = 0; j < width; ++j) {
         const int ci = col[row * width + j];
         if (ci < 0) break;
@@ -55,13 +59,14 @@ __global__ void axis_apply_kernel(T* out, const T* in, const int* col, const dou
         acc += w * in[ii];
       }
     }
-    out[idx] = acc;
+    if (!add) out[idx] = acc;
+    else if (!ofix) out[idx] += acc;
   }
 }
 
 template <typename T>
 void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, const long long* dims_in, int ncomp,
-                  const uint8_t* in_mask, const uint8_t* out_mask, hipStream_t s) {
+                  const uint8_t* in_mask, const uint8_t* out_mask, hipStream_t s, bool add) {
   Dims3 d{{dims_in[0], dims_in[1], dim == 3 ? dims_in[2] : 1}};
   long long total = ncomp;
   for (int a = 0; a < dim; ++a) total *= (a == axis ? A.n_out : d.n[a]);
@@ -69,7 +74,7 @@ void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, con
   if (nb > 65536) nb = 65536;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(axis_apply_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, out, in, A.col, A.val, A.valf, A.width,
-                     axis, dim, d, A.n_out, ncomp, in_mask, out_mask);
+                     axis, dim, d, A.n_out, ncomp, in_mask, out_mask, add ? 1 : 0);
 }
 
 // out = / += P~ xc on the fine level: gather of (kc+1)^d coarse values per fine node
@@ -80,10 +85,11 @@ __global__ void prolong_kernel(T* out, const T* xc, const int* col, const double
   const int dim = gf.dim;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nnf; i += (long long)gridDim.x * blockDim.x) {
     int f[3] = {0, 0, 0};
-    long long rem = i;
+    unsigned rem = (unsigned)i;
     for (int a = 0; a < dim; ++a) {
-      f[a] = (int)(rem % gf.M);
-      rem /= gf.M;
+      const unsigned q = rem / (unsigned)gf.M;
+      f[a] = (int)(rem - q * (unsigned)gf.M);
+      rem = q;
     }
     T v[4] = {T(0), T(0), T(0), T(0)};
     const int w2 = dim == 3 ? width : 1;
@@ -139,7 +145,7 @@ template <typename T>
 __global__ void mask_comp_kernel(T* y, const uint8_t* mask, long long nn, int dim) {
   const long long n = (long long)(dim + 1) * nn;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const long long comp = i / nn;
+    const long long comp = udiv(i, nn);
     const uint8_t m = mask[i - comp * nn];
     const bool f = comp < dim ? (m & kMaskU) : (m & kMaskPhi);
     if (f) y[i] = T(0);
@@ -156,7 +162,7 @@ template <typename T>
 __global__ void add_masked_kernel(T* y, const T* x, const uint8_t* mask, long long nn, int dim) {
   const long long n = (long long)(dim + 1) * nn;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
-    const long long comp = i / nn;
+    const long long comp = udiv(i, nn);
     const uint8_t m = mask[i - comp * nn];
     const bool f = comp < dim ? (m & kMaskU) : (m & kMaskPhi);
     if (!f) y[i] += x[i];
@@ -170,9 +176,9 @@ void k_add_masked(T* y, const T* x, const uint8_t* mask, long long nn, int dim, 
 }
 
 template void k_axis_apply<double>(double*, const double*, const Sparse1D&, int, int, const long long*, int, const uint8_t*,
-                                   const uint8_t*, hipStream_t);
+                                   const uint8_t*, hipStream_t, bool);
 template void k_axis_apply<float>(float*, const float*, const Sparse1D&, int, int, const long long*, int, const uint8_t*,
-                                  const uint8_t*, hipStream_t);
+                                  const uint8_t*, hipStream_t, bool);
 template void k_prolong<double>(double*, const double*, const Sparse1D&, const uint8_t*, const uint8_t*, const Geom&,
                                 const Geom&, bool, hipStream_t);
 template void k_prolong<float>(float*, const float*, const Sparse1D&, const uint8_t*, const uint8_t*, const Geom&, const Geom&,

@@ -17,7 +17,7 @@ static inline unsigned grid_for(long long n, int per = kThreads) {
 
 __device__ __forceinline__ bool fixed_at(const uint8_t* mask, long long i, long long nn, int dim) {
   if (!mask) return false;
-  const long long comp = i / nn;
+  const long long comp = udiv(i, nn);
   const uint8_t m = mask[i - comp * nn];
   return comp < dim ? (m & kMaskU) : (m & kMaskPhi);
 }
