@@ -138,3 +138,19 @@ def test_fp32_level_products(name):
     e = rel_err(host(ctx.vcycle(dev(r))), H.vcycle(r))
     say(name, "fp32 vcycle rel err", e)
     assert e <= 1e-4
+
+
+@pytest.mark.parametrize("name", ["2d_q1", "2d_q2", "3d_q2"])
+def test_products_and_vcycle_are_bitwise_reproducible(name):
+    # fixed summation orders (colour phases in 2D, ordered node gather in 3D, block-ordered
+    # reductions): repeated calls give identical bits
+    from paper_2005_00331_amd import OP_BLOCKDIAG, OP_G, OP_GT
+    cfg, levels, inp, H = oracle_case(name)
+    ctx = ctx_for(name)
+    x = dev(np.random.default_rng(21).standard_normal(H.levels[-1].mesh.n_dofs))
+    say(name, "reproducibility")
+    for opn in (OP_G, OP_GT, OP_BLOCKDIAG):
+        a = host(ctx.apply_jacobian(-1, x, op=opn))
+        b = host(ctx.apply_jacobian(-1, x, op=opn))
+        assert np.array_equal(a, b), opn
+    assert np.array_equal(host(ctx.vcycle(x)), host(ctx.vcycle(x)))
