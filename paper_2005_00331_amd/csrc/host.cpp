@@ -146,6 +146,9 @@ struct mfpff_ctx {
   double hhost_scalar = 0.0;
   // V-cycle captured as a graph after each linearisation (replayed per GMRES iteration)
   hipStream_t cap_s = nullptr;
+  // the two coarse factorisations run on side streams while the Lanczos estimates run on s
+  hipStream_t side[2] = {nullptr, nullptr};
+  hipEvent_t ev_fork = nullptr, ev_join[2] = {nullptr, nullptr};
   hipGraphExec_t vgraph = nullptr;
   bool graph_ok = true;
   std::string err;
@@ -642,13 +645,25 @@ void coarse_setup(mfpff_ctx* c) {
   k_extract_block(c->App, np, c->dense, n, nu, nu, np, np, c->s);
   k_extract_block(c->Gpu, nu, c->dense, n, nu, 0, np, nu, c->s);
   HIPCHK(hipMemsetAsync(c->info_dev, 0, 2 * sizeof(int), c->s));
-  HIPCHK(cholesky_lower(c->Auu, nu, c->info_dev, c->chol_scratch, c->s));
-  HIPCHK(cholesky_lower(c->App, np, c->info_dev + 1, c->chol_scratch, c->s));
-  HIPCHK(tri_inverse_lower(c->Wu, c->Auu, nu, c->s));
-  HIPCHK(tri_inverse_lower(c->Wp, c->App, np, c->s));
-  k_transpose(c->WuT, c->Wu, nu, c->s);
-  k_transpose(c->WpT, c->Wp, np, c->s);
-  LAUNCHCHK();
+  // fork: u and phi blocks factorised and inverted concurrently; coarse_join waits for both
+  HIPCHK(hipEventRecord(c->ev_fork, c->s));
+  double* A[2] = {c->Auu, c->App};
+  double* W[2] = {c->Wu, c->Wp};
+  double* WT[2] = {c->WuT, c->WpT};
+  const int nb[2] = {nu, np};
+  for (int b = 0; b < 2; ++b) {
+    hipStream_t ss = c->side[b];
+    HIPCHK(hipStreamWaitEvent(ss, c->ev_fork, 0));
+    HIPCHK(cholesky_lower(A[b], nb[b], c->info_dev + b, c->chol_scratch + b * 32 * 32, ss));
+    HIPCHK(tri_inverse_lower(W[b], A[b], nb[b], ss));
+    k_transpose(WT[b], W[b], nb[b], ss);
+    LAUNCHCHK();
+    HIPCHK(hipEventRecord(c->ev_join[b], ss));
+  }
+}
+
+void coarse_join(mfpff_ctx* c) {
+  for (int b = 0; b < 2; ++b) HIPCHK(hipStreamWaitEvent(c->s, c->ev_join[b], 0));
 }
 
 void require_state(mfpff_ctx* c) {
@@ -875,8 +890,9 @@ void set_linearization(mfpff_ctx* c, const double* u, const double* phi, const d
     if (c->f32) k_cast_d2f(L.dinv32, L.dinv, L.n, c->s);
     LAUNCHCHK();
   }
+  coarse_setup(c);  // forks the dense factorisations onto the side streams
   for (int l = 1; l <= c->L; ++l) lanczos_level(c, l);
-  coarse_setup(c);
+  coarse_join(c);
   // read back Lanczos scalars and the factorisation status
   std::vector<LanczosState> hs(c->L + 1);
   HIPCHK(hipMemcpyAsync(hs.data(), c->lst, (c->L + 1) * sizeof(LanczosState), hipMemcpyDeviceToHost, c->s));
@@ -1030,7 +1046,14 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
     c->nu0 = (int)(d * C.nn);
     c->np0 = (int)C.nn;
     c->info_dev = dalloc<int>(2);
-    c->chol_scratch = dalloc<double>(32 * 32);
+    c->chol_scratch = dalloc<double>(2 * 32 * 32);
+    for (int b = 0; b < 2; ++b) {
+      if (hipStreamCreateWithFlags(&c->side[b], hipStreamNonBlocking) != hipSuccess ||
+          hipEventCreateWithFlags(&c->ev_join[b], hipEventDisableTiming) != hipSuccess)
+        throw StatusError{MFPFF_ERR_HIP, "stream or event creation failed"};
+    }
+    if (hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) != hipSuccess)
+      throw StatusError{MFPFF_ERR_HIP, "event creation failed"};
     c->finite_flag = dalloc<double>(1);
     // lumped mass on the finest level: integrals of the 1D basis functions
     Tables<double> t{};
@@ -1065,6 +1088,8 @@ void mfpff_destroy(mfpff_ctx* c) {
   if (!c) return;
   if (c->s) hipStreamSynchronize(c->s);
   else hipDeviceSynchronize();
+  for (auto ss : c->side)
+    if (ss) hipStreamSynchronize(ss);
   auto F = [](void* p) {
     if (p) hipFree(p);
   };
@@ -1099,6 +1124,11 @@ void mfpff_destroy(mfpff_ctx* c) {
     if (e) hipEventDestroy(e);
   if (c->vgraph) hipGraphExecDestroy(c->vgraph);
   if (c->cap_s) hipStreamDestroy(c->cap_s);
+  for (int b = 0; b < 2; ++b) {
+    if (c->side[b]) hipStreamDestroy(c->side[b]);
+    if (c->ev_join[b]) hipEventDestroy(c->ev_join[b]);
+  }
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
   delete c;
 }
 
