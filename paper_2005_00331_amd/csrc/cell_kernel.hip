@@ -49,8 +49,8 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
     jp = j % P;
   }
   const bool valid = inb && cell < ncells;
-  const long long node = valid ? node_of<DIM, K>(g, cell, p) : 0;
-  const uint8_t mk = (valid && a.mask) ? a.mask[node] : (uint8_t)0;
+  const long long node = valid ? node_of<DIM, K>(g, cell, p) : 0;  // invalid lanes read node 0
+  const uint8_t mk = a.mask ? a.mask[node] : (uint8_t)0;
 
   // ---------------- gather nodal values into buf0
   // field order: XMODE: x_0..x_d, u_0..u_{d-1}, phi, phit
@@ -66,30 +66,42 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
         const uint8_t jm = a.mask ? a.mask[jnode] : (uint8_t)0;
         colfixed = (jcomp < DIM) ? (jm & kMaskU) : (jm & kMaskPhi);
       }
+      // loads are unconditional and masked by bitwise selects afterwards (all in flight at once)
+      T xv[DIM + 1];
+      if (MODE != MODE_ELEM) {
+#pragma unroll
+        for (int cc = 0; cc <= DIM; ++cc) xv[cc] = a.x[cc * nn + node];
+      }
+      T lin[DIM + 2];
+      if (!QD) {
+#pragma unroll
+        for (int cc = 0; cc < DIM; ++cc) lin[cc] = a.u[cc * nn + node];
+        lin[DIM] = a.phi[node];
+        lin[DIM + 1] = a.phit[node];
+      }
 #pragma unroll
       for (int cc = 0; cc <= DIM; ++cc) {
-        T v = 0;
-        if (valid) {
-          if (MODE == MODE_ELEM) {
-            v = (cc == jcomp && p == jp && !colfixed) ? T(1) : T(0);
-          } else {
-            const bool fixed = (cc < DIM) ? (mk & kMaskU) : (mk & kMaskPhi);
-            v = fixed ? T(0) : a.x[cc * nn + node];
-          }
+        T v;
+        if (MODE == MODE_ELEM) {
+          v = (valid && cc == jcomp && p == jp && !colfixed) ? T(1) : T(0);
+        } else {
+          const bool fixed = (cc < DIM) ? (mk & kMaskU) : (mk & kMaskPhi);
+          v = keep_if(xv[cc], valid && !fixed);
         }
         buf0[cc * NPTS + o] = v;
       }
       if (!QD) {
 #pragma unroll
-        for (int cc = 0; cc < DIM; ++cc) buf0[(DIM + 1 + cc) * NPTS + o] = valid ? a.u[cc * nn + node] : T(0);
-        buf0[(2 * DIM + 1) * NPTS + o] = valid ? a.phi[node] : T(0);
-        buf0[(2 * DIM + 2) * NPTS + o] = valid ? a.phit[node] : T(0);
+        for (int cc = 0; cc < DIM + 2; ++cc) buf0[(DIM + 1 + cc) * NPTS + o] = keep_if(lin[cc], valid);
       }
     } else if (MODE == MODE_RESIDUAL || MODE == MODE_QDATA) {
+      T lin[DIM + 2];
 #pragma unroll
-      for (int cc = 0; cc < DIM; ++cc) buf0[cc * NPTS + o] = valid ? a.u[cc * nn + node] : T(0);
-      buf0[DIM * NPTS + o] = valid ? a.phi[node] : T(0);
-      buf0[(DIM + 1) * NPTS + o] = valid ? a.phit[node] : T(0);
+      for (int cc = 0; cc < DIM; ++cc) lin[cc] = a.u[cc * nn + node];
+      lin[DIM] = a.phi[node];
+      lin[DIM + 1] = a.phit[node];
+#pragma unroll
+      for (int cc = 0; cc < DIM + 2; ++cc) buf0[cc * NPTS + o] = keep_if(lin[cc], valid);
     } else {  // PVJP
       buf0[o] = valid ? a.phi[node] : T(0);
       buf0[NPTS + o] = valid ? a.x[DIM * nn + node] : T(0);
@@ -469,7 +481,7 @@ __global__ __launch_bounds__(kThreads) void gather3d_kernel(const T* __restrict_
   for (int cc = 0; cc < NC; ++cc) {
     const long long idx = cc * nn + node;
     const bool fixed = (cc < 3) ? (m & kMaskU) : (m & kMaskPhi);
-    const T xo = (EPI == EPI_CHEB || fixed) ? a.x[idx] : T(0);
+    const T xo = a.x[idx];  // unconditional: a load behind the mask test would wait for the mask
     const T gx = fixed ? xo : sum[cc];
     if (EPI == EPI_APPLY) {
       e.y[idx] = gx;

@@ -12,6 +12,18 @@ constexpr int kThreads = 256;
 __host__ __device__ __forceinline__ unsigned udiv(unsigned long long a, unsigned long long b) {
   return (unsigned)a / (unsigned)b;
 }
+// v where keep, else +0: a bitwise select, so that the compiler does not turn it into a branch
+// around the load that produced v (which would wait for the condition before issuing the load)
+template <typename T>
+__device__ __forceinline__ T keep_if(T v, bool keep) {
+  if constexpr (sizeof(T) == 8) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v) & (keep ? ~0ull : 0ull);
+    return __longlong_as_double((long long)b);
+  } else {
+    const unsigned b = __float_as_uint(v) & (keep ? ~0u : 0u);
+    return __uint_as_float(b);
+  }
+}
 
 // Geometry of one structured level: unit square/cube, N cells per direction,
 // Q_k with equispaced nodes, M = k*N + 1 nodes per direction.

@@ -84,29 +84,29 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   }
   const T wr = tabd->w[r];
 
-  // ---- node row r of the cell: u_0, u_1, phi, phi~, x_0, x_1, x_phi (x zeroed at fixed dofs)
+  // ---- node row r of the cell: u_0, u_1, phi, phi~, x_0, x_1, x_phi (x zeroed at fixed dofs).
+  // Every load is unconditional (invalid lanes read node 0 / their own tile slot) and the
+  // masking is a bitwise select afterwards, so all loads of a thread are in flight together
+  // (a select on the mask before the load made the compiler wait for the mask first).
   constexpr bool LIN = !QD;                // linearisation computed here
   constexpr bool XIN = MODE != MODE_QDATA;  // a trial vector is applied
+  const long long nd0 = valid ? (long long)(K * cx) + M * (K * cy + r) : 0;
   T f[7][NP];
+  uint8_t mk[NP];
 #pragma unroll
   for (int i0 = 0; i0 < NP; ++i0) {
-#pragma unroll
-    for (int q = 0; q < 7; ++q) f[q][i0] = T(0);
-    if (valid) {
-      const long long nd = (long long)(K * cx + i0) + M * (K * cy + r);
-      if (LIN) {
-        f[0][i0] = a.u[nd];
-        f[1][i0] = a.u[nn + nd];
-        f[2][i0] = a.phi[nd];
-        f[3][i0] = a.phit[nd];
-      }
-      if (XIN) {
-        const uint8_t mk = a.mask ? a.mask[nd] : (uint8_t)0;
-        const T x0 = a.x[nd], x1 = a.x[nn + nd], x2 = a.x[2 * nn + nd];
-        f[4][i0] = (mk & kMaskU) ? T(0) : x0;
-        f[5][i0] = (mk & kMaskU) ? T(0) : x1;
-        f[6][i0] = (mk & kMaskPhi) ? T(0) : x2;
-      }
+    const long long nd = nd0 + i0;
+    if (LIN) {
+      f[0][i0] = a.u[nd];
+      f[1][i0] = a.u[nn + nd];
+      f[2][i0] = a.phi[nd];
+      f[3][i0] = a.phit[nd];
+    }
+    if (XIN) {
+      mk[i0] = a.mask ? a.mask[nd] : (uint8_t)0;
+      f[4][i0] = a.x[nd];
+      f[5][i0] = a.x[nn + nd];
+      f[6][i0] = a.x[2 * nn + nd];
     }
   }
   // cached tangent coefficients of the Gauss row r, stored per tile (halo cells included) so
@@ -117,7 +117,22 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
 #pragma unroll
     for (int c = 0; c < kQCoef; ++c)
 #pragma unroll
-      for (int q0 = 0; q0 < NP; ++q0) qc[c][q0] = valid ? qtile[(c * NP * NP + q0) * kRowCells] : T(0);
+      for (int q0 = 0; q0 < NP; ++q0) qc[c][q0] = qtile[(c * NP * NP + q0) * kRowCells];
+  }
+#pragma unroll
+  for (int i0 = 0; i0 < NP; ++i0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) f[q][i0] = LIN ? keep_if(f[q][i0], valid) : T(0);
+    const bool ku = XIN && valid && !(mk[i0] & kMaskU), kp = XIN && valid && !(mk[i0] & kMaskPhi);
+    f[4][i0] = keep_if(f[4][i0], ku);
+    f[5][i0] = keep_if(f[5][i0], ku);
+    f[6][i0] = keep_if(f[6][i0], kp);
+  }
+  if (QD) {
+#pragma unroll
+    for (int c = 0; c < kQCoef; ++c)
+#pragma unroll
+      for (int q0 = 0; q0 < NP; ++q0) qc[c][q0] = keep_if(qc[c][q0], valid);
   }
 
   // ---- owned nodes and their epilogue operands (resid: b, dinv; cheb: r, d, dinv, x), loaded
@@ -146,10 +161,13 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
       if (ok && EPI == EPI_RESID) {
         o.ea[cc] = e.b[idx];
         if (e.z0) o.eb[cc] = e.dinv[idx];
+        o.ex[cc] = a.x[idx];
       } else if (ok && EPI == EPI_CHEB) {
         o.ea[cc] = e.r[idx];
         o.eb[cc] = e.d[idx];
         o.ec[cc] = e.dinv[idx];
+        o.ex[cc] = a.x[idx];
+      } else if (ok) {
         o.ex[cc] = a.x[idx];
       }
     }
@@ -160,7 +178,7 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
     for (int cc = 0; cc < 3; ++cc) {
       const long long idx = cc * nn + o.node;
       const bool fixed = (cc < 2) ? (o.m & kMaskU) : (o.m & kMaskPhi);
-      const T xo = (EPI == EPI_CHEB) ? o.ex[cc] : (fixed ? a.x[idx] : T(0));
+      const T xo = o.ex[cc];
       const T gx = fixed ? xo : acc[cc * AN * AN + o.bo];
       if (EPI == EPI_APPLY) {
         e.y[idx] = gx;
