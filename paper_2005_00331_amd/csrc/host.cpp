@@ -374,14 +374,17 @@ void op_cheb_step(mfpff_ctx* c, int l, int i, const T* zin, T* zout, const T* r,
   launch_fused<T>(c, L, MODE_BLOCK, EPI_CHEB, a, e);
 }
 
-// x = diag(C_u, C_phi) r (Chebyshev from zero); work vectors zA, zB, d, t (x distinct from them)
+// x = diag(C_u, C_phi) r (Chebyshev from zero); work vectors zA, zB, d, t (x distinct from them);
+// started: the Chebyshev start z = d = D^-1 r / theta is already in (s == 1 ? x : zA) and d
 template <typename T>
-void chebyshev(mfpff_ctx* c, int l, const T* r, T* x, T* zA, T* zB, T* d, T* t) {
+void chebyshev(mfpff_ctx* c, int l, const T* r, T* x, T* zA, T* zB, T* d, T* t, bool started = false) {
   Level& L = c->lv[l];
   const int s = c->prob.cheb_degree;
   T* zc = (s == 1) ? x : zA;
-  k_cheb_init<T>(zc, d, r, level_dinv<T>(L), L.nn, c->dim, (T)L.ith_u, (T)L.ith_p, c->s);
-  LAUNCHCHK();
+  if (!started) {
+    k_cheb_init<T>(zc, d, r, level_dinv<T>(L), L.nn, c->dim, (T)L.ith_u, (T)L.ith_p, c->s);
+    LAUNCHCHK();
+  }
   for (int i = 1; i < s; ++i) {
     T* zn = (i == s - 1) ? x : (zc == zA ? zB : zA);
     op_cheb_step<T>(c, l, i, zc, zn, r, d, t, nullptr, nullptr);
@@ -412,14 +415,16 @@ void post_smooth(mfpff_ctx* c, int l, const T* b, T* x, T* r, T* zA, T* zB, T* d
 // masked transfer between level l-1 and l; dir 0: out(level l) = P~ in (or += when add);
 // dir 1: out(level l-1) = R~ in (axis passes, masks fused into the first and last pass)
 template <typename T>
-void transfer(mfpff_ctx* c, int l, int dir, const T* in, T* out, bool add, T* ta, T* tb) {
+void transfer(mfpff_ctx* c, int l, int dir, const T* in, T* out, bool add, T* ta, T* tb,
+              ChebStart<T> cs = ChebStart<T>{}) {
   Level& F = c->lv[l];
   Level& C = c->lv[l - 1];
   const int d = c->dim, nc = d + 1;
-  if (dir == 0 && d == 2) {
+  if (dir == 0 && d == 2 && F.P1.s.width <= 5) {
     k_prolong<T>(out, in, F.P1.s, C.mask, F.mask, F.g, C.g, add, c->s);
   } else if (dir == 0) {
-    // 3D: axis passes (coarse mask on the first, fine mask and accumulation on the last)
+    // 3D (and wide 2D rows): axis passes (coarse mask on the first, fine mask and accumulation
+    // on the last)
     long long dims[3] = {C.g.M, C.g.M, C.g.M};
     const T* src = in;
     T* bufs[2] = {ta, tb};
@@ -438,7 +443,8 @@ void transfer(mfpff_ctx* c, int l, int dir, const T* in, T* out, bool add, T* ta
     for (int ax = 0; ax < d; ++ax) {
       const bool first = ax == 0, last = ax == d - 1;
       T* o = last ? out : bufs[ax & 1];
-      k_axis_apply<T>(o, src, F.R1.s, ax, d, dims, nc, first ? F.mask : nullptr, last ? C.mask : nullptr, c->s);
+      k_axis_apply<T>(o, src, F.R1.s, ax, d, dims, nc, first ? F.mask : nullptr, last ? C.mask : nullptr, c->s, false,
+                      last ? cs : ChebStart<T>{});
       dims[ax] = C.g.M;
       src = o;
     }
@@ -472,7 +478,7 @@ void coarse_solve_T<float>(mfpff_ctx* c, const float* r, float* x) {
 }
 
 template <typename T>
-void vcycle_rec(mfpff_ctx* c, int l) {
+void vcycle_rec(mfpff_ctx* c, int l, bool started = false) {
   Level& L = c->lv[l];
   T* b = (T*)L.w[WB];
   T* x = (T*)L.w[WX];
@@ -487,10 +493,21 @@ void vcycle_rec(mfpff_ctx* c, int l) {
   T* zB = (T*)L.w[WZ2];
   T* ta = std::is_same<T, double>::value ? (T*)c->t64a : (T*)c->t32a;
   T* tb = std::is_same<T, double>::value ? (T*)c->t64b : (T*)c->t32b;
-  chebyshev<T>(c, l, b, x, zA, zB, d, t);
+  chebyshev<T>(c, l, b, x, zA, zB, d, t, started);
   op_resid<T>(c, l, b, x, r, (T*)nullptr, (T*)nullptr);
-  transfer<T>(c, l, 1, r, (T*)c->lv[l - 1].w[WB], false, ta, tb);
-  vcycle_rec<T>(c, l - 1);
+  // restriction; its last pass also writes the coarser level's Chebyshev start
+  Level& C = c->lv[l - 1];
+  const bool cstart = l - 1 > 0;
+  ChebStart<T> cs;
+  if (cstart) {
+    cs.z0 = (T*)C.w[c->prob.cheb_degree == 1 ? WX : WZ];
+    cs.d0 = (T*)C.w[WD];
+    cs.dinv = level_dinv<T>(C);
+    cs.ith_u = (T)C.ith_u;
+    cs.ith_p = (T)C.ith_p;
+  }
+  transfer<T>(c, l, 1, r, (T*)C.w[WB], false, ta, tb, cs);
+  vcycle_rec<T>(c, l - 1, cstart);
   transfer<T>(c, l, 0, (const T*)c->lv[l - 1].w[WX], x, true, ta, tb);
   post_smooth<T>(c, l, b, x, r, zA, zB, d, t);
 }

@@ -202,12 +202,21 @@ struct Sparse1D {
   const double* val;        // n_out*width
   const float* valf;
 };
+// Chebyshev start written by a restriction's last pass: z0 = d0 = D^-1 out / theta_b (z0 null: none)
+template <typename T>
+struct ChebStart {
+  T* z0 = nullptr;
+  T* d0 = nullptr;
+  const T* dinv = nullptr;
+  T ith_u = T(1), ith_p = T(1);
+};
 // in_mask: zero inputs at fixed dofs (input must be a whole level vector);
 // out_mask: zero outputs at fixed dofs (output must be a whole level vector);
-// add: out += result instead (fixed outputs left unchanged)
+// add: out += result instead (fixed outputs left unchanged); cs: see ChebStart (last pass only)
 template <typename T>
 void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, const long long* dims_in,
-                  int ncomp, const uint8_t* in_mask, const uint8_t* out_mask, hipStream_t s, bool add = false);
+                  int ncomp, const uint8_t* in_mask, const uint8_t* out_mask, hipStream_t s, bool add = false,
+                  ChebStart<T> cs = ChebStart<T>{});
 // out (fine level) = / += P~ xc: single pass, (kc+1)^d coarse terms per fine node
 template <typename T>
 void k_prolong(T* out, const T* xc, const Sparse1D& P, const uint8_t* mask_c, const uint8_t* mask_f, const Geom& gf,

@@ -23,7 +23,7 @@ __device__ __forceinline__ bool comp_fixed(const uint8_t* mask, long long node, 
 template <typename T>
 __global__ void axis_apply_kernel(T* out, const T* in, const int* col, const double* val, const float* valf, int width,
                                   int axis, int dim, Dims3 din, int nout_axis, int ncomp, const uint8_t* in_mask,
-                                  const uint8_t* out_mask, int add) {
+                                  const uint8_t* out_mask, int add, ChebStart<T> cs) {
   long long nin[3] = {din.n[0], din.n[1], din.n[2]};
   long long no[3] = {nin[0], nin[1], nin[2]};
   no[axis] = nout_axis;
@@ -61,12 +61,17 @@ __global__ void axis_apply_kernel(T* out, const T* in, const int* col, const dou
     }
     if (!add) out[idx] = acc;
     else if (!ofix) out[idx] += acc;
+    if (cs.z0) {
+      const T zv = cs.dinv[idx] * acc * (comp < (unsigned)dim ? cs.ith_u : cs.ith_p);
+      cs.z0[idx] = zv;
+      cs.d0[idx] = zv;
+    }
   }
 }
 
 template <typename T>
 void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, const long long* dims_in, int ncomp,
-                  const uint8_t* in_mask, const uint8_t* out_mask, hipStream_t s, bool add) {
+                  const uint8_t* in_mask, const uint8_t* out_mask, hipStream_t s, bool add, ChebStart<T> cs) {
   Dims3 d{{dims_in[0], dims_in[1], dim == 3 ? dims_in[2] : 1}};
   long long total = ncomp;
   for (int a = 0; a < dim; ++a) total *= (a == axis ? A.n_out : d.n[a]);
@@ -74,53 +79,49 @@ void k_axis_apply(T* out, const T* in, const Sparse1D& A, int axis, int dim, con
   if (nb > 65536) nb = 65536;
   if (nb < 1) nb = 1;
   hipLaunchKernelGGL(axis_apply_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, out, in, A.col, A.val, A.valf, A.width,
-                     axis, dim, d, A.n_out, ncomp, in_mask, out_mask, add ? 1 : 0);
+                     axis, dim, d, A.n_out, ncomp, in_mask, out_mask, add ? 1 : 0, cs);
 }
 
-// out = / += P~ xc on the fine level: gather of (kc+1)^d coarse values per fine node
-template <typename T>
-__global__ void prolong_kernel(T* out, const T* xc, const int* col, const double* val, const float* valf, int width,
+// out = / += P~ xc on the fine level (2D): gather of the coarse values of a fine node's row
+// pair; W is the padded row width and every load is issued unconditionally (padding reads
+// node 0 with weight 0)
+template <typename T, int W>
+__global__ void prolong_kernel(T* out, const T* xc, const int* col, const double* val, const float* valf,
                                const uint8_t* mask_c, const uint8_t* mask_f, Geom gf, Geom gc, int add) {
   const long long nnf = gf.n_nodes, nnc = gc.n_nodes;
-  const int dim = gf.dim;
+  const unsigned Mf = (unsigned)gf.M;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < nnf; i += (long long)gridDim.x * blockDim.x) {
-    int f[3] = {0, 0, 0};
-    unsigned rem = (unsigned)i;
-    for (int a = 0; a < dim; ++a) {
-      const unsigned q = rem / (unsigned)gf.M;
-      f[a] = (int)(rem - q * (unsigned)gf.M);
-      rem = q;
+    const unsigned q = (unsigned)i / Mf;
+    const int f0 = (int)((unsigned)i - q * Mf), f1 = (int)q;
+    int c0[W], c1[W];
+    T w0[W], w1[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int a = col[f0 * W + j], b = col[f1 * W + j];
+      c0[j] = a < 0 ? 0 : a;
+      c1[j] = b < 0 ? 0 : b;
+      w0[j] = a < 0 ? T(0) : (sizeof(T) == 8 ? (T)val[f0 * W + j] : (T)valf[f0 * W + j]);
+      w1[j] = b < 0 ? T(0) : (sizeof(T) == 8 ? (T)val[f1 * W + j] : (T)valf[f1 * W + j]);
     }
-    T v[4] = {T(0), T(0), T(0), T(0)};
-    const int w2 = dim == 3 ? width : 1;
-    for (int j2 = 0; j2 < w2; ++j2) {
-      int c2 = 0;
-      T wz = T(1);
-      if (dim == 3) {
-        c2 = col[f[2] * width + j2];
-        if (c2 < 0) break;
-        wz = sizeof(T) == 8 ? (T)val[f[2] * width + j2] : (T)valf[f[2] * width + j2];
-      }
-      for (int j1 = 0; j1 < width; ++j1) {
-        const int c1 = col[f[1] * width + j1];
-        if (c1 < 0) break;
-        const T wy = wz * (sizeof(T) == 8 ? (T)val[f[1] * width + j1] : (T)valf[f[1] * width + j1]);
-        for (int j0 = 0; j0 < width; ++j0) {
-          const int c0 = col[f[0] * width + j0];
-          if (c0 < 0) break;
-          const T w = wy * (sizeof(T) == 8 ? (T)val[f[0] * width + j0] : (T)valf[f[0] * width + j0]);
-          const long long nc = c0 + (long long)gc.M * (c1 + (long long)gc.M * c2);
-          const uint8_t mc = mask_c[nc];
-          for (int cc = 0; cc <= dim; ++cc) {
-            const bool fx = cc < dim ? (mc & kMaskU) : (mc & kMaskPhi);
-            if (!fx) v[cc] += w * xc[cc * nnc + nc];
-          }
+    T v[3] = {T(0), T(0), T(0)};
+#pragma unroll
+    for (int j1 = 0; j1 < W; ++j1) {
+#pragma unroll
+      for (int j0 = 0; j0 < W; ++j0) {
+        const T w = w1[j1] * w0[j0];
+        const long long nc = c0[j0] + (long long)gc.M * c1[j1];
+        const uint8_t mc = mask_c[nc];
+#pragma unroll
+        for (int cc = 0; cc < 3; ++cc) {
+          const T xv = xc[cc * nnc + nc];
+          v[cc] += w * keep_if(xv, !(cc < 2 ? (mc & kMaskU) : (mc & kMaskPhi)));
         }
       }
     }
     const uint8_t mf = mask_f[i];
-    for (int cc = 0; cc <= dim; ++cc) {
-      const bool fx = cc < dim ? (mf & kMaskU) : (mf & kMaskPhi);
+#pragma unroll
+    for (int cc = 0; cc < 3; ++cc) {
+      const bool fx = cc < 2 ? (mf & kMaskU) : (mf & kMaskPhi);
       const long long idx = cc * nnf + i;
       if (add) {
         if (!fx) out[idx] += v[cc];
@@ -136,9 +137,20 @@ void k_prolong(T* out, const T* xc, const Sparse1D& P, const uint8_t* mask_c, co
                const Geom& gc, bool add, hipStream_t s) {
   long long nb = (gf.n_nodes + kThreads - 1) / kThreads;
   if (nb > 65536) nb = 65536;
-  hipLaunchKernelGGL(prolong_kernel<T>, dim3((unsigned)nb), dim3(kThreads), 0, s, out, xc, P.col, P.val, P.valf, P.width,
-                     mask_c, mask_f, gf, gc, add ? 1 : 0);
+  const dim3 g((unsigned)nb), b(kThreads);
+#define MFPFF_PW(WW)                                                                                                 \
+  case WW:                                                                                                           \
+    hipLaunchKernelGGL((prolong_kernel<T, WW>), g, b, 0, s, out, xc, P.col, P.val, P.valf, mask_c, mask_f, gf, gc, \
+                       add ? 1 : 0);                                                                                 \
+    break;
+  switch (P.width) {
+    MFPFF_PW(1) MFPFF_PW(2) MFPFF_PW(3) MFPFF_PW(4) MFPFF_PW(5)
+    default: break;  // the host uses the axis passes for wider rows
+  }
+#undef MFPFF_PW
 }
+
+
 
 // zero the fixed dofs of a level vector
 template <typename T>
@@ -176,9 +188,9 @@ void k_add_masked(T* y, const T* x, const uint8_t* mask, long long nn, int dim, 
 }
 
 template void k_axis_apply<double>(double*, const double*, const Sparse1D&, int, int, const long long*, int, const uint8_t*,
-                                   const uint8_t*, hipStream_t, bool);
+                                   const uint8_t*, hipStream_t, bool, ChebStart<double>);
 template void k_axis_apply<float>(float*, const float*, const Sparse1D&, int, int, const long long*, int, const uint8_t*,
-                                  const uint8_t*, hipStream_t, bool);
+                                  const uint8_t*, hipStream_t, bool, ChebStart<float>);
 template void k_prolong<double>(double*, const double*, const Sparse1D&, const uint8_t*, const uint8_t*, const Geom&,
                                 const Geom&, bool, hipStream_t);
 template void k_prolong<float>(float*, const float*, const Sparse1D&, const uint8_t*, const uint8_t*, const Geom&, const Geom&,
