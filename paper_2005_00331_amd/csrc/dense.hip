@@ -259,34 +259,45 @@ void k_transpose(double* At, const double* A, int n, hipStream_t s) {
   hipLaunchKernelGGL(transpose_kernel, grid, dim3(kThreads), 0, s, At, A, n);
 }
 
-// y = alpha * A x + yin  (one wave per row)
-// one wave per row, four independent partial sums per lane (loads in flight)
-__global__ void gemv_kernel(double* y, const double* A, long long lda, const double* x, int rows, int cols, double alpha,
-                            const double* yin, int shape) {
-  const int lane = threadIdx.x & 63;
-  const int row = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-  if (row >= rows) return;
+// y = alpha * A x + yin.  One workgroup per row: thread t takes the columns t, t + 256, ...
+// in chunks of kGemvChunk per thread whose loads are all issued before the first product
+// (the tail of a chunk reads a clamped in-range column with weight 0), so a row of a few
+// thousand columns costs one or two memory round trips; then a fixed-order block reduction.
+constexpr int kGemvChunk = 8;
+__global__ __launch_bounds__(kThreads) void gemv_kernel(double* y, const double* A, long long lda, const double* x,
+                                                        int cols, double alpha, const double* yin, int shape) {
+  __shared__ double part[kThreads / 64];
+  const int row = blockIdx.x;
+  const int t = threadIdx.x;
   const int j0 = shape == GEMV_UPPER ? row : 0;
   const int j1 = shape == GEMV_LOWER ? row + 1 : cols;
   const double* a = A + (long long)row * lda;
-  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
-  int j = j0 + lane;
-  for (; j + 192 < j1; j += 256) {
-    s0 += a[j] * x[j];
-    s1 += a[j + 64] * x[j + 64];
-    s2 += a[j + 128] * x[j + 128];
-    s3 += a[j + 192] * x[j + 192];
+  double acc = 0;
+  for (int base = j0 + t; base < j1; base += kGemvChunk * kThreads) {
+    double av[kGemvChunk], xv[kGemvChunk];
+#pragma unroll
+    for (int i = 0; i < kGemvChunk; ++i) {
+      const int j = min(base + i * kThreads, j1 - 1);
+      av[i] = a[j];
+      xv[i] = x[j];
+    }
+#pragma unroll
+    for (int i = 0; i < kGemvChunk; ++i) acc += base + i * kThreads < j1 ? av[i] * xv[i] : 0.0;
   }
-  for (; j < j1; j += 64) s0 += a[j] * x[j];
-  double acc = (s0 + s1) + (s2 + s3);
   for (int off = 32; off > 0; off >>= 1) acc += __shfl_down(acc, off, 64);
-  if (lane == 0) y[row] = alpha * acc + (yin ? yin[row] : 0.0);
+  if ((t & 63) == 0) part[t >> 6] = acc;
+  __syncthreads();
+  if (t == 0) {
+    double s = 0;
+#pragma unroll
+    for (int w = 0; w < kThreads / 64; ++w) s += part[w];
+    y[row] = alpha * s + (yin ? yin[row] : 0.0);
+  }
 }
 void k_gemv(double* y, const double* A, long long lda, const double* x, int rows, int cols, double alpha, const double* yin,
             int shape, hipStream_t s) {
-  const int rpb = kThreads / 64;
-  hipLaunchKernelGGL(gemv_kernel, dim3((rows + rpb - 1) / rpb), dim3(kThreads), 0, s, y, A, lda, x, rows, cols, alpha, yin,
-                     shape);
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)rows), dim3(kThreads), 0, s, y, A, lda, x, cols, alpha, yin, shape);
 }
 
 }  // namespace mfpff

@@ -14,6 +14,18 @@ __host__ __device__ __forceinline__ unsigned udiv(unsigned long long a, unsigned
 }
 // v where keep, else +0: a bitwise select, so that the compiler does not turn it into a branch
 // around the load that produced v (which would wait for the condition before issuing the load)
+// sign bit of v (true for -0.0 too) and |v|, both by bits
+template <typename T>
+__device__ __forceinline__ bool sign_bit(T v) {
+  if constexpr (sizeof(T) == 8) return __double_as_longlong(v) < 0;
+  else return __float_as_int(v) < 0;
+}
+template <typename T>
+__device__ __forceinline__ T abs_bits(T v) {
+  if constexpr (sizeof(T) == 8) return __longlong_as_double(__double_as_longlong(v) & 0x7fffffffffffffffll);
+  else return __int_as_float(__float_as_int(v) & 0x7fffffff);
+}
+
 template <typename T>
 __device__ __forceinline__ T keep_if(T v, bool keep) {
   if constexpr (sizeof(T) == 8) {
@@ -68,10 +80,10 @@ enum CellMode : int {
 };
 
 // Tangent coefficients of eq. (G) cached per Gauss point for the 2D row kernel:
-// g(phi~) K or K (volumetric, by the sign of tr e), 2 mu g(phi~), g'(phi) sigma^+ (xx, yy, xy),
-// g''(phi) E^+ + Gc/eps; layout [tile][coefficient][Gauss row][Gauss column][cell of the tile],
+// g(phi~) with the sign bit set where tr e < 0, g'(phi) sigma^+ (xx, yy, xy), g''(phi) E^+ + Gc/eps;
+// layout [tile][coefficient][Gauss row][Gauss column][cell of the tile],
 // rowcell_qdata_len values per level
-constexpr int kQCoef = 6;
+constexpr int kQCoef = 5;
 long long rowcell_qdata_len(const Geom& g);
 
 template <typename T>

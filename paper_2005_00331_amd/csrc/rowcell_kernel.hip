@@ -49,9 +49,11 @@ long long rowcell_qdata_len(const Geom& g) {
 
 // at most 128 VGPRs: four wavefronts per SIMD (the FP64 products issue well below peak with one or two)
 // QD: the tangent coefficients come from a.qd instead of being computed from u, phi, phi~
-template <int K, typename T, int MODE, int EPI, bool QD>
-__global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_eu(4))) void rowcell_kernel_2d(CellArgs<T> a, Epilogue<T> e, Tab2<K + 1, T> tb,
-                                                                         const Tables<T>* __restrict__ tabd) {
+// EARLY (grids of at most two workgroups per CU, where occupancy does not matter): the epilogue
+// operands are loaded with the cell inputs, so the kernel waits for memory once, not twice
+template <int K, typename T, int MODE, int EPI, bool QD, bool EARLY>
+__global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_eu(EARLY ? 1 : 4))) void rowcell_kernel_2d(
+    CellArgs<T> a, Epilogue<T> e, Tab2<K + 1, T> tb, const Tables<T>* __restrict__ tabd) {
   constexpr int NP = K + 1;
   constexpr int NT = kRowCells * NP;
   constexpr int AN = K * kRowTile + 1;      // node box per direction
@@ -201,6 +203,12 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
     }
   };
 
+  Owned pre[EARLY ? MAXO : 1];
+  if (EARLY) {
+#pragma unroll
+    for (int j = 0; j < MAXO; ++j) eload(j, pre[j]);
+  }
+
   int slot = 0;
   // publish two kinds of this thread's row (indexed [q][r]); after the barrier every
   // thread reads the NP rows of its own cell
@@ -276,16 +284,17 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
     }
     slot ^= 1;
   }
-  T cvol[NP], cdev[NP], sxx[NP], syy[NP], sxy[NP], cpp[NP];
+  // gs = g(phi~) with its sign bit set where tr e < 0 (compression), so the two split
+  // coefficients g K or K and 2 mu g come from one stored value, bit for bit
+  T gs[NP], sxx[NP], syy[NP], sxy[NP], cpp[NP];
 #pragma unroll
   for (int q0 = 0; q0 < NP; ++q0) {
     if (QD) {
-      cvol[q0] = qc[0][q0];
-      cdev[q0] = qc[1][q0];
-      sxx[q0] = qc[2][q0];
-      syy[q0] = qc[3][q0];
-      sxy[q0] = qc[4][q0];
-      cpp[q0] = qc[5][q0];
+      gs[q0] = qc[0][q0];
+      sxx[q0] = qc[1][q0];
+      syy[q0] = qc[2][q0];
+      sxy[q0] = qc[3][q0];
+      cpp[q0] = qc[4][q0];
       continue;
     }
     const T exx = gu00[q0] * ih, eyy = gu11[q0] * ih;
@@ -298,8 +307,7 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
     const T pt = ptq[q0];
     const T gt = (T(1) - kap) * pt * pt + kap;
     const T dg = T(2) * (T(1) - kap) * phq[q0];
-    cvol[q0] = H ? gt * Kb : Kb;
-    cdev[q0] = T(2) * mu * gt;
+    gs[q0] = H ? gt : -gt;
     sxx[q0] = dg * (T(2) * mu * dxx + Kb * tp);
     syy[q0] = dg * (T(2) * mu * dyy + Kb * tp);
     sxy[q0] = dg * (T(2) * mu * exy);
@@ -312,15 +320,21 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
       constexpr int cs = NP * NP * kRowCells;  // coefficient stride
 #pragma unroll
       for (int q0 = 0; q0 < NP; ++q0) {
-        o[q0 * kRowCells] = cvol[q0];
-        o[cs + q0 * kRowCells] = cdev[q0];
-        o[2 * cs + q0 * kRowCells] = sxx[q0];
-        o[3 * cs + q0 * kRowCells] = syy[q0];
-        o[4 * cs + q0 * kRowCells] = sxy[q0];
-        o[5 * cs + q0 * kRowCells] = cpp[q0];
+        o[q0 * kRowCells] = gs[q0];
+        o[cs + q0 * kRowCells] = sxx[q0];
+        o[2 * cs + q0 * kRowCells] = syy[q0];
+        o[3 * cs + q0 * kRowCells] = sxy[q0];
+        o[4 * cs + q0 * kRowCells] = cpp[q0];
       }
     }
     return;
+  }
+  T cvol[NP], cdev[NP];
+#pragma unroll
+  for (int q0 = 0; q0 < NP; ++q0) {
+    const T gt = abs_bits(gs[q0]);
+    cvol[q0] = sign_bit(gs[q0]) ? Kb : gt * Kb;
+    cdev[q0] = T(2) * mu * gt;
   }
 
   // ---- trial functions at the Gauss points of row r
@@ -425,9 +439,13 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   // ---- fused epilogue on the owned nodes
 #pragma unroll
   for (int j = 0; j < MAXO; ++j) {
-    Owned on;
-    eload(j, on);
-    efinish(on);
+    if (EARLY) {
+      efinish(pre[j]);
+    } else {
+      Owned on;
+      eload(j, on);
+      efinish(on);
+    }
   }
 }
 
@@ -443,17 +461,20 @@ static hipError_t launch_row_k(int mode, int epi, const CellArgs<T>& a, const Ep
     }
   }
   const long long nb = rowcell_blocks_2d(a.g);
+  const bool early = nb <= 512;
   dim3 grid((unsigned)nb), block(kRowCells * (K + 1));
-#define MFPFF_R(MD, EP)                                                                                 \
-  if (mode == MD && epi == EP) {                                                                        \
-    if (a.qd)                                                                                           \
-      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true>), grid, block, 0, s, a, e, tb, tabd);   \
-    else                                                                                                \
-      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, false>), grid, block, 0, s, a, e, tb, tabd);  \
-    return hipGetLastError();                                                                           \
+#define MFPFF_R(MD, EP)                                                                                        \
+  if (mode == MD && epi == EP) {                                                                               \
+    if (a.qd && early)                                                                                         \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, true>), grid, block, 0, s, a, e, tb, tabd);    \
+    else if (a.qd)                                                                                             \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, false>), grid, block, 0, s, a, e, tb, tabd);   \
+    else                                                                                                       \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, false, false>), grid, block, 0, s, a, e, tb, tabd);  \
+    return hipGetLastError();                                                                                  \
   }
   if (mode == MODE_QDATA) {
-    hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MODE_QDATA, EPI_APPLY, false>), grid, block, 0, s, a, e, tb, tabd);
+    hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MODE_QDATA, EPI_APPLY, false, false>), grid, block, 0, s, a, e, tb, tabd);
     return hipGetLastError();
   }
   MFPFF_R(MODE_APPLY, EPI_APPLY)
