@@ -125,6 +125,10 @@ struct Epilogue {
 template <typename T>
 hipError_t launch_gather_3d(int epi, const T* elem, const CellArgs<T>& a, const Epilogue<T>& e, hipStream_t s);
 long long elem_len(const Geom& g);  // values in the element buffer of one level
+// 3D products (APPLY, APPLY_T, BLOCK) from the cached coefficients into the element buffer,
+// one thread per node line (linecell_kernel.hip); a.qd and a.elem required
+template <typename T>
+hipError_t launch_linecell(int mode, const CellArgs<T>& a, const Tables<T>* tab_dev, hipStream_t s);
 long long cell_qdata_len(const Geom& g);  // 3D: values of the cached tangent coefficients of one level
 template <typename T>
 hipError_t launch_tile_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<T>* tab, hipStream_t s);
