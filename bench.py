@@ -91,23 +91,24 @@ def time_newton(ctx, state, steps, warmup):
     return (t1 - t0) / steps, infos
 
 
-def time_apply(ctx, n_launch=50):
-    """Average duration of one finest-level product (FP64, full operator), timed with
-    HIP events on the stream the library launches on. 2D: one owner-computes kernel;
-    3D: the cell kernel (element results) plus the node gather."""
+def time_apply(ctx, n_launch=50, f32=False):
+    """Average duration of one finest-level product (full operator, FP64 unless f32), timed
+    with HIP events on the stream the library launches on. 2D: one owner-computes kernel;
+    3D: the line kernel (element results) plus the node gather."""
     import torch
-    from paper_2005_00331_amd import OP_G
+    from paper_2005_00331_amd import F32, F64, OP_G
     n = ctx.n_dofs
     op = OP_G
-    x = torch.randn(n, dtype=torch.float64, device="cuda")
-    y = torch.zeros(n, dtype=torch.float64, device="cuda")
+    prec, dt = (F32, torch.float32) if f32 else (F64, torch.float64)
+    x = torch.randn(n, dtype=dt, device="cuda")
+    y = torch.zeros(n, dtype=dt, device="cuda")
     for _ in range(5):
-        ctx.apply_jacobian(-1, x, y, op=op)
+        ctx.apply_jacobian(-1, x, y, prec=prec, op=op)
     s = torch.cuda.current_stream()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(s)
     for _ in range(n_launch):
-        ctx.apply_jacobian(-1, x, y, op=op)
+        ctx.apply_jacobian(-1, x, y, prec=prec, op=op)
     e1.record(s)
     e1.synchronize()
     return e0.elapsed_time(e1) / 1e3 / n_launch
@@ -135,6 +136,30 @@ def time_solve(cfg, prec):
     ctx.close()
     return {"ms_setup": (t1 - t0) * 1e3, "ms_solve": (t2 - t1) * 1e3, "ms_total": (t2 - t0) * 1e3,
             "gmres_iterations": st["iterations"], "converged": st["converged"], "rel_residual": st["rel_residual"]}
+
+
+def contraction_flops_3d(cfg):
+    """FP64/FP32 flops of the sum-factorised contractions of one 3D product in the line
+    kernel: per cell 33 (k+1)^4 multiply-adds forward (x, y, z steps over four fields)
+    and 33 (k+1)^4 backward; the point physics (about 100 flops per Gauss point) is not
+    counted."""
+    n_cells = cfg.N ** 3
+    return 2 * 66 * (cfg.k + 1) ** 4 * n_cells
+
+
+def time_products_3d(cfg):
+    """Finest-level product of a 3D workload in FP64 and FP32 after set_linearization."""
+    ctx, levels, state = build_context(cfg, prec="f32")
+    ctx.set_linearization(state["u"], state["phi"], state["phi_old"], state["active"], state["phi_tilde"])
+    fl = contraction_flops_3d(cfg)
+    res = {"workload": f"{cfg.name}: 3D {cfg.N}^3 cells Q{cfg.k}, {cfg.n_dofs} dofs, finest-level product "
+                       f"(line kernel + node gather)", "contraction_gflop": fl / 1e9}
+    for f32, tag, peak in ((False, "f64", 78.6), (True, "f32", 157.3)):
+        t = time_apply(ctx, f32=f32)
+        res[tag] = {"apply_us": t * 1e6, "dofs_per_s": ctx.n_dofs / t, "contraction_tflops": fl / t / 1e12,
+                    "frac_of_peak": fl / t / 1e12 / peak, "peak_tflops": peak}
+    ctx.close()
+    return res
 
 
 def cpu_baseline(cfg_name):
@@ -169,7 +194,7 @@ def main():
     ap.add_argument("--workload", default="C2")
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison step")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 3D FP32-vs-FP64 V-cycle solve comparison")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D runs (C3 solves, C4 products)")
     ap.add_argument("--apply-only", action="store_true",
                     help="only time the finest-level cell kernel (for kernel-trace and counter runs)")
     args = ap.parse_args()
@@ -230,6 +255,9 @@ def main():
             res[prec + "_vcycle"] = time_solve(c3, prec)
             print(f"[bench] C3 solve, {prec} V-cycle: {res[prec + '_vcycle']}", file=sys.stderr, flush=True)
         detail["c3_solve"] = res
+        c4 = time_products_3d(CONFIGS["C4"])
+        print(f"[bench] C4 products: {c4}", file=sys.stderr, flush=True)
+        detail["c4_products"] = c4
     out = {
         "metric": METRIC,
         "value": ctx.n_dofs / sec,
@@ -250,7 +278,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg),
                      "kernel": ((f"rowcell_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>" if cfg.k <= 2 else
                                  f"tile_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>") if cfg.dim == 2 else
-                                f"cell_kernel<{cfg.dim},{cfg.k},double,APPLY> + gather3d_kernel") + " on the finest level",
+                                f"linecell_kernel<{cfg.k},double,APPLY> + gather3d_kernel") + " on the finest level",
                      "bytes_per_launch": byts},
         "detail": detail,
     }

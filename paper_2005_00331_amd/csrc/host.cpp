@@ -522,7 +522,7 @@ void vcycle_body(mfpff_ctx* c) {
 // until the next linearisation.  Any failure leaves the direct launch path.
 void capture_vcycle(mfpff_ctx* c) {
   if (c->vgraph) {
-    hipGraphExecDestroy(c->vgraph);
+    (void)hipGraphExecDestroy(c->vgraph);
     c->vgraph = nullptr;
   }
   if (!c->graph_ok) return;
@@ -549,7 +549,7 @@ void capture_vcycle(mfpff_ctx* c) {
     c->vgraph = nullptr;
     ok = false;
   }
-  if (g) hipGraphDestroy(g);
+  if (g) (void)hipGraphDestroy(g);
   (void)hipGetLastError();
   if (!ok) {
     c->graph_ok = false;
@@ -1103,12 +1103,12 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
 
 void mfpff_destroy(mfpff_ctx* c) {
   if (!c) return;
-  if (c->s) hipStreamSynchronize(c->s);
-  else hipDeviceSynchronize();
+  if (c->s) (void)hipStreamSynchronize(c->s);
+  else (void)hipDeviceSynchronize();
   for (auto ss : c->side)
-    if (ss) hipStreamSynchronize(ss);
+    if (ss) (void)hipStreamSynchronize(ss);
   auto F = [](void* p) {
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   };
   for (auto& L : c->lv) {
     F(L.lin);
@@ -1136,16 +1136,16 @@ void mfpff_destroy(mfpff_ctx* c) {
                 c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out};
   for (void* p : ps) F(p);
   for (int i = 0; i < 5; ++i) F(c->s64[i]);
-  if (c->hhost) hipHostFree(c->hhost);
+  if (c->hhost) (void)hipHostFree(c->hhost);
   for (auto e : c->hev)
-    if (e) hipEventDestroy(e);
-  if (c->vgraph) hipGraphExecDestroy(c->vgraph);
-  if (c->cap_s) hipStreamDestroy(c->cap_s);
+    if (e) (void)hipEventDestroy(e);
+  if (c->vgraph) (void)hipGraphExecDestroy(c->vgraph);
+  if (c->cap_s) (void)hipStreamDestroy(c->cap_s);
   for (int b = 0; b < 2; ++b) {
-    if (c->side[b]) hipStreamDestroy(c->side[b]);
-    if (c->ev_join[b]) hipEventDestroy(c->ev_join[b]);
+    if (c->side[b]) (void)hipStreamDestroy(c->side[b]);
+    if (c->ev_join[b]) (void)hipEventDestroy(c->ev_join[b]);
   }
-  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   delete c;
 }
 
@@ -1290,8 +1290,8 @@ mfpff_status mfpff_gmres_solve(mfpff_ctx* c, const double* b, double* x, mfpff_s
     HIPCHK(hipEventSynchronize(e1));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
     loc.ms_solve = ms;
     if (info) *info = loc;
     if (st == MFPFF_ERR_NOCONV) c->err = "GMRES reached max_iter";
@@ -1399,9 +1399,9 @@ mfpff_status mfpff_newton_step(mfpff_ctx* c, double* u, double* phi, const doubl
     float ms1 = 0, ms2 = 0;
     HIPCHK(hipEventElapsedTime(&ms1, e0, e1));
     HIPCHK(hipEventElapsedTime(&ms2, e1, e2));
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
-    hipEventDestroy(e2);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    (void)hipEventDestroy(e2);
     loc.ms_setup = ms1;
     loc.ms_solve = ms2;
     std::vector<uint8_t> mh(F.nn);
