@@ -100,10 +100,11 @@ struct SharedTables {
 // the d+1 cell-local results [comp][cell][node].  All threads of the block
 // must call it (it contains barriers); the caller has synchronised buf0.
 // Tangent coefficients per Gauss point (MODE_QDATA writes them, QD products read them):
-// [0] g(phi~) K or K (by the sign of tr e), [1] 2 mu g(phi~), [2 ..] g'(phi) sigma^+ (00, 11, (22),
-// 01, (02, 12)), [last] g''(phi) E^+ + Gc/eps; qcf points at this block's [coefficient][point][cell]
+// [0] g(phi~) with its sign bit set where tr e < 0 (the split coefficients g K or K and 2 mu g are
+// rebuilt from it with the same operations), [1 ..] g'(phi) sigma^+ (00, 11, (22), 01, (02, 12)),
+// [last] g''(phi) E^+ + Gc/eps; qcf points at this block's [coefficient][point][cell]
 template <int DIM>
-__host__ __device__ constexpr int n_qcoef() { return 3 + DIM * (DIM + 1) / 2; }
+__host__ __device__ constexpr int n_qcoef() { return 2 + DIM * (DIM + 1) / 2; }
 
 template <int DIM, int K, typename T, int MODE, int NT = kThreads, bool QD = false>
 __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>& st, const MatParams& mp, T h,
@@ -173,13 +174,12 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
       const T ddg = T(2) * (T(1) - kap);
       T* q = qcf_out + (long long)p * CPB + c;
       constexpr int QS = P * CPB;  // coefficient stride
-      q[0] = H ? gt * Kb : Kb;
-      q[QS] = gt * T(2) * mu;
+      q[0] = H ? gt : -gt;
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
         const int i = SI[k], j = SJ[k];
         const T spij = T(2) * mu * (e[i][j] - (i == j ? t / T(DIM) : T(0))) + (i == j ? Kb * tp : T(0));
-        q[(2 + k) * QS] = dg * spij;
+        q[(1 + k) * QS] = dg * spij;
       }
       q[(NQ - 1) * QS] = ddg * Ep + Gc / eps;
     }
@@ -197,12 +197,14 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
     if (DIM == 3) jxw *= st.W[p / (NP * NP)] * h;
     const T* q = qcf + (long long)p * CPB + c;
     constexpr int QS = P * CPB;
-    const T cvol = q[0], cdev = q[QS], cpp = q[(NQ - 1) * QS];
+    const T gsv = q[0], cpp = q[(NQ - 1) * QS];
+    const T gta = abs_bits(gsv);
+    const T cvol = sign_bit(gsv) ? Kb : gta * Kb, cdev = gta * T(2) * mu;
     T gsp[DIM][DIM];
     if (MODE != MODE_BLOCK) {
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
-        const T v = q[(2 + k) * QS];
+        const T v = q[(1 + k) * QS];
         gsp[SI[k]][SJ[k]] = v;
         gsp[SJ[k]][SI[k]] = v;
       }

@@ -189,7 +189,8 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
 
   // ---- point physics of eq. (G) from the cached coefficients, on the points (la, lb, q2)
   const T h = (T)g.h, ih = T(1) / h;
-  const T Gc = (T)a.m.Gc, eps = (T)a.m.eps;
+  const T Gc = (T)a.m.Gc, eps = (T)a.m.eps, lam = (T)a.m.lam, mu = (T)a.m.mu;
+  const T Kb = lam + T(2) * mu / T(3);
   const long long blk = vc / CPB;
   const int cw = (int)(vc - blk * CPB);
   const T* qb = a.qd + blk * NQ * P * CPB + cw;
@@ -202,12 +203,14 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
     const int p = l + L * q;
     const T* qq = qb + (long long)p * CPB;
     constexpr int QS = P * CPB;
-    const T cvol = keep_if(qq[0], valid), cdev = keep_if(qq[QS], valid), cpp = keep_if(qq[(NQ - 1) * QS], valid);
+    const T gsv = keep_if(qq[0], valid), cpp = keep_if(qq[(NQ - 1) * QS], valid);
+    const T gta = abs_bits(gsv);
+    const T cvol = sign_bit(gsv) ? Kb : gta * Kb, cdev = gta * T(2) * mu;
     T gsp[3][3];
     if (MODE != MODE_BLOCK) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const T v = keep_if(qq[(2 + k) * QS], valid);
+        const T v = keep_if(qq[(1 + k) * QS], valid);
         gsp[SI[k]][SJ[k]] = v;
         gsp[SJ[k]][SI[k]] = v;
       }

@@ -44,6 +44,8 @@ CASES = {
     "3d_q3": ("C4", [(3, 1), (3, 3)], {}),
     "3d_q4": ("C4", [(2, 2), (2, 4), (4, 4)], {}),
     "3d_q2_f32": ("C3", [(2, 2), (4, 2)], dict(vcycle_prec="f32")),
+    "3d_q3_f32": ("C4", [(3, 1), (3, 3)], dict(vcycle_prec="f32")),
+    "3d_q4_f32": ("C4", [(2, 1), (2, 2), (2, 4), (4, 4)], dict(vcycle_prec="f32")),
     "2d_q2_f32": ("C2", [(5, 2), (10, 2)], dict(vcycle_prec="f32")),
 }
 
