@@ -46,13 +46,16 @@ void k_extract_block(double* dst, long long ldd, const double* src, long long ld
   hipLaunchKernelGGL(extract_block_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, dst, ldd, src, lds, r0, c0, nr, nc);
 }
 
-// Factor the diagonal block at k0 in LDS (identity padding past n); block 0
-// writes L11 to `diag` (copied into A by the next kernel, so that no block
-// reads a half-written diagonal block), block b >= 1 solves
-// X L11^T = A[rows of b][k0:k0+TB] in place.
-__global__ __launch_bounds__(kThreads) void potrf_panel_kernel(double* A, int n, int k0, int* info, double* diag) {
+// Factor the diagonal block at k0 (identity padding past n) with one wavefront: lane i < TB
+// holds row i in registers, each column of L goes through LDS once.  Block 0 writes L11 to
+// `diag` (copied into A by the next launch, so that no block reads a half-written diagonal
+// block); block b >= 1 solves X L11^T = A[rows of b][k0:k0+TB] in place.
+constexpr int kPanelLanes = 64;
+__global__ __launch_bounds__(kPanelLanes) void potrf_panel_kernel(double* A, int n, int k0, int* info, double* diag) {
   __shared__ double L[TB][TB + 1];
   __shared__ double X[TB][TB + 1];
+  __shared__ double col[TB];
+  __shared__ double rinv[TB];  // 1 / L[j][j]
   const int tid = threadIdx.x;
   for (int e = tid; e < TB * TB; e += blockDim.x) {
     const int i = e / TB, j = e % TB;
@@ -60,24 +63,42 @@ __global__ __launch_bounds__(kThreads) void potrf_panel_kernel(double* A, int n,
     L[i][j] = (gi < n && gj < n) ? A[(long long)gi * n + gj] : (i == j ? 1.0 : 0.0);
   }
   __syncthreads();
-  for (int j = 0; j < TB; ++j) {
-    if (tid == 0) {
-      double d = L[j][j];
-      if (!(d > 0.0)) {
-        if (blockIdx.x == 0) atomicMax(info, k0 + j + 1);
-        d = 1.0;
+  {
+    const int i = tid < TB ? tid : TB - 1;  // lanes past TB shadow the last row and store nothing
+    double row[TB];
+#pragma clang loop unroll(full)
+    for (int l = 0; l < TB; ++l) row[l] = L[i][l];
+#pragma clang loop unroll(full)
+    for (int j = 0; j < TB; ++j) {
+      if (tid == j) {
+        double d = row[j];
+        if (!(d > 0.0)) {
+          if (blockIdx.x == 0) atomicMax(info, k0 + j + 1);
+          d = 1.0;
+        }
+        row[j] = sqrt(d);
+        rinv[j] = 1.0 / row[j];
       }
-      L[j][j] = sqrt(d);
+      __syncthreads();
+      if (tid > j && tid < TB) {
+        row[j] *= rinv[j];
+        col[tid] = row[j];
+      }
+      __syncthreads();
+      if (tid > j && tid < TB) {
+        const double lij = row[j];
+#pragma clang loop unroll(full)
+        for (int l = 0; l < TB; ++l)
+          if (l > j) row[l] -= lij * col[l];  // entries past the diagonal are never read
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (int i = j + 1 + tid; i < TB; i += blockDim.x) L[i][j] /= L[j][j];
-    __syncthreads();
-    for (int e = tid; e < TB * TB; e += blockDim.x) {
-      const int i = e / TB, l = e % TB;
-      if (l > j && i >= l) L[i][l] -= L[i][j] * L[l][j];
+    if (tid < TB) {
+#pragma clang loop unroll(full)
+      for (int l = 0; l < TB; ++l) L[i][l] = row[l];
     }
-    __syncthreads();
   }
+  __syncthreads();
   if (blockIdx.x == 0) {
     for (int e = tid; e < TB * TB; e += blockDim.x) diag[e] = L[e / TB][e % TB];
     return;
@@ -97,7 +118,7 @@ __global__ __launch_bounds__(kThreads) void potrf_panel_kernel(double* A, int n,
     for (int j = 0; j < TB; ++j) xr[j] = X[i][j];
 #pragma clang loop unroll(full)
     for (int j = 0; j < TB; ++j) {
-      const double xj = xr[j] / L[j][j];
+      const double xj = xr[j] * rinv[j];
       xr[j] = xj;
 #pragma clang loop unroll(full)
       for (int l = 0; l < TB; ++l)
@@ -114,18 +135,24 @@ __global__ __launch_bounds__(kThreads) void potrf_panel_kernel(double* A, int n,
   }
 }
 
-__global__ void copy_diag_kernel(double* A, int n, int k0, const double* diag) {
+// Lower triangle of the factored diagonal block back into A (workgroup 0 of the launch that
+// follows the panel kernel)
+__device__ void copy_diag(double* A, int n, int k0, const double* diag) {
   for (int e = threadIdx.x; e < TB * TB; e += blockDim.x) {
     const int i = e / TB, j = e % TB;
     const int gi = k0 + i, gj = k0 + j;
     if (gi < n && gj < n && j <= i) A[(long long)gi * n + gj] = diag[e];
   }
 }
+__global__ void copy_diag_kernel(double* A, int n, int k0, const double* diag) { copy_diag(A, n, k0, diag); }
 
-// Trailing update A[i][j] -= sum_l L[i][l] L[j][l], l in the panel, for tiles bi >= bj.
-__global__ __launch_bounds__(kThreads) void syrk_update_kernel(double* A, int n, int k0) {
+// Trailing update A[i][j] -= sum_l L[i][l] L[j][l], l in the panel, for tiles bi >= bj
+// (rows and columns past the panel, so the diagonal block is not touched: workgroup 0 also
+// copies it back from `diag`).
+__global__ __launch_bounds__(kThreads) void syrk_update_kernel(double* A, int n, int k0, const double* diag) {
   __shared__ double Li[TB][TB + 1];
   __shared__ double Lj[TB][TB + 1];
+  if (blockIdx.x == 0) copy_diag(A, n, k0, diag);
   const int k1 = k0 + TB;
   // blockIdx.x -> (bi, bj), bi >= bj
   int t = blockIdx.x, bi = 0;
@@ -158,12 +185,14 @@ __global__ __launch_bounds__(kThreads) void syrk_update_kernel(double* A, int n,
 hipError_t cholesky_lower(double* A, int n, int* info_dev, double* scratch, hipStream_t s) {
   for (int k0 = 0; k0 < n; k0 += TB) {
     const int nrb = (n - k0 + TB - 1) / TB;
-    hipLaunchKernelGGL(potrf_panel_kernel, dim3(nrb), dim3(kThreads), 0, s, A, n, k0, info_dev, scratch);
-    hipLaunchKernelGGL(copy_diag_kernel, dim3(1), dim3(kThreads), 0, s, A, n, k0, (const double*)scratch);
+    hipLaunchKernelGGL(potrf_panel_kernel, dim3(nrb), dim3(kPanelLanes), 0, s, A, n, k0, info_dev, scratch);
     const int k1 = k0 + TB;
     if (k1 < n) {
       const int nt = (n - k1 + TB - 1) / TB;
-      hipLaunchKernelGGL(syrk_update_kernel, dim3(nt * (nt + 1) / 2), dim3(kThreads), 0, s, A, n, k0);
+      hipLaunchKernelGGL(syrk_update_kernel, dim3(nt * (nt + 1) / 2), dim3(kThreads), 0, s, A, n, k0,
+                         (const double*)scratch);
+    } else {
+      hipLaunchKernelGGL(copy_diag_kernel, dim3(1), dim3(kThreads), 0, s, A, n, k0, (const double*)scratch);
     }
   }
   return hipGetLastError();
@@ -174,27 +203,38 @@ __global__ void eye_kernel(double* W, int n) {
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (long long)gridDim.x * blockDim.x)
     W[e] = (e / n == e % n) ? 1.0 : 0.0;
 }
-// W[k0:k0+TB, 0:ncols] = L11^-1 W[k0:k0+TB, 0:ncols]: one wave per block, one
-// column per lane, the column held in LDS (registers would spill the triangle)
+// W[k0:k0+TB, 0:ncols] = L11^-1 W[k0:k0+TB, 0:ncols]: one wave per block, one column per
+// lane, staged through LDS and solved in registers; L11 is read from LDS at addresses common
+// to the wave (broadcast)
 constexpr int kTrsmLanes = 64;
 __global__ __launch_bounds__(kTrsmLanes) void trsm_diag_kernel(double* W, const double* L, int n, int k0, int ncols) {
   __shared__ double L11[TB][TB + 1];
   __shared__ double xs[TB][kTrsmLanes];
+  __shared__ double rinv[TB];  // 1 / L11[j][j]
   const int tid = threadIdx.x;
   for (int e = tid; e < TB * TB; e += blockDim.x) {
     const int i = e / TB, j = e % TB;
     const int gi = k0 + i, gj = k0 + j;
     L11[i][j] = (gi < n && gj < n) ? L[(long long)gi * n + gj] : (i == j ? 1.0 : 0.0);
   }
+  if (tid < TB) rinv[tid] = (k0 + tid < n) ? 1.0 / L[(long long)(k0 + tid) * n + k0 + tid] : 1.0;
   const int col = blockIdx.x * kTrsmLanes + tid;
   const bool ok = col < ncols;
   for (int i = 0; i < TB; ++i) xs[i][tid] = (ok && k0 + i < n) ? W[(long long)(k0 + i) * n + col] : 0.0;
   __syncthreads();
+  double xr[TB];
+#pragma clang loop unroll(full)
+  for (int i = 0; i < TB; ++i) xr[i] = xs[i][tid];
+#pragma clang loop unroll(full)
   for (int j = 0; j < TB; ++j) {
-    const double xj = xs[j][tid] / L11[j][j];
-    xs[j][tid] = xj;
-    for (int i = j + 1; i < TB; ++i) xs[i][tid] -= L11[i][j] * xj;
+    const double xj = xr[j] * rinv[j];
+    xr[j] = xj;
+#pragma clang loop unroll(full)
+    for (int i = 0; i < TB; ++i)
+      if (i > j) xr[i] -= L11[i][j] * xj;
   }
+#pragma clang loop unroll(full)
+  for (int i = 0; i < TB; ++i) xs[i][tid] = xr[i];
   if (!ok) return;
   for (int i = 0; i < TB; ++i)
     if (k0 + i < n) W[(long long)(k0 + i) * n + col] = xs[i][tid];
