@@ -11,7 +11,7 @@ basis tables, and runs the multigrid and Krylov algorithms on them.
 
 Modules
   fe          1D tables, quadrature, mesh numbering, tensor-product basis
-  material    degradation function and the volumetric/deviatoric split
+  material    degradation function, the volumetric/deviatoric split and the spectral split
   operator    residual, Jacobian assembly, constraints, diagonal, VJPs
   multigrid   levels, injection, transfers, Lanczos, Chebyshev, V-cycle
   krylov      flexible GMRES with classical Gram-Schmidt twice

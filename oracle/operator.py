@@ -33,11 +33,12 @@ class Material:
     Gc: float
     eps: float
     kappa: float
+    split: str = "amor"   # "amor" (volumetric/deviatoric) or "miehe" (spectral)
 
 
 def material_of(cfg, N=None) -> Material:
     N = cfg.N if N is None else N
-    return Material(cfg.lam, cfg.mu, cfg.Gc, cfg.eps_factor / N, cfg.kappa)
+    return Material(cfg.lam, cfg.mu, cfg.Gc, cfg.eps_factor / N, cfg.kappa, getattr(cfg, "split", "amor"))
 
 
 class CellData:
@@ -56,7 +57,8 @@ class CellData:
         self.phi = pl @ self.N.T                            # (nc, Q)
         self.grad_phi = np.einsum("qpa,np->nqa", self.gradN, pl)
         self.phi_t = phi_t[self.nodes] @ self.N.T
-        self.split = mat.amor_split(self.grad_u, m.lam, m.mu)
+        self.split = (mat.miehe_split(self.grad_u, m.lam, m.mu) if m.split == "miehe"
+                      else mat.amor_split(self.grad_u, m.lam, m.mu))
         self.gt = mat.g(self.phi_t, m.kappa)
         self.dg = mat.dg(self.phi, m.kappa)
         self.ddg = mat.ddg(self.phi, m.kappa)
@@ -86,7 +88,11 @@ def element_jacobians(mesh, m: Material, u, phi, phi_t, cells):
     s = cd.split
     nc = len(cells)
     # delta sigma for every trial basis function: (nc, Q, d, P, d, d)
-    dsig = mat.dsigma(cd.Eb[None], s["H"][:, :, None, None], cd.gt[:, :, None, None], s["K"], m.mu)
+    if m.split == "miehe":
+        sb = dict(H=s["H"][:, :, None, None], ev=s["ev"][:, :, None, None], V=s["V"][:, :, None, None])
+        dsig = mat.dsigma_miehe(cd.Eb[None], sb, cd.gt[:, :, None, None], m.lam, m.mu)
+    else:
+        dsig = mat.dsigma(cd.Eb[None], s["H"][:, :, None, None], cd.gt[:, :, None, None], s["K"], m.mu)
     Ge = np.zeros((nc, (d + 1) * P, (d + 1) * P))
     # G_uu: (delta sigma(trial), e(test))
     Guu = np.einsum("q,nqCPij,qcpij->ncpCP", cd.JxW, dsig, cd.Eb)
