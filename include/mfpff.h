@@ -61,6 +61,13 @@ typedef enum {
 
 typedef enum { MFPFF_F64 = 0, MFPFF_F32 = 1 } mfpff_prec;
 
+/* Tension/compression split of the elastic energy (Section 2.1).  AMOR: volumetric/deviatoric,
+ * E^+ = K/2 <tr e>_+^2 + mu dev e : dev e with K = lambda + 2 mu / dim.  MIEHE: spectral,
+ * E^+ = lambda/2 <tr e>_+^2 + mu e^+ : e^+ with e^+ the positive part of the strain from its
+ * eigensystem; the tangent differentiates e^+ in the eigenbasis (Section 3.5) with divided
+ * differences, which equal Algorithm 2 on distinct eigenvalues. */
+typedef enum { MFPFF_SPLIT_AMOR = 0, MFPFF_SPLIT_MIEHE = 1 } mfpff_split;
+
 typedef enum {
   MFPFF_OP_G = 0,         /* y = G^ x */
   MFPFF_OP_GT = 1,        /* y = G^T-hat x (transpose: coupling moves to the u rows) */
@@ -90,6 +97,7 @@ typedef struct {
   int restart;                      /* GMRES restart length m (<= 64) */
   int max_iter;                     /* total GMRES iteration cap */
   double rtol;                      /* relative true-residual tolerance */
+  int split;                        /* mfpff_split */
 } mfpff_problem;
 
 typedef struct {

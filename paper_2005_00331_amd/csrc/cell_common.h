@@ -9,6 +9,7 @@
 // is evaluated through the tensor-product structure of the unit cell).
 #pragma once
 #include "internal.h"
+#include "miehe.h"
 
 namespace mfpff {
 
@@ -112,7 +113,10 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
   using S = Shape<DIM, K, NT>;
   constexpr int NP = S::NP, P = S::P, NPTS = S::NPTS, CPB = S::CPB;
   constexpr bool XMODE = (MODE == MODE_APPLY || MODE == MODE_APPLY_T || MODE == MODE_BLOCK || MODE == MODE_ELEM);
-  constexpr int NQ = n_qcoef<DIM>();
+  const bool miehe = mp.split == SPLIT_MIEHE;
+  const int NQ = miehe ? n_qcoef_miehe<DIM>() : n_qcoef<DIM>();
+  constexpr int NVG = n_voigt<DIM>();              // Voigt components
+  constexpr int NTAN = NVG * (NVG + 1) / 2;        // stored entries of the spectral Voigt tangent
   // symmetric index pairs of the stored g'(phi) sigma^+ components
   constexpr int SI[6] = {0, 1, DIM == 3 ? 2 : 0, 0, 0, 1};
   constexpr int SJ[6] = {0, 1, DIM == 3 ? 2 : 1, 1, 2, 2};
@@ -174,6 +178,20 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
       const T ddg = T(2) * (T(1) - kap);
       T* q = qcf_out + (long long)p * CPB + c;
       constexpr int QS = P * CPB;  // coefficient stride
+      if (miehe) {
+        // spectral split: upper triangle of the Voigt tangent, g'(phi) sigma^+, g'' E^+ + Gc/eps
+        const MiehePoint<DIM, T> mpt = miehe_point<DIM, T>(e, lam, mu);
+        T Dv[NVG][NVG];
+        miehe_voigt_tangent<DIM, T>(mpt.eig, mpt.H, gt, lam, mu, Dv);
+#pragma unroll
+        for (int r = 0, kk = 0; r < NVG; ++r)
+#pragma unroll
+          for (int c2 = r; c2 < NVG; ++c2, ++kk) q[kk * QS] = Dv[r][c2];
+#pragma unroll
+        for (int k = 0; k < NVG; ++k) q[(NTAN + k) * QS] = dg * mpt.sp[SI[k]][SJ[k]];
+        q[(NQ - 1) * QS] = ddg * mpt.Ep + Gc / eps;
+        return V;
+      }
       q[0] = H ? gt : -gt;
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
@@ -202,9 +220,10 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
     const T cvol = sign_bit(gsv) ? Kb : gta * Kb, cdev = gta * T(2) * mu;
     T gsp[DIM][DIM];
     if (MODE != MODE_BLOCK) {
+      const int co = miehe ? NTAN : 1;  // first coupling coefficient
 #pragma unroll
       for (int k = 0; k < NS; ++k) {
-        const T v = q[(1 + k) * QS];
+        const T v = q[(co + k) * QS];
         gsp[SI[k]][SJ[k]] = v;
         gsp[SJ[k]][SI[k]] = v;
       }
@@ -226,11 +245,32 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
     const T vol = cvol * dt;
     T Su[DIM][DIM];
     T spde = 0;
+    if (miehe) {
+      // Voigt tangent times the engineering strain of the trial function
+      T dv[NVG], sv[NVG];
+#pragma unroll
+      for (int k = 0; k < NVG; ++k) dv[k] = (SI[k] == SJ[k] ? T(1) : T(2)) * de[SI[k]][SJ[k]];
+#pragma unroll
+      for (int r = 0; r < NVG; ++r) sv[r] = T(0);
+#pragma unroll
+      for (int r = 0, kk = 0; r < NVG; ++r)
+#pragma unroll
+        for (int c2 = r; c2 < NVG; ++c2, ++kk) {
+          const T dvk = q[kk * QS];
+          sv[r] += dvk * dv[c2];
+          if (c2 != r) sv[c2] += dvk * dv[r];
+        }
+#pragma unroll
+      for (int k = 0; k < NVG; ++k) {
+        Su[SI[k]][SJ[k]] = sv[k];
+        Su[SJ[k]][SI[k]] = sv[k];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < DIM; ++i)
 #pragma unroll
       for (int j = 0; j < DIM; ++j) {
-        Su[i][j] = cdev * (de[i][j] - (i == j ? dt / T(DIM) : T(0))) + (i == j ? vol : T(0));
+        if (!miehe) Su[i][j] = cdev * (de[i][j] - (i == j ? dt / T(DIM) : T(0))) + (i == j ? vol : T(0));
         if (MODE == MODE_APPLY || MODE == MODE_ELEM) spde += gsp[i][j] * de[i][j];
         if (MODE == MODE_APPLY_T) Su[i][j] += dph * gsp[i][j];
       }
@@ -307,6 +347,19 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
 #pragma unroll
       for (int j = 0; j < DIM; ++j)
         sp[i][j] = T(2) * mu * (e[i][j] - (i == j ? t / T(DIM) : T(0))) + (i == j ? Kb * tp : T(0));
+    // spectral split: sigma^+, sigma^-, E^+ from the eigensystem of e
+    MiehePoint<DIM, T> mpt{};
+    T Fdd[DIM][DIM] = {};
+    if (miehe) {
+      mpt = miehe_point<DIM, T>(e, lam, mu);
+      divided_differences<DIM, T>(mpt.eig, Fdd);
+    }
+    const T EpS = miehe ? mpt.Ep : Ep;
+#pragma unroll
+    for (int i = 0; i < DIM; ++i)
+#pragma unroll
+      for (int j = 0; j < DIM; ++j)
+        if (miehe) sp[i][j] = mpt.sp[i][j];
 
     T Su[DIM][DIM];
     T fval = 0, fgrad[DIM];
@@ -325,14 +378,15 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
         for (int j = 0; j < DIM; ++j) de[i][j] = T(0.5) * (gx[i][j] + gx[j][i]);
         dt += de[i][i];
       }
-      // delta sigma = g~ [K H dt I + 2 mu dev de] + K (1-H) dt I
+      // delta sigma = g~ [K H dt I + 2 mu dev de] + K (1-H) dt I  (spectral split: miehe.h)
       const T vol = (H ? gt * Kb * dt : Kb * dt);
       T spde = 0;
+      if (miehe) miehe_tangent_apply<DIM, T>(mpt.eig, Fdd, H, gt, lam, mu, de, Su);
 #pragma unroll
       for (int i = 0; i < DIM; ++i)
 #pragma unroll
         for (int j = 0; j < DIM; ++j) {
-          Su[i][j] = gt * T(2) * mu * (de[i][j] - (i == j ? dt / T(DIM) : T(0))) + (i == j ? vol : T(0));
+          if (!miehe) Su[i][j] = gt * T(2) * mu * (de[i][j] - (i == j ? dt / T(DIM) : T(0))) + (i == j ? vol : T(0));
           spde += sp[i][j] * de[i][j];
         }
       if (MODE == MODE_APPLY_T) {
@@ -341,7 +395,7 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
 #pragma unroll
           for (int j = 0; j < DIM; ++j) Su[i][j] += dg * dph * sp[i][j];
       }
-      fval = (ddg * Ep + Gc / eps) * dph;
+      fval = (ddg * EpS + Gc / eps) * dph;
       if (MODE == MODE_APPLY || MODE == MODE_ELEM) fval += dg * spde;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) fgrad[m] = Gc * eps * coll_deriv<NP, P, NPTS, T>(V + DIM * NPTS, st.C, m, c, p) * ih;
@@ -349,8 +403,8 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
 #pragma unroll
       for (int i = 0; i < DIM; ++i)
 #pragma unroll
-        for (int j = 0; j < DIM; ++j) Su[i][j] = gt * sp[i][j] + (i == j ? Kb * tm : T(0));
-      fval = dg * Ep - Gc * (T(1) - ph) / eps;
+        for (int j = 0; j < DIM; ++j) Su[i][j] = miehe ? gt * mpt.sp[i][j] + mpt.sm[i][j] : gt * sp[i][j] + (i == j ? Kb * tm : T(0));
+      fval = dg * EpS - Gc * (T(1) - ph) / eps;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) fgrad[m] = Gc * eps * coll_deriv<NP, P, NPTS, T>(V + fph * NPTS, st.C, m, c, p) * ih;
     }

@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
       a.partials[2 * blockIdx.x + 1] = sred[kThreads];
     }
   } else {
-    constexpr int NQ = n_qcoef<DIM>();
+    const int NQ = a.m.split == SPLIT_MIEHE ? n_qcoef_miehe<DIM>() : n_qcoef<DIM>();
     const long long qoff = (long long)blockIdx.x * NQ * P * CPB;
     const T* R = cell_compute<DIM, K, T, MODE, kThreads, QD>(buf0, buf1, st, a.m, (T)g.h, tid, QD ? a.qd + qoff : nullptr,
                                                              MODE == MODE_QDATA ? a.qd_out + qoff : nullptr);
@@ -209,11 +209,27 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
 // with F = D^2 along m and B^2 elsewhere, alpha from the tangent
 // delta sigma = a tr(de) I + b de: alpha_{c,m} = JxW (b/2 + [m=c](a + b/2)) / h^2;
 // diag_phi(p)   = sum_q JxW (g'' E^+ + Gc/eps) B^2... + sum_m JxW Gc eps / h^2 (...).
-template <int DIM, int K, typename T>
+// Spectral split (SPLIT): the tangent is a full Voigt matrix Dv at each point, so with
+// v(c, m) the Voigt index of the strain pair (c, m), alpha_{c,m} = JxW Dv[v(c,m)][v(c,m)] / h^2
+// and the cross terms m < m' add beta = 2 JxW Dv[v(c,m)][v(c,m')] / h^2 times the product of
+// B D along m and m' and B^2 elsewhere.
+template <int DIM>
+__device__ __forceinline__ int voigt_of(int c, int m) {
+  if (c == m) return c;
+  if (DIM == 2) return 2;
+  const int lo = c < m ? c : m, hi = c < m ? m : c;
+  return lo == 0 ? (hi == 1 ? 3 : 4) : 5;
+}
+
+template <int DIM, int K, typename T, int SPLIT = SPLIT_AMOR>
 __global__ __launch_bounds__(kThreads) void diag_kernel(CellArgs<T> a, const Tables<T>* __restrict__ tab) {
   using S = Shape<DIM, K>;
-  constexpr int NP = S::NP, P = S::P, CPB = S::CPB, NPTS = S::NPTS, NBUF = S::NBUF;
-  __shared__ T sB[NP * NP], sC[NP * NP], sB2t[NP * NP], sD2t[NP * NP], sW[NP];  // basis, collocation, squared tables
+  constexpr int NP = S::NP, P = S::P, CPB = S::CPB, NPTS = S::NPTS;
+  constexpr int NT = DIM * (DIM + 1) + 1;                    // isotropic fields
+  constexpr int NPAIR = DIM * (DIM - 1) / 2;                 // pairs m < m'
+  constexpr int NX = SPLIT == SPLIT_MIEHE ? NT + DIM * NPAIR : NT;
+  constexpr int NBUF = NX > S::NBUF ? NX : S::NBUF;
+  __shared__ T sB[NP * NP], sC[NP * NP], sB2t[NP * NP], sD2t[NP * NP], sBDt[NP * NP], sW[NP];
   __shared__ T buf0[NBUF * NPTS];
   __shared__ T buf1[NBUF * NPTS];
   const int tid = threadIdx.x;
@@ -223,6 +239,7 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(CellArgs<T> a, const Tab
     sC[tid] = tab->C[q][i];
     sB2t[i * NP + q] = tab->B[q][i] * tab->B[q][i];
     sD2t[i * NP + q] = tab->D[q][i] * tab->D[q][i];
+    sBDt[i * NP + q] = tab->B[q][i] * tab->D[q][i];
   }
   if (tid < NP) sW[tid] = tab->w[tid];
   const Geom g = a.g;
@@ -255,12 +272,13 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(CellArgs<T> a, const Tab
   const T ih = T(1) / h;
   const T lam = (T)a.m.lam, mu = (T)a.m.mu, Gc = (T)a.m.Gc, eps = (T)a.m.eps, kap = (T)a.m.kappa;
   const T Kb = lam + T(2) * mu / T(DIM);
-  constexpr int NT = DIM * (DIM + 1) + 1;
+  // the phase-field terms (phi rows) use E^+ of the split; g'' E^+ is read where the split is spectral
+  T gu[DIM][DIM];
+  T jxw = 0;
   if (inb) {
     const int o = c * P + p;
-    T jxw = sW[p % NP] * sW[(p / NP) % NP] * h * h;
+    jxw = sW[p % NP] * sW[(p / NP) % NP] * h * h;
     if (DIM == 3) jxw *= sW[p / (NP * NP)] * h;
-    T gu[DIM][DIM];
 #pragma unroll
     for (int cc = 0; cc < DIM; ++cc)
 #pragma unroll
@@ -280,23 +298,52 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(CellArgs<T> a, const Tab
         const T dv = eij - (i == j ? t / T(DIM) : T(0));
         devdev += dv * dv;
       }
-    const T Ep = T(0.5) * Kb * tp * tp + mu * devdev;
+    T Ep = T(0.5) * Kb * tp * tp + mu * devdev;
     const T gt = (T(1) - kap) * pt * pt + kap;
     const T ddg = T(2) * (T(1) - kap);
-    const T av = (H ? gt * Kb : Kb) - T(2) * mu * gt / T(DIM);
-    const T bv = T(2) * mu * gt;
     const T ih2 = ih * ih;
+    if (SPLIT == SPLIT_MIEHE) {
+      T e[DIM][DIM];
 #pragma unroll
-    for (int m = 0; m < DIM; ++m) {
+      for (int i = 0; i < DIM; ++i)
+#pragma unroll
+        for (int j = 0; j < DIM; ++j) e[i][j] = T(0.5) * (gu[i][j] + gu[j][i]);
+      const MiehePoint<DIM, T> mpt = miehe_point<DIM, T>(e, lam, mu);
+      Ep = mpt.Ep;
+      T Dv[n_voigt<DIM>()][n_voigt<DIM>()];
+      miehe_voigt_tangent<DIM, T>(mpt.eig, mpt.H, gt, lam, mu, Dv);
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+#pragma unroll
+        for (int cc = 0; cc < DIM; ++cc) {
+          const int vm = voigt_of<DIM>(cc, m);
+          W[(m * (DIM + 1) + cc) * NPTS + o] = jxw * ih2 * Dv[vm][vm];
+        }
+        W[(m * (DIM + 1) + DIM) * NPTS + o] = jxw * ih2 * Gc * eps;
+      }
 #pragma unroll
       for (int cc = 0; cc < DIM; ++cc)
-        W[(m * (DIM + 1) + cc) * NPTS + o] = jxw * ih2 * (T(0.5) * bv + (m == cc ? av + T(0.5) * bv : T(0)));
-      W[(m * (DIM + 1) + DIM) * NPTS + o] = jxw * ih2 * Gc * eps;
+#pragma unroll
+        for (int pi = 0, m = 0; m < DIM; ++m)
+#pragma unroll
+          for (int m2 = m + 1; m2 < DIM; ++m2, ++pi)
+            W[(NT + cc * NPAIR + pi) * NPTS + o] = jxw * ih2 * T(2) * Dv[voigt_of<DIM>(cc, m)][voigt_of<DIM>(cc, m2)];
+    } else {
+      const T av = (H ? gt * Kb : Kb) - T(2) * mu * gt / T(DIM);
+      const T bv = T(2) * mu * gt;
+#pragma unroll
+      for (int m = 0; m < DIM; ++m) {
+#pragma unroll
+        for (int cc = 0; cc < DIM; ++cc)
+          W[(m * (DIM + 1) + cc) * NPTS + o] = jxw * ih2 * (T(0.5) * bv + (m == cc ? av + T(0.5) * bv : T(0)));
+        W[(m * (DIM + 1) + DIM) * NPTS + o] = jxw * ih2 * Gc * eps;
+      }
     }
     W[(NT - 1) * NPTS + o] = jxw * (ddg * Ep + Gc / eps);
   }
   __syncthreads();
-  // three transposed sweeps with per-tensor matrices (D^2 along its own direction)
+  // three transposed sweeps with per-tensor matrices (D^2 along its own direction; B D along
+  // both directions of a cross term)
   T* in = W;
   T* out = V;
 #pragma unroll
@@ -305,9 +352,19 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(CellArgs<T> a, const Tab
       const int st = dir == 0 ? 1 : (dir == 1 ? NP : NP * NP);
       const int dg = (p / st) % NP;
       const int base = c * P + p - dg * st;
-      for (int f = 0; f < NT; ++f) {
-        const int grp = f / (DIM + 1);
-        const T* mrow = ((f < NT - 1) && grp == dir ? sD2t : sB2t) + dg * NP;
+      for (int f = 0; f < NX; ++f) {
+        const T* tabr;
+        if (f < NT) {
+          const int grp = f / (DIM + 1);
+          tabr = ((f < NT - 1) && grp == dir ? sD2t : sB2t);
+        } else {
+          // pair index -> (m, m')
+          const int pi = (f - NT) % (NPAIR > 0 ? NPAIR : 1);
+          const int m = (DIM == 2 || pi < 2) ? 0 : 1;
+          const int m2 = DIM == 2 ? 1 : (pi == 0 ? 1 : 2);
+          tabr = (dir == m || dir == m2) ? sBDt : sB2t;
+        }
+        const T* mrow = tabr + dg * NP;
         const T* src = in + f * NPTS + base;
         T acc = 0;
 #pragma unroll
@@ -327,6 +384,10 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(CellArgs<T> a, const Tab
       T s = 0;
 #pragma unroll
       for (int m = 0; m < DIM; ++m) s += in[(m * (DIM + 1) + cc) * NPTS + o];
+      if (SPLIT == SPLIT_MIEHE) {
+#pragma unroll
+        for (int pi = 0; pi < NPAIR; ++pi) s += in[(NT + cc * NPAIR + pi) * NPTS + o];
+      }
       atomic_add(a.y + cc * nn + node, s);
     }
     T s = in[(NT - 1) * NPTS + o];
@@ -407,8 +468,12 @@ hipError_t launch_diag(const CellArgs<T>& a, const Tables<T>* tab, hipStream_t s
   if (nb <= 0) return hipSuccess;
   dim3 grid((unsigned)nb), block(kThreads);
   const int d = a.g.dim, k = a.g.k;
-#define MFPFF_CASE(D, KK) \
-  if (d == D && k == KK) { hipLaunchKernelGGL((diag_kernel<D, KK, T>), grid, block, 0, s, a, tab); return hipGetLastError(); }
+#define MFPFF_CASE(D, KK)                                                                             \
+  if (d == D && k == KK) {                                                                            \
+    if (a.m.split == SPLIT_MIEHE) hipLaunchKernelGGL((diag_kernel<D, KK, T, SPLIT_MIEHE>), grid, block, 0, s, a, tab); \
+    else hipLaunchKernelGGL((diag_kernel<D, KK, T>), grid, block, 0, s, a, tab);                      \
+    return hipGetLastError();                                                                         \
+  }
   MFPFF_CASE(2, 1) MFPFF_CASE(2, 2) MFPFF_CASE(2, 3) MFPFF_CASE(2, 4)
   MFPFF_CASE(3, 1) MFPFF_CASE(3, 2) MFPFF_CASE(3, 3) MFPFF_CASE(3, 4)
 #undef MFPFF_CASE
@@ -422,9 +487,9 @@ hipError_t launch_diag(const CellArgs<T>& a, const Tables<T>* tab, hipStream_t s
 //   EPI_CHEB:  d = c1 d + c2 D^-1 (r - G^_blk z), z' = z + d (optional xout = xacc + z').
 // Fixed rows take the identity.  Workgroups are mapped so that each XCD works on one
 // contiguous range of nodes (its L2 then holds the element lines its nodes share).
-long long cell_qdata_len(const Geom& g) {
+long long cell_qdata_len(const Geom& g, int split) {
   const long long P = (long long)(g.k + 1) * (g.k + 1) * (g.k + 1);
-  return cell_blocks(g, MODE_APPLY) * cpb_of(g.dim, g.k) * P * n_qcoef<3>();
+  return cell_blocks(g, MODE_APPLY) * cpb_of(g.dim, g.k) * P * (split == SPLIT_MIEHE ? n_qcoef_miehe<3>() : n_qcoef<3>());
 }
 
 long long elem_len(const Geom& g) {

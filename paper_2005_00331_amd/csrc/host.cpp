@@ -270,7 +270,7 @@ template <typename T>
 CellArgs<T> cell_args(mfpff_ctx* c, const Level& L, const T* lin, const T* x, T* y, T scale) {
   CellArgs<T> a{};
   a.g = L.g;
-  a.m = MatParams{c->prob.lambda, c->prob.mu, c->prob.Gc, c->prob.eps, c->prob.kappa};
+  a.m = MatParams{c->prob.lambda, c->prob.mu, c->prob.Gc, c->prob.eps, c->prob.kappa, c->prob.split};
   a.x = x;
   a.y = y;
   a.u = lin;
@@ -968,6 +968,7 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
   if (p.cheb_degree < 1 || p.cheb_degree > 32 || p.lanczos_steps < 0 || p.lanczos_steps > 64) return MFPFF_ERR_ARG;
   if (p.restart < 1 || p.restart > 64 || p.max_iter < 0 || !(p.rtol >= 0.0)) return MFPFF_ERR_ARG;
   if (p.vcycle_prec != MFPFF_F64 && p.vcycle_prec != MFPFF_F32) return MFPFF_ERR_ARG;
+  if (p.split != MFPFF_SPLIT_AMOR && p.split != MFPFF_SPLIT_MIEHE) return MFPFF_ERR_ARG;
   if (!(p.eps > 0.0) || !(p.kappa >= 0.0) || !(p.cheb_hi > p.cheb_lo) || !(p.cheb_lo > 0.0)) return MFPFF_ERR_ARG;
   for (int l = 0; l < p.n_levels; ++l) {
     if (p.level_N[l] < 1 || p.level_k[l] < 1 || p.level_k[l] > kMaxDeg) return MFPFF_ERR_ARG;
@@ -1008,7 +1009,7 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
         if (eb > elem_bytes) elem_bytes = eb;
       }
       if ((d == 2 && L.g.k <= 2) || d == 3) {
-        const size_t nq = (size_t)(d == 2 ? rowcell_qdata_len(L.g) : cell_qdata_len(L.g));
+        const size_t nq = (size_t)(d == 2 ? rowcell_qdata_len(L.g, p.split) : cell_qdata_len(L.g, p.split));
         L.qd = dalloc<double>(nq);
         if (c->f32) L.qd32 = dalloc<float>(nq);
       }

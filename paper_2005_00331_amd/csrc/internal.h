@@ -47,6 +47,7 @@ struct Geom {
 
 struct MatParams {
   double lam, mu, Gc, eps, kappa;
+  int split;  // SplitKind: 0 volumetric/deviatoric (Amor), 1 spectral (Miehe)
 };
 
 // 1D tables of one degree k on the unit interval (q = k+1 Gauss points):
@@ -84,7 +85,7 @@ enum CellMode : int {
 // layout [tile][coefficient][Gauss row][Gauss column][cell of the tile],
 // rowcell_qdata_len values per level
 constexpr int kQCoef = 5;
-long long rowcell_qdata_len(const Geom& g);
+long long rowcell_qdata_len(const Geom& g, int split);
 
 template <typename T>
 struct CellArgs {
@@ -129,7 +130,7 @@ long long elem_len(const Geom& g);  // values in the element buffer of one level
 // one thread per node line (linecell_kernel.hip); a.qd and a.elem required
 template <typename T>
 hipError_t launch_linecell(int mode, const CellArgs<T>& a, const Tables<T>* tab_dev, hipStream_t s);
-long long cell_qdata_len(const Geom& g);  // 3D: values of the cached tangent coefficients of one level
+long long cell_qdata_len(const Geom& g, int split);  // 3D: values of the cached tangent coefficients of one level
 template <typename T>
 hipError_t launch_tile_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<T>* tab, hipStream_t s);
 long long tile_blocks_2d(const Geom& g);

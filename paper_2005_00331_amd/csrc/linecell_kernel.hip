@@ -17,6 +17,7 @@
 // A workgroup takes NOB consecutive blocks of that layout (CPB cells each), so the
 // coefficient cache and the element buffer are read and written in its order.
 #include "cell_common.h"
+#include "miehe.h"
 
 namespace mfpff {
 
@@ -37,9 +38,11 @@ struct LineShape {
 // waves per SIMD the register allocation must allow: four (at most 128 VGPRs) wherever the
 // 13 (k+1) values a thread holds at its Gauss points fit without spilling; three for FP64 Q3,
 // two for FP64 Q4
-template <int K, typename T>
+template <int K, typename T, int SPLIT>
 struct LineWaves {
-  static constexpr int value = (K <= 2 || sizeof(T) == 4) ? 4 : (K == 3 ? 3 : 2);
+  static constexpr int amor = (K <= 2 || sizeof(T) == 4) ? 4 : (K == 3 ? 3 : 2);
+  // the spectral split reads the 21 entries of the Voigt tangent per point: one wave fewer
+  static constexpr int value = SPLIT == 1 ? (amor > 2 ? amor - 1 : 2) : amor;
 };
 
 }  // namespace
@@ -57,12 +60,15 @@ long long linecell_blocks(const Geom& g) {
   return (nc + cw - 1) / cw;
 }
 
-template <int K, typename T, int MODE>
-__global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_eu(LineWaves<K, T>::value))) void linecell_kernel(
+// SPLIT: the cached coefficients are those of the volumetric/deviatoric split or of the
+// spectral split (upper triangle of the Voigt tangent, coupling, phase coefficient)
+template <int K, typename T, int MODE, int SPLIT = SPLIT_AMOR>
+__global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_eu(LineWaves<K, T, SPLIT>::value))) void linecell_kernel(
     CellArgs<T> a, const Tables<T>* __restrict__ tabd) {
   using S = LineShape<K>;
   constexpr int NP = S::NP, P = S::P, L = S::L, CPB = S::CPB, CW = S::CW, TS = S::TS;
-  constexpr int NQ = n_qcoef<3>();
+  constexpr int NQ = SPLIT == SPLIT_MIEHE ? n_qcoef_miehe<3>() : n_qcoef<3>();
+  constexpr int CO = SPLIT == SPLIT_MIEHE ? 21 : 1;  // first coupling coefficient
   constexpr int NC = 4;
   __shared__ T lds[5 * TS];
   T* bufA = lds;           // two tensors
@@ -210,7 +216,7 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
     if (MODE != MODE_BLOCK) {
 #pragma unroll
       for (int k = 0; k < 6; ++k) {
-        const T v = keep_if(qq[(1 + k) * QS], valid);
+        const T v = keep_if(qq[(CO + k) * QS], valid);
         gsp[SI[k]][SJ[k]] = v;
         gsp[SJ[k]][SI[k]] = v;
       }
@@ -227,11 +233,33 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
     const T dph = pv[q];
     T Su[3][3];
     T spde = 0;
+    if (SPLIT == SPLIT_MIEHE) {
+      // Voigt tangent times the engineering strain
+      T dv[6], sv[6];
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        dv[k] = (k < 3 ? T(1) : T(2)) * de[SI[k]][SJ[k]];
+        sv[k] = T(0);
+      }
+#pragma unroll
+      for (int r = 0, kk = 0; r < 6; ++r)
+#pragma unroll
+        for (int c2 = r; c2 < 6; ++c2, ++kk) {
+          const T dk = keep_if(qq[kk * QS], valid);
+          sv[r] += dk * dv[c2];
+          if (c2 != r) sv[c2] += dk * dv[r];
+        }
+#pragma unroll
+      for (int k = 0; k < 6; ++k) {
+        Su[SI[k]][SJ[k]] = sv[k];
+        Su[SJ[k]][SI[k]] = sv[k];
+      }
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i)
 #pragma unroll
       for (int j = 0; j < 3; ++j) {
-        Su[i][j] = cdev * (de[i][j] - (i == j ? dt / T(3) : T(0))) + (i == j ? vol : T(0));
+        if (SPLIT != SPLIT_MIEHE) Su[i][j] = cdev * (de[i][j] - (i == j ? dt / T(3) : T(0))) + (i == j ? vol : T(0));
         if (MODE == MODE_APPLY) spde += gsp[i][j] * de[i][j];
         if (MODE == MODE_APPLY_T) Su[i][j] += dph * gsp[i][j];
       }
@@ -334,10 +362,17 @@ static hipError_t launch_lk(int mode, const CellArgs<T>& a, const Tables<T>* tab
   if (nb <= 0) return hipSuccess;
   if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid((unsigned)nb), block(LineShape<K>::NT);
+  const bool miehe = a.m.split == SPLIT_MIEHE;
   switch (mode) {
-    case MODE_APPLY: hipLaunchKernelGGL((linecell_kernel<K, T, MODE_APPLY>), grid, block, 0, s, a, tab); break;
-    case MODE_APPLY_T: hipLaunchKernelGGL((linecell_kernel<K, T, MODE_APPLY_T>), grid, block, 0, s, a, tab); break;
-    case MODE_BLOCK: hipLaunchKernelGGL((linecell_kernel<K, T, MODE_BLOCK>), grid, block, 0, s, a, tab); break;
+#define MFPFF_L(MD)                                                                                       \
+  case MD:                                                                                                \
+    if (miehe) hipLaunchKernelGGL((linecell_kernel<K, T, MD, SPLIT_MIEHE>), grid, block, 0, s, a, tab);   \
+    else hipLaunchKernelGGL((linecell_kernel<K, T, MD>), grid, block, 0, s, a, tab);                     \
+    break;
+    MFPFF_L(MODE_APPLY)
+    MFPFF_L(MODE_APPLY_T)
+    MFPFF_L(MODE_BLOCK)
+#undef MFPFF_L
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -21,6 +21,7 @@
 // threads then apply the epilogue of the operation (product, residual with the
 // Chebyshev start, Chebyshev step).
 #include "internal.h"
+#include "miehe.h"
 
 namespace mfpff {
 
@@ -43,16 +44,20 @@ long long rowcell_blocks_2d(const Geom& g) {
   const long long nt = (g.N + kRowOwn - 1) / kRowOwn;
   return nt * nt;
 }
-long long rowcell_qdata_len(const Geom& g) {
-  return rowcell_blocks_2d(g) * kQCoef * (g.k + 1) * (g.k + 1) * kRowCells;
+long long rowcell_qdata_len(const Geom& g, int split) {
+  return rowcell_blocks_2d(g) * (split == SPLIT_MIEHE ? n_qcoef_miehe<2>() : kQCoef) * (g.k + 1) * (g.k + 1) * kRowCells;
 }
 
-// at most 128 VGPRs: four wavefronts per SIMD (the FP64 products issue well below peak with one or two)
+// at most 128 VGPRs: four wavefronts per SIMD (the FP64 products issue well below peak with one or two);
+// three for the spectral split (its Voigt tangent holds twice the coefficients), none for MODE_QDATA
 // QD: the tangent coefficients come from a.qd instead of being computed from u, phi, phi~
 // EARLY (grids of at most two workgroups per CU, where occupancy does not matter): the epilogue
 // operands are loaded with the cell inputs, so the kernel waits for memory once, not twice
-template <int K, typename T, int MODE, int EPI, bool QD, bool EARLY>
-__global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_eu(EARLY ? 1 : 4))) void rowcell_kernel_2d(
+// SPLIT (products from the cache): the cached coefficients are those of the volumetric/
+// deviatoric split (kQCoef per point) or of the spectral split (the Voigt tangent, the coupling
+// and the phase coefficient, n_qcoef_miehe<2>() per point); MODE_QDATA writes either by a.m.split
+template <int K, typename T, int MODE, int EPI, bool QD, bool EARLY, int SPLIT = SPLIT_AMOR>
+__global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_eu(EARLY || MODE == MODE_QDATA ? 1 : (SPLIT == SPLIT_MIEHE ? 3 : 4)))) void rowcell_kernel_2d(
     CellArgs<T> a, Epilogue<T> e, Tab2<K + 1, T> tb, const Tables<T>* __restrict__ tabd) {
   constexpr int NP = K + 1;
   constexpr int NT = kRowCells * NP;
@@ -113,11 +118,12 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   }
   // cached tangent coefficients of the Gauss row r, stored per tile (halo cells included) so
   // that every load of a wavefront reads 64 consecutive values
-  const T* qtile = a.qd + (long long)blockIdx.x * kQCoef * NP * NP * kRowCells + (r * NP) * kRowCells + cl;
-  T qc[kQCoef][NP];
+  constexpr int NQR = SPLIT == SPLIT_MIEHE ? n_qcoef_miehe<2>() : kQCoef;
+  const T* qtile = a.qd + (long long)blockIdx.x * NQR * NP * NP * kRowCells + (r * NP) * kRowCells + cl;
+  T qc[NQR][NP];
   if (QD) {
 #pragma unroll
-    for (int c = 0; c < kQCoef; ++c)
+    for (int c = 0; c < NQR; ++c)
 #pragma unroll
       for (int q0 = 0; q0 < NP; ++q0) qc[c][q0] = qtile[(c * NP * NP + q0) * kRowCells];
   }
@@ -132,7 +138,7 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   }
   if (QD) {
 #pragma unroll
-    for (int c = 0; c < kQCoef; ++c)
+    for (int c = 0; c < NQR; ++c)
 #pragma unroll
       for (int q0 = 0; q0 < NP; ++q0) qc[c][q0] = keep_if(qc[c][q0], valid);
   }
@@ -287,14 +293,26 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   // gs = g(phi~) with its sign bit set where tr e < 0 (compression), so the two split
   // coefficients g K or K and 2 mu g come from one stored value, bit for bit
   T gs[NP], sxx[NP], syy[NP], sxy[NP], cpp[NP];
+  constexpr int NQM = n_qcoef_miehe<2>();
+  const bool miehe_rt = a.m.split == SPLIT_MIEHE;  // MODE_QDATA: which coefficients to write
+  T mq[MODE == MODE_QDATA ? NQM : 1][NP];
 #pragma unroll
   for (int q0 = 0; q0 < NP; ++q0) {
     if (QD) {
-      gs[q0] = qc[0][q0];
-      sxx[q0] = qc[1][q0];
-      syy[q0] = qc[2][q0];
-      sxy[q0] = qc[3][q0];
-      cpp[q0] = qc[4][q0];
+      if (SPLIT == SPLIT_MIEHE) {
+        // Voigt tangent (upper triangle) stays in qc[0..5]; coupling and phase coefficient
+        gs[q0] = T(0);
+        sxx[q0] = qc[6][q0];
+        syy[q0] = qc[7][q0];
+        sxy[q0] = qc[8][q0];
+        cpp[q0] = qc[9][q0];
+      } else {
+        gs[q0] = qc[0][q0];
+        sxx[q0] = qc[1][q0];
+        syy[q0] = qc[2][q0];
+        sxy[q0] = qc[3][q0];
+        cpp[q0] = qc[4][q0];
+      }
       continue;
     }
     const T exx = gu00[q0] * ih, eyy = gu11[q0] * ih;
@@ -312,10 +330,33 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
     syy[q0] = dg * (T(2) * mu * dyy + Kb * tp);
     sxy[q0] = dg * (T(2) * mu * exy);
     cpp[q0] = T(2) * (T(1) - kap) * Ep + Gc / eps;
+    if (MODE == MODE_QDATA && miehe_rt) {
+      const T e2[2][2] = {{exx, exy}, {exy, eyy}};
+      const MiehePoint<2, T> mpt = miehe_point<2, T>(e2, lam, mu);
+      T Dv[3][3];
+      miehe_voigt_tangent<2, T>(mpt.eig, mpt.H, gt, lam, mu, Dv);
+      mq[0][q0] = Dv[0][0];
+      mq[1][q0] = Dv[0][1];
+      mq[2][q0] = Dv[0][2];
+      mq[3][q0] = Dv[1][1];
+      mq[4][q0] = Dv[1][2];
+      mq[5][q0] = Dv[2][2];
+      mq[6][q0] = dg * mpt.sp[0][0];
+      mq[7][q0] = dg * mpt.sp[1][1];
+      mq[8][q0] = dg * mpt.sp[0][1];
+      mq[NQM - 1][q0] = T(2) * (T(1) - kap) * mpt.Ep + Gc / eps;
+    }
   }
 
   if (MODE == MODE_QDATA) {
-    if (valid) {
+    if (valid && miehe_rt) {
+      T* o = a.qd_out + (long long)blockIdx.x * NQM * NP * NP * kRowCells + (r * NP) * kRowCells + cl;
+      constexpr int cs = NP * NP * kRowCells;
+#pragma unroll
+      for (int c = 0; c < NQM; ++c)
+#pragma unroll
+        for (int q0 = 0; q0 < NP; ++q0) o[c * cs + q0 * kRowCells] = mq[MODE == MODE_QDATA ? c : 0][q0];
+    } else if (valid) {
       T* o = a.qd_out + (long long)blockIdx.x * kQCoef * NP * NP * kRowCells + (r * NP) * kRowCells + cl;
       constexpr int cs = NP * NP * kRowCells;  // coefficient stride
 #pragma unroll
@@ -374,6 +415,13 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
     T Sxx = cdev[q0] * dxx + vol;
     T Syy = cdev[q0] * dyy + vol;
     T Sxy = cdev[q0] * dxy;
+    if (QD && SPLIT == SPLIT_MIEHE) {
+      // Voigt tangent times the engineering strain (dxx, dyy, 2 dxy)
+      const T d2 = T(2) * dxy;
+      Sxx = qc[0][q0] * dxx + qc[1][q0] * dyy + qc[2][q0] * d2;
+      Syy = qc[1][q0] * dxx + qc[3][q0] * dyy + qc[4][q0] * d2;
+      Sxy = qc[2][q0] * dxx + qc[4][q0] * dyy + qc[5][q0] * d2;
+    }
     const T dph = pv[q0];
     T fv = cpp[q0] * dph;
     if (MODE == MODE_APPLY) fv += sxx[q0] * dxx + syy[q0] * dyy + T(2) * sxy[q0] * dxy;
@@ -463,15 +511,21 @@ static hipError_t launch_row_k(int mode, int epi, const CellArgs<T>& a, const Ep
   const long long nb = rowcell_blocks_2d(a.g);
   const bool early = nb <= 512;
   dim3 grid((unsigned)nb), block(kRowCells * (K + 1));
-#define MFPFF_R(MD, EP)                                                                                        \
-  if (mode == MD && epi == EP) {                                                                               \
-    if (a.qd && early)                                                                                         \
-      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, true>), grid, block, 0, s, a, e, tb, tabd);    \
-    else if (a.qd)                                                                                             \
-      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, false>), grid, block, 0, s, a, e, tb, tabd);   \
-    else                                                                                                       \
-      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, false, false>), grid, block, 0, s, a, e, tb, tabd);  \
-    return hipGetLastError();                                                                                  \
+  const bool miehe = a.m.split == SPLIT_MIEHE;
+  if (miehe && !a.qd && mode != MODE_QDATA) return hipErrorInvalidValue;  // spectral products read the cache
+#define MFPFF_R(MD, EP)                                                                                              \
+  if (mode == MD && epi == EP) {                                                                                     \
+    if (miehe && early)                                                                                              \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, true, SPLIT_MIEHE>), grid, block, 0, s, a, e, tb, tabd); \
+    else if (miehe)                                                                                                  \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, false, SPLIT_MIEHE>), grid, block, 0, s, a, e, tb, tabd); \
+    else if (a.qd && early)                                                                                          \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, true>), grid, block, 0, s, a, e, tb, tabd);          \
+    else if (a.qd)                                                                                                   \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, false>), grid, block, 0, s, a, e, tb, tabd);         \
+    else                                                                                                             \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, false, false>), grid, block, 0, s, a, e, tb, tabd);        \
+    return hipGetLastError();                                                                                        \
   }
   if (mode == MODE_QDATA) {
     hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MODE_QDATA, EPI_APPLY, false, false>), grid, block, 0, s, a, e, tb, tabd);

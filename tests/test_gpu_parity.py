@@ -120,7 +120,7 @@ def test_coarse_solve_and_vcycle(name):
     assert e <= 1e-10, (name, e)
 
 
-@pytest.mark.parametrize("name", ["3d_q2_f32", "3d_q3_f32", "3d_q4_f32", "2d_q2_f32"])
+@pytest.mark.parametrize("name", ["3d_q2_f32", "3d_q3_f32", "3d_q4_f32", "2d_q2_f32", "2d_q2_miehe_f32", "3d_q2_miehe_f32"])
 def test_fp32_level_products(name):
     import torch
     from paper_2005_00331_amd import F32, OP_BLOCKDIAG, OP_G

@@ -18,7 +18,8 @@ def _ctx(cfg, levels, **kw):
     return Context(problem_from(cfg, levels, **kw))
 
 
-@pytest.mark.parametrize("name,kw", [("C1", {}), ("C2", dict(N=10)), ("C5", dict(N=4)), ("C4", dict(N=3, k=3))])
+@pytest.mark.parametrize("name,kw", [("C1", {}), ("C2", dict(N=10)), ("C5", dict(N=4)), ("C4", dict(N=3, k=3)),
+                                     ("C2", dict(N=10, split="miehe")), ("C5", dict(N=4, split="miehe"))])
 def test_residual_and_param_vjp(name, kw):
     cfg = CONFIGS[name].with_(n_h_levels=1, p_coarse=(), **kw)
     inp = make_inputs(cfg, ("cotangent",))
@@ -51,7 +52,9 @@ def test_active_set_matches_oracle_rule():
 
 @pytest.mark.parametrize("name,kw,prec", [("C1", {}, "f64"), ("C2", dict(N=16, n_h_levels=3), "f64"),
                                           ("C3", dict(N=4, n_h_levels=2), "f64"),
-                                          ("C3", dict(N=4, n_h_levels=2), "f32")])
+                                          ("C3", dict(N=4, n_h_levels=2), "f32"),
+                                          ("C2", dict(N=16, n_h_levels=3, split="miehe"), "f64"),
+                                          ("C3", dict(N=4, n_h_levels=2, split="miehe"), "f32")])
 def test_fgmres_solve(name, kw, prec):
     cfg = CONFIGS[name].with_(**kw)
     levels = level_list(cfg)
