@@ -25,10 +25,11 @@ def sample_nodes(cfg, n_random, seed):
     return np.array(sorted(set(int(p) for p in picks)))
 
 
-@pytest.mark.parametrize("name,n_random", [("C2", 40), ("C3", 24), ("C4", 8), ("C5", 24)])
-def test_fullsize_sampled_rows(name, n_random):
+@pytest.mark.parametrize("name,n_random,split", [("C2", 40, "amor"), ("C3", 24, "amor"), ("C4", 8, "amor"),
+                                                 ("C5", 24, "amor"), ("C2", 24, "miehe"), ("C3", 12, "miehe")])
+def test_fullsize_sampled_rows(name, n_random, split):
     from paper_2005_00331_amd import OP_G, OP_GT, Context, problem_from
-    cfg = CONFIGS[name]
+    cfg = CONFIGS[name].with_(split=split)
     levels = level_list(cfg)
     inp = make_inputs(cfg)
     mesh = Mesh(cfg.dim, cfg.N, cfg.k)
@@ -36,7 +37,7 @@ def test_fullsize_sampled_rows(name, n_random):
     nodes = sample_nodes(cfg, n_random, 31)
     rows = np.stack([c * mesh.n_nodes + nodes for c in range(cfg.dim + 1)])
     pvec = op.free_vector(mesh, inp["active"], cfg.dirichlet)
-    say(name, "full size", mesh.n_dofs, "dofs, levels", levels)
+    say(name, split, "full size", mesh.n_dofs, "dofs, levels", levels)
     ctx = Context(problem_from(cfg, levels))
     args = (dev(inp["u"]), dev(inp["phi"]), dev(inp["phi_old"]), dev(inp["active"]), dev(inp["phi_tilde"]))
     full = len(levels) > 1
