@@ -49,7 +49,8 @@ def test_invalid_problems_rejected_without_device(lib):
     lib = binding._lib
     h = ctypes.c_void_p()
     good = binding.make_problem(2, [(4, 1), (8, 1)], eps=0.25)
-    for field, bad in [("dim", 5), ("n_levels", 0), ("cheb_degree", 0), ("restart", 0), ("vcycle_prec", 7)]:
+    for field, bad in [("dim", 5), ("n_levels", 0), ("cheb_degree", 0), ("restart", 0), ("vcycle_prec", 7),
+                       ("split", 2)]:
         p = binding.make_problem(2, [(4, 1), (8, 1)], eps=0.25)
         setattr(p, field, bad)
         assert lib.mfpff_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
@@ -69,3 +70,41 @@ def test_null_context_paths(lib):
     L.mfpff_destroy(None)
     d = binding.LevelDesc()
     assert L.mfpff_level_info(None, 0, ctypes.byref(d)) == 1
+
+
+def _c_struct_fields(name):
+    """(type, field) pairs of a typedef struct in the header, arrays as (type, field, length)."""
+    txt = open(HEADER).read()
+    end = re.search(r"\}\s*" + name + ";", txt).start()
+    body = txt[txt.rindex("typedef struct {", 0, end) + len("typedef struct {"):end]
+    body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
+    out = []
+    for decl in body.split(";"):
+        decl = " ".join(decl.split())
+        if not decl:
+            continue
+        m = re.match(r"(unsigned long long|long long|double|int) (.*)", decl)
+        assert m, decl
+        for v in m.group(2).split(","):
+            v = v.strip()
+            a = re.match(r"(\w+)\[(\w+)\]", v)
+            out.append((m.group(1), a.group(1), a.group(2)) if a else (m.group(1), v))
+    return out
+
+
+def test_problem_structure_matches_header():
+    """The ctypes structures mirror the header field by field, in order and type."""
+    import ctypes as C
+    from paper_2005_00331_amd import binding
+    ctype = {"int": C.c_int, "double": C.c_double, "unsigned long long": C.c_ulonglong, "long long": C.c_longlong}
+    for cname, pyst in (("mfpff_problem", binding.Problem), ("mfpff_solve_info", binding.SolveInfo),
+                        ("mfpff_level_desc", binding.LevelDesc)):
+        cf = _c_struct_fields(cname)
+        pf = pyst._fields_
+        assert len(cf) == len(pf), cname
+        for c, (pname, ptype) in zip(cf, pf):
+            assert pname.rstrip("_") == c[1], (cname, pname, c)
+            if len(c) == 3:
+                assert ptype._type_ is ctype[c[0]] and ptype._length_ == binding.MAX_LEVELS, (cname, pname)
+            else:
+                assert ptype is ctype[c[0]], (cname, pname, c[0])
