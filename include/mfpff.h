@@ -206,6 +206,31 @@ mfpff_status mfpff_active_set(mfpff_ctx* ctx, const double* R, const double* phi
 mfpff_status mfpff_newton_step(mfpff_ctx* ctx, double* u, double* phi, const double* phi_old,
                                const double* phi_tilde, uint8_t* active, mfpff_solve_info* info);
 
+/* Result of mfpff_pdas_solve. */
+typedef struct {
+  int newton_steps;                 /* Newton steps taken (linear solves) */
+  int converged;                    /* 1: the active set repeated and ||P R|| <= tol ||P_0 R_0|| */
+  int gmres_iterations;             /* FGMRES iterations summed over the steps */
+  int n_active;                     /* size of the final active set */
+  double rel_residual;              /* ||P_k R_k|| / ||P_0 R_0|| at the last test */
+  double ms_total;                  /* wall time of the call, ms */
+} mfpff_pdas_info;
+
+/* Algorithm 1 (primal-dual active set) to its stopping test: repeat
+ *   R_k = R(u, phi; phi~), A_k from the active-set rule (as in mfpff_active_set),
+ *   stop if k > 0, A_k = A_{k-1} and ||P_k R_k||_2 <= tol ||P_0 R_0||_2
+ *   (P_k: free dofs, i.e. u-dofs off the Dirichlet faces and phi-dofs outside A_k;
+ *    the paper's eps_as is read relative to the first iterate),
+ *   otherwise one Newton step as mfpff_newton_step with A_k,
+ * for at most max_newton steps.  u (dim*n_nodes), phi (n_nodes) are device arrays updated in
+ * place; phi_old, phi_tilde (NULL: phi_old) are read; active (n_nodes bytes, device) receives the
+ * final active set.  Returns MFPFF_OK when the test is met, MFPFF_ERR_NOCONV after max_newton
+ * steps or when a linear solve reaches max_iter (the state is the last iterate; *info is filled
+ * either way), MFPFF_ERR_ARG for max_newton < 0, tol < 0 or a null pointer.  Synchronises. */
+mfpff_status mfpff_pdas_solve(mfpff_ctx* ctx, double* u, double* phi, const double* phi_old,
+                              const double* phi_tilde, uint8_t* active, int max_newton, double tol,
+                              mfpff_pdas_info* info);
+
 #ifdef __cplusplus
 }
 #endif

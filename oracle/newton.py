@@ -38,3 +38,34 @@ def newton_step(cfg, levels_nk, u, phi, phi_old, phi_t):
     u_new = u + dU[: d * nn].reshape(d, nn)
     phi_new = phi + dU[d * nn:]
     return dict(R=R, active=act, indicator=ind, b=b, dU=dU, u=u_new, phi=phi_new, info=info, hier=hier)
+
+
+def pdas_solve(cfg, levels_nk, u, phi, phi_old, phi_t, max_newton=20, tol=1e-8):
+    """Algorithm 1 to its stopping test: repeat (active set from the residual at U_k, Newton step
+    on the inactive set) until the active set equals the previous one and the residual on the
+    free dofs, ||P_k R_k||, is at most tol ||P_0 R_0|| (reading: the paper's eps_as taken relative
+    to the first iterate).  Returns the final state, the number of Newton steps taken, the norms
+    and the FGMRES iteration counts."""
+    mesh = Mesh(cfg.dim, cfg.N, cfg.k)
+    m = op.material_of(cfg)
+    prev = None
+    norms, iters = [], []
+    converged = False
+    r0 = None
+    for k in range(max_newton + 1):
+        R = op.residual(mesh, m, u, phi, phi_t)
+        act, _ = active_set(mesh, R, phi, phi_old, cfg.as_c)
+        pvec = op.free_vector(mesh, act, cfg.dirichlet)
+        rn = float(np.linalg.norm(pvec * R))
+        r0 = rn if r0 is None else r0
+        norms.append(rn)
+        if prev is not None and np.array_equal(act, prev) and rn <= tol * r0:
+            converged = True
+            break
+        if k == max_newton:
+            break
+        out = newton_step(cfg, levels_nk, u, phi, phi_old, phi_t)
+        u, phi = out["u"], out["phi"]
+        iters.append(out["info"]["iterations"])
+        prev = act
+    return dict(u=u, phi=phi, active=act, steps=len(iters), converged=converged, norms=norms, gmres_iterations=iters)

@@ -68,6 +68,20 @@ class SolveInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class PdasInfo(ctypes.Structure):
+    _fields_ = [
+        ("newton_steps", ctypes.c_int),
+        ("converged", ctypes.c_int),
+        ("gmres_iterations", ctypes.c_int),
+        ("n_active", ctypes.c_int),
+        ("rel_residual", ctypes.c_double),
+        ("ms_total", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class LevelDesc(ctypes.Structure):
     _fields_ = [
         ("N", ctypes.c_int),
@@ -86,7 +100,7 @@ EXPORTS = [
     "mfpff_set_point",
     "mfpff_apply_jacobian", "mfpff_diagonal", "mfpff_smooth", "mfpff_transfer", "mfpff_coarse_solve",
     "mfpff_vcycle", "mfpff_gmres_solve", "mfpff_residual", "mfpff_residual_param_vjp", "mfpff_active_set",
-    "mfpff_newton_step",
+    "mfpff_newton_step", "mfpff_pdas_solve",
 ]
 
 _lib = None
@@ -119,6 +133,7 @@ def load_library(path=LIB_PATH):
         "mfpff_residual_param_vjp": ([VP, P, P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "mfpff_active_set": ([VP, P, P, P, P], I),
         "mfpff_newton_step": ([VP, P, P, P, P, P, ctypes.POINTER(SolveInfo)], I),
+        "mfpff_pdas_solve": ([VP, P, P, P, P, P, I, D, ctypes.POINTER(PdasInfo)], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -316,6 +331,24 @@ class Context:
                                         _ptr(phi, torch.float64, nn, "phi"), _ptr(phi_old, torch.float64, nn, "phi_old"),
                                         _ptr(phi_tilde, torch.float64, nn, "phi_tilde", allow_none=True),
                                         _ptr(active, torch.uint8, nn, "active"), ctypes.byref(info))
+        if st != 5 or raise_on_noconv:
+            self._check(st)
+        self.levels = [self.level_info(l) for l in range(len(self.levels))]
+        return active, info.as_dict()
+
+    def pdas_solve(self, u, phi, phi_old, phi_tilde=None, active=None, max_newton=20, tol=1e-8,
+                   raise_on_noconv=True):
+        """Algorithm 1 to its stopping test (u, phi updated in place); returns the final active
+        set and the loop's counts."""
+        nn = self.n_nodes
+        if active is None:
+            active = torch.empty(nn, dtype=torch.uint8, device=u.device)
+        info = PdasInfo()
+        st = self.lib.mfpff_pdas_solve(self.h, _ptr(u, torch.float64, self.dim * nn, "u"),
+                                       _ptr(phi, torch.float64, nn, "phi"), _ptr(phi_old, torch.float64, nn, "phi_old"),
+                                       _ptr(phi_tilde, torch.float64, nn, "phi_tilde", allow_none=True),
+                                       _ptr(active, torch.uint8, nn, "active"), int(max_newton), float(tol),
+                                       ctypes.byref(info))
         if st != 5 or raise_on_noconv:
             self._check(st)
         self.levels = [self.level_info(l) for l in range(len(self.levels))]

@@ -8,6 +8,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -139,6 +140,8 @@ struct mfpff_ctx {
   double* b = nullptr;
   double* dU = nullptr;
   double* pvjp_part = nullptr;
+  uint8_t* act_prev = nullptr;   // active-set loop: the previous step's active set
+  double* pdas_part = nullptr;   // active-set loop: stopping-test partial sums
   double* pvjp_out = nullptr;
   bool linearized = false;  // full linearisation (smoothers, coarse solve)
   bool has_point = false;   // fields and masks injected (products allowed)
@@ -1134,7 +1137,7 @@ void mfpff_destroy(mfpff_ctx* c) {
   }
   void* ps[] = {c->elem, c->finite_flag, c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
                 c->WpT, c->Gpu, c->cs_in, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lst, c->part, c->V,
-                c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out};
+                c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out, c->act_prev, c->pdas_part};
   for (void* p : ps) F(p);
   for (int i = 0; i < 5; ++i) F(c->s64[i]);
   if (c->hhost) (void)hipHostFree(c->hhost);
@@ -1358,6 +1361,68 @@ mfpff_status mfpff_active_set(mfpff_ctx* c, const double* R, const double* phi, 
   });
 }
 
+}  // extern "C"
+
+namespace {
+// residual at (u, phi; phi~) into c->R and the active set of Algorithm 1 from it
+static void residual_and_active(mfpff_ctx* c, const double* u, const double* phi, const double* phi_old, const double* pt,
+                                uint8_t* active) {
+  Level& F = c->lv[c->L];
+  k_fill<double>(c->R, 0.0, F.n, c->s);
+  CellArgs<double> a = cell_args<double>(c, F, F.lin, nullptr, c->R, 1.0);
+  a.u = u;
+  a.phi = phi;
+  a.phit = pt;
+  a.mask = nullptr;
+  HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
+  k_active_set(active, c->R, phi, phi_old, c->ml, F.nn, c->dim, c->prob.as_c, c->s);
+  LAUNCHCHK();
+}
+
+// linearise at (u, phi, active), solve G^ dU = -P R (R in c->R), update u and phi; fills
+// iterations, residual and times of *loc
+static mfpff_status linearise_solve_update(mfpff_ctx* c, double* u, double* phi, const double* phi_old, const double* pt,
+                                           const uint8_t* active, hipEvent_t e0, mfpff_solve_info* loc) {
+  Level& F = c->lv[c->L];
+  const int d = c->dim;
+  hipEvent_t e1 = nullptr, e2 = nullptr;
+  HIPCHK(hipEventCreate(&e1));
+  HIPCHK(hipEventCreate(&e2));
+  c->linearized = false;
+  set_linearization(c, u, phi, phi_old, active, pt);
+  HIPCHK(hipEventRecord(e1, c->s));
+  // b = -P R
+  k_copy<double>(c->b, c->R, F.n, c->s);
+  k_mask_vec(c->b, F.mask, F.nn, d, -1.0, c->s);
+  LAUNCHCHK();
+  mfpff_status st = gmres(c, c->b, c->dU, loc);
+  k_axpy<double>(u, 1.0, c->dU, (long long)d * F.nn, c->s);
+  k_axpy<double>(phi, 1.0, c->dU + (size_t)d * F.nn, F.nn, c->s);
+  LAUNCHCHK();
+  HIPCHK(hipEventRecord(e2, c->s));
+  HIPCHK(hipEventSynchronize(e2));
+  float ms1 = 0, ms2 = 0;
+  HIPCHK(hipEventElapsedTime(&ms1, e0, e1));
+  HIPCHK(hipEventElapsedTime(&ms2, e1, e2));
+  (void)hipEventDestroy(e1);
+  (void)hipEventDestroy(e2);
+  loc->ms_setup = ms1;
+  loc->ms_solve = ms2;
+  return st;
+}
+
+static int count_active(mfpff_ctx* c) {
+  Level& F = c->lv[c->L];
+  std::vector<uint8_t> mh(F.nn);
+  HIPCHK(hipMemcpy(mh.data(), F.mask, F.nn, hipMemcpyDeviceToHost));
+  int na = 0;
+  for (auto v : mh) na += (v & kMaskPhi) ? 1 : 0;
+  return na;
+}
+}  // namespace
+
+extern "C" {
+
 mfpff_status mfpff_newton_step(mfpff_ctx* c, double* u, double* phi, const double* phi_old, const double* phi_tilde,
                                uint8_t* active, mfpff_solve_info* info) {
   return run(c, [&]() {
@@ -1366,52 +1431,85 @@ mfpff_status mfpff_newton_step(mfpff_ctx* c, double* u, double* phi, const doubl
     require_ptr(phi_old, "phi_old");
     require_ptr(active, "active");
     const double* pt = phi_tilde ? phi_tilde : phi_old;
-    Level& F = c->lv[c->L];
-    const int d = c->dim;
-    hipEvent_t e0, e1, e2;
+    hipEvent_t e0 = nullptr;
     HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventCreate(&e2));
     HIPCHK(hipEventRecord(e0, c->s));
-    // residual and active set
-    k_fill<double>(c->R, 0.0, F.n, c->s);
-    CellArgs<double> a = cell_args<double>(c, F, F.lin, nullptr, c->R, 1.0);
-    a.u = u;
-    a.phi = phi;
-    a.phit = pt;
-    a.mask = nullptr;
-    HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
-    k_active_set(active, c->R, phi, phi_old, c->ml, F.nn, d, c->prob.as_c, c->s);
-    LAUNCHCHK();
-    c->linearized = false;
-    set_linearization(c, u, phi, phi_old, active, pt);
-    HIPCHK(hipEventRecord(e1, c->s));
-    // b = -P R
-    k_copy<double>(c->b, c->R, F.n, c->s);
-    k_mask_vec(c->b, F.mask, F.nn, d, -1.0, c->s);
-    LAUNCHCHK();
+    residual_and_active(c, u, phi, phi_old, pt, active);
     mfpff_solve_info loc{};
-    mfpff_status st = gmres(c, c->b, c->dU, &loc);
-    k_axpy<double>(u, 1.0, c->dU, (long long)d * F.nn, c->s);
-    k_axpy<double>(phi, 1.0, c->dU + (size_t)d * F.nn, F.nn, c->s);
-    LAUNCHCHK();
-    HIPCHK(hipEventRecord(e2, c->s));
-    HIPCHK(hipEventSynchronize(e2));
-    float ms1 = 0, ms2 = 0;
-    HIPCHK(hipEventElapsedTime(&ms1, e0, e1));
-    HIPCHK(hipEventElapsedTime(&ms2, e1, e2));
+    const mfpff_status st = linearise_solve_update(c, u, phi, phi_old, pt, active, e0, &loc);
     (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    (void)hipEventDestroy(e2);
-    loc.ms_setup = ms1;
-    loc.ms_solve = ms2;
-    std::vector<uint8_t> mh(F.nn);
-    HIPCHK(hipMemcpy(mh.data(), F.mask, F.nn, hipMemcpyDeviceToHost));
-    int na = 0;
-    for (auto v : mh) na += (v & kMaskPhi) ? 1 : 0;
-    loc.n_active = na;
+    loc.n_active = count_active(c);
     if (info) *info = loc;
     if (st == MFPFF_ERR_NOCONV) c->err = "GMRES reached max_iter";
+    return st;
+  });
+}
+
+mfpff_status mfpff_pdas_solve(mfpff_ctx* c, double* u, double* phi, const double* phi_old, const double* phi_tilde,
+                              uint8_t* active, int max_newton, double tol, mfpff_pdas_info* info) {
+  return run(c, [&]() {
+    require_ptr(u, "u");
+    require_ptr(phi, "phi");
+    require_ptr(phi_old, "phi_old");
+    require_ptr(active, "active");
+    if (max_newton < 0 || !(tol >= 0.0)) throw StatusError{MFPFF_ERR_ARG, "max_newton must be >= 0 and tol >= 0"};
+    const double* pt = phi_tilde ? phi_tilde : phi_old;
+    Level& F = c->lv[c->L];
+    if (!c->act_prev) c->act_prev = dalloc<uint8_t>(F.nn);
+    if (!c->pdas_part) c->pdas_part = dalloc<double>((size_t)2 * pdas_check_blocks(F.nn));
+    const int nb = pdas_check_blocks(F.nn);
+    std::vector<double> ph((size_t)2 * nb);
+    mfpff_pdas_info out{};
+    mfpff_status st = MFPFF_ERR_NOCONV;
+    double r0 = -1.0;
+    const auto t0 = std::chrono::steady_clock::now();
+    for (int k = 0; k <= max_newton; ++k) {
+      hipEvent_t e0 = nullptr;
+      HIPCHK(hipEventCreate(&e0));
+      HIPCHK(hipEventRecord(e0, c->s));
+      residual_and_active(c, u, phi, phi_old, pt, active);
+      // stopping test: the active set repeats and ||P_k R_k|| <= tol ||P_0 R_0||
+      k_pdas_check(c->pdas_part, c->R, active, c->act_prev, F.g, c->prob.dirichlet, c->s);
+      LAUNCHCHK();
+      HIPCHK(hipMemcpyAsync(ph.data(), c->pdas_part, ph.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
+      HIPCHK(hipStreamSynchronize(c->s));
+      double ss = 0, nd = 0;
+      for (int b = 0; b < nb; ++b) {
+        ss += ph[2 * b];
+        nd += ph[2 * b + 1];
+      }
+      const double rn = std::sqrt(ss);
+      if (r0 < 0) r0 = rn;
+      out.rel_residual = r0 > 0 ? rn / r0 : 0.0;
+      if (k > 0 && nd == 0.0 && rn <= tol * r0) {
+        (void)hipEventDestroy(e0);
+        st = MFPFF_OK;
+        out.converged = 1;
+        break;
+      }
+      if (k == max_newton) {
+        (void)hipEventDestroy(e0);
+        break;
+      }
+      mfpff_solve_info loc{};
+      const mfpff_status sst = linearise_solve_update(c, u, phi, phi_old, pt, active, e0, &loc);
+      (void)hipEventDestroy(e0);
+      out.newton_steps = k + 1;
+      out.gmres_iterations += loc.iterations;
+      HIPCHK(hipMemcpyAsync(c->act_prev, active, F.nn, hipMemcpyDeviceToDevice, c->s));
+      if (sst != MFPFF_OK) {
+        st = sst;
+        c->err = "GMRES reached max_iter inside the active-set loop";
+        break;
+      }
+    }
+    HIPCHK(hipStreamSynchronize(c->s));
+    std::vector<uint8_t> ah(F.nn);
+    HIPCHK(hipMemcpy(ah.data(), active, F.nn, hipMemcpyDeviceToHost));
+    for (auto v : ah) out.n_active += v ? 1 : 0;
+    out.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = out;
+    if (st == MFPFF_ERR_NOCONV && !out.converged && c->err.empty()) c->err = "active-set loop reached max_newton";
     return st;
   });
 }

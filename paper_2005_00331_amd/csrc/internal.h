@@ -180,6 +180,10 @@ void k_splitmix_start(double* v, const uint8_t* mask, long long nn, int dim, uns
 
 // Reductions: partial sums per block, then a one-block finish.
 int dot_blocks(long long n);
+// stopping test of Algorithm 1: per-workgroup (sum of R^2 on the free dofs, changed nodes of act vs prev)
+int pdas_check_blocks(long long nn);
+void k_pdas_check(double* part, const double* R, const uint8_t* act, const uint8_t* prev, const Geom& g, int dirichlet,
+                  hipStream_t s);
 void k_multidot_partials(double* part, const double* V, long long ldv, int nvec, const double* w, long long n, hipStream_t s);
 void k_multidot_finish(double* out, const double* part, int nblocks, int nvec, hipStream_t s);
 void k_seg_dot_partials(double* part, const double* a, const double* b, long long nu, long long n, hipStream_t s);

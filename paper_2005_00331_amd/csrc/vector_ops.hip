@@ -230,6 +230,64 @@ void k_active_set(uint8_t* act, const double* R, const double* phi, const double
   hipLaunchKernelGGL(active_set_kernel, dim3(grid_for(nn)), dim3(kThreads), 0, s, act, R, phi, phi_old, ml, nn, dim, c);
 }
 
+// Stopping test of Algorithm 1, one pass: per workgroup, the sum of R_i^2 over the free dofs
+// (u-dofs off the Dirichlet faces, phi-dofs outside the active set act) and the number of
+// nodes where act differs from prev.  part: 2 doubles per workgroup (sum, count).
+__global__ void pdas_check_kernel(double* part, const double* R, const uint8_t* act, const uint8_t* prev, Geom g,
+                                  int dirichlet) {
+  __shared__ double sh[2][kThreads / 64];
+  const long long nn = g.n_nodes;
+  const int dim = g.dim;
+  const unsigned M = (unsigned)g.M;
+  double ss = 0, nd = 0;
+  GSTRIDE(i, nn) {
+    // index of the node along the last axis (the Dirichlet faces are normal to it)
+    const unsigned q = (unsigned)i / M;
+    const unsigned last = dim == 2 ? q : q / M;
+    const bool dir = dirichlet && (last == 0 || last == M - 1);
+    const bool a = act[i] != 0;
+    if (!dir) {
+      for (int cc = 0; cc < dim; ++cc) {
+        const double r = R[cc * nn + i];
+        ss += r * r;
+      }
+    }
+    if (!a) {
+      const double r = R[dim * nn + i];
+      ss += r * r;
+    }
+    nd += (prev[i] != 0) != a ? 1.0 : 0.0;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    ss += __shfl_down(ss, off, 64);
+    nd += __shfl_down(nd, off, 64);
+  }
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) {
+    sh[0][wid] = ss;
+    sh[1][wid] = nd;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0, b = 0;
+    for (int w = 0; w < kThreads / 64; ++w) {
+      a += sh[0][w];
+      b += sh[1][w];
+    }
+    part[2 * blockIdx.x] = a;
+    part[2 * blockIdx.x + 1] = b;
+  }
+}
+int pdas_check_blocks(long long nn) {
+  const long long b = (nn + kThreads - 1) / kThreads;
+  return (int)(b < 256 ? (b < 1 ? 1 : b) : 256);
+}
+void k_pdas_check(double* part, const double* R, const uint8_t* act, const uint8_t* prev, const Geom& g, int dirichlet,
+                  hipStream_t s) {
+  hipLaunchKernelGGL(pdas_check_kernel, dim3((unsigned)pdas_check_blocks(g.n_nodes)), dim3(kThreads), 0, s, part, R, act,
+                     prev, g, dirichlet);
+}
+
 // SplitMix64 (Steele, Lea, Flood 2014): output n of stream st with seed s is
 // mix(s + (n + 1 + st * 2^40) * 0x9E3779B97F4A7C15), mapped to [-1, 1).
 __device__ __forceinline__ double splitmix_pm1(unsigned long long seed, unsigned long long st, unsigned long long n) {

@@ -96,3 +96,23 @@ def test_newton_step_small():
     A = out["hier"].levels[-1].A
     assert np.linalg.norm(out["b"] - A @ dU) <= 1.001 * cfg.rtol * np.linalg.norm(out["b"])
     assert np.linalg.norm(dU - out["dU"]) <= 1e-5 * np.linalg.norm(out["dU"])
+
+
+@pytest.mark.parametrize("name,kw", [("C1", {}), ("C2", dict(N=16, n_h_levels=3)),
+                                     ("C2", dict(N=16, n_h_levels=3, split="miehe"))])
+def test_active_set_loop_matches_oracle(name, kw):
+    from paper_2005_00331_amd import Context, problem_from
+    cfg = CONFIGS[name].with_(**kw)
+    levels = level_list(cfg)
+    inp = make_inputs(cfg)
+    ref = newton.pdas_solve(cfg, levels, inp["u"], inp["phi"], inp["phi_old"], inp["phi_tilde"], max_newton=20, tol=1e-8)
+    ctx = Context(problem_from(cfg, levels))
+    u, phi = dev(inp["u"]), dev(inp["phi"])
+    say(name, kw, "active-set loop")
+    act, info = ctx.pdas_solve(u, phi, dev(inp["phi_old"]), dev(inp["phi_tilde"]), max_newton=20, tol=1e-8)
+    say(name, "gpu steps", info["newton_steps"], "oracle steps", ref["steps"], "rel residual", info["rel_residual"])
+    assert info["converged"] == 1 and ref["converged"]
+    assert info["newton_steps"] == ref["steps"]
+    assert np.array_equal(host(act), ref["active"])
+    assert info["n_active"] == int(ref["active"].sum())
+    assert rel_err(host(u).ravel(), ref["u"].ravel()) <= 1e-6 and rel_err(host(phi), ref["phi"]) <= 1e-6

@@ -200,3 +200,24 @@ def test_newton_step_solves_linearised_system():
     # constrained dofs do not move
     p = out["hier"].levels[-1].pvec
     assert np.all(out["dU"][p == 0] == 0)
+
+
+@pytest.mark.parametrize("name,kw", [("C1", {}), ("C2", dict(N=16, n_h_levels=3))])
+def test_active_set_loop_stops_at_a_fixed_point_with_a_superlinear_tail(name, kw):
+    # Algorithm 1 to its stopping test: the final active set is a fixed point of the rule, the
+    # free residual is below tol times the first one, and the Newton tail contracts
+    # superlinearly (the Jacobian is the derivative of the residual).
+    cfg = CONFIGS[name].with_(**kw)
+    inp = make_inputs(cfg)
+    out = newton.pdas_solve(cfg, level_list(cfg), inp["u"], inp["phi"], inp["phi_old"], inp["phi_tilde"],
+                            max_newton=20, tol=1e-8)
+    assert out["converged"] and 1 <= out["steps"] <= 20
+    mesh = fe.Mesh(cfg.dim, cfg.N, cfg.k)
+    m = op.material_of(cfg)
+    R = op.residual(mesh, m, out["u"], out["phi"], inp["phi_tilde"])
+    act, _ = newton.active_set(mesh, R, out["phi"], inp["phi_old"], cfg.as_c)
+    assert np.array_equal(act, out["active"])
+    pvec = op.free_vector(mesh, act, cfg.dirichlet)
+    assert np.linalg.norm(pvec * R) <= 1e-8 * out["norms"][0]
+    r = out["norms"]
+    assert r[-1] / r[-2] <= 1e-3 and r[-1] / r[-2] < r[-2] / r[-3]
