@@ -247,6 +247,17 @@ def main():
         print(f"[bench] mixed newton step {msec * 1e3:.2f} ms", file=sys.stderr, flush=True)
         mctx.close()
     if not args.no_mixed:
+        # Algorithm 1 to its stopping test from the same state (one load step)
+        import torch
+        pu, pphi = state["u"].clone(), state["phi"].clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, pinfo = ctx.pdas_solve(pu, pphi, state["phi_old"], state["phi_tilde"], max_newton=20, tol=1e-8,
+                                  raise_on_noconv=False)
+        torch.cuda.synchronize()
+        pinfo["ms_wall"] = (time.perf_counter() - t0) * 1e3
+        detail["active_set_loop"] = pinfo
+        print(f"[bench] active-set loop: {pinfo}", file=sys.stderr, flush=True)
         # the same Newton step with the spectral (Miehe) split of Section 2.1
         sctx, _, sstate = build_context(cfg.with_(split="miehe"))
         ssec, sinfos = time_newton(sctx, sstate, 2, 1)
