@@ -162,6 +162,69 @@ def time_products_3d(cfg):
     return res
 
 
+def spmv_study():
+    """Section 6's comparison on this GPU: per degree, the matrix-free product (unconstrained,
+    cached coefficients where the level has them) against the sparse product of the assembled
+    Jacobian (CSR with 32-bit indices, rocSPARSE's generic SpMV, the fastest of its adaptive,
+    row-split and LRB algorithms), at about the
+    same number of dofs; memory per dof of each.  Prints one JSON line per case."""
+    import torch
+    from paper_2005_00331_amd import OP_G
+    from paper_2005_00331_amd.assembly import RocsparseSpmv, assemble_csr
+    from synth import CONFIGS
+    cases = [(2, 512, 1), (2, 256, 2), (2, 170, 3), (2, 128, 4), (3, 64, 1), (3, 32, 2), (3, 21, 3), (3, 16, 4)]
+    for dim, N, k in cases:
+        base = CONFIGS["C2"] if dim == 2 else CONFIGS["C3"]
+        cfg = base.with_(N=N, k=k, n_h_levels=1, p_coarse=(), dirichlet=False, vcycle_prec="f64")
+        ctx, _, st = build_context(cfg)
+        zeros = torch.zeros(ctx.n_nodes, dtype=torch.uint8, device="cuda")
+        ctx.set_point(st["u"], st["phi"], st["phi_old"], zeros, st["phi_tilde"])
+        t_mf = time_apply(ctx)
+        em = ctx.element_matrices(-1)
+        A = assemble_csr(em, dim, N, k)
+        del em
+        torch.cuda.empty_cache()
+        x = torch.randn(ctx.n_dofs, dtype=torch.float64, device="cuda")
+        ymf = ctx.apply_jacobian(-1, x, op=OP_G)
+        t_sp, alg_best, err = None, None, None
+        for alg in ("adaptive", "rowsplit", "lrb"):
+            sp = RocsparseSpmv(A, alg)
+            sp.x.copy_(x)
+            y = sp.mv()
+            e = float((y - ymf).norm() / ymf.norm())
+            for _ in range(3):
+                sp.mv()
+            s = torch.cuda.current_stream()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            for _ in range(20):
+                sp.mv()
+            e1.record(s)
+            e1.synchronize()
+            t = e0.elapsed_time(e1) / 1e3 / 20
+            sp.close()
+            del sp
+            if t_sp is None or t < t_sp:
+                t_sp, alg_best, err = t, alg, e
+        nnz = A.values().numel()
+        n = ctx.n_dofs
+        csr_bytes = nnz * 12 + (n + 1) * 4
+        qd = 0
+        if (dim == 2 and k <= 2) or dim == 3:
+            P = (k + 1) ** dim
+            ncoef = 5 if dim == 2 else 8
+            qd = N ** dim * P * ncoef * 8 * (64 / 49 if dim == 2 else 1)
+        out = {"dim": dim, "N": N, "k": k, "n_dofs": n, "nnz": nnz, "nnz_per_row": nnz / n,
+               "mf_us": t_mf * 1e6, "spmv_us": t_sp * 1e6, "spmv_over_mf": t_sp / t_mf,
+               "csr_bytes_per_dof": csr_bytes / n, "spmv_GBs": (csr_bytes + 16 * n) / t_sp / 1e9,
+               "mf_state_bytes_per_dof": (algorithmic_bytes_per_apply(dim, ctx.n_nodes, 8) - 16 * n) / n,
+               "mf_cache_bytes_per_dof": qd / n, "csr_vs_mf_rel_diff": err, "spmv_alg": alg_best}
+        print(json.dumps(out), flush=True)
+        del A, x, y, ymf
+        ctx.close()
+        torch.cuda.empty_cache()
+
+
 def cpu_baseline(cfg_name):
     """Oracle Newton step on a bounded sample of the same workload family."""
     import numpy as np
@@ -195,6 +258,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison step")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D runs (C3 solves, C4 products)")
+    ap.add_argument("--spmv", action="store_true",
+                    help="instead: matrix-free product against the assembled CSR product (rocSPARSE) at p = 1..4")
     ap.add_argument("--apply-only", action="store_true",
                     help="only time the finest-level cell kernel (for kernel-trace and counter runs)")
     args = ap.parse_args()
@@ -205,6 +270,9 @@ def main():
     import torch
     from synth import CONFIGS
     torch.cuda.set_device(0)
+    if args.spmv:
+        spmv_study()
+        return
     cfg = CONFIGS[args.workload]
     print(f"[bench] workload {cfg.name}: {cfg.dim}D N={cfg.N} Q{cfg.k}, {cfg.n_dofs} dofs", file=sys.stderr, flush=True)
     ctx, levels, state = build_context(cfg)

@@ -200,6 +200,17 @@ mfpff_status mfpff_residual_param_vjp(mfpff_ctx* ctx, const double* u, const dou
 mfpff_status mfpff_active_set(mfpff_ctx* ctx, const double* R, const double* phi,
                               const double* phi_old, uint8_t* active);
 
+/* Unconstrained element matrices of eq. (G) on one level at the current point (after
+ * mfpff_set_point or mfpff_set_linearization), FP64, for assembling the sparse Jacobian (the
+ * matrix-based product that Section 6 compares the matrix-free one against).  em (device,
+ * caller-owned) receives n_cells * nl * nl values, nl = (dim + 1) (k + 1)^dim, laid out
+ * [cell][row][column]; cells in lexicographic order (x fastest), local rows and columns
+ * (component, local node) with the local node lexicographic in the cell (x fastest), so that
+ * local node (i0, i1, i2) of cell (cx, cy, cz) is global node
+ * (k cx + i0) + M (k cy + i1) + M^2 (k cz + i2), M = k N + 1, and dof = component * n_nodes + node.
+ * MFPFF_ERR_STATE before a point is set. */
+mfpff_status mfpff_element_matrices(mfpff_ctx* ctx, int level, double* em);
+
 /* One semi-smooth Newton step of Algorithm 1 on the finest level: residual,
  * active set (written to `active`), linearisation, b = -P R, GMRES solve,
  * u += du, phi += dphi (u, phi updated in place).  Synchronises. */

@@ -100,7 +100,7 @@ EXPORTS = [
     "mfpff_set_point",
     "mfpff_apply_jacobian", "mfpff_diagonal", "mfpff_smooth", "mfpff_transfer", "mfpff_coarse_solve",
     "mfpff_vcycle", "mfpff_gmres_solve", "mfpff_residual", "mfpff_residual_param_vjp", "mfpff_active_set",
-    "mfpff_newton_step", "mfpff_pdas_solve",
+    "mfpff_newton_step", "mfpff_pdas_solve", "mfpff_element_matrices",
 ]
 
 _lib = None
@@ -134,6 +134,7 @@ def load_library(path=LIB_PATH):
         "mfpff_active_set": ([VP, P, P, P, P], I),
         "mfpff_newton_step": ([VP, P, P, P, P, P, ctypes.POINTER(SolveInfo)], I),
         "mfpff_pdas_solve": ([VP, P, P, P, P, P, I, D, ctypes.POINTER(PdasInfo)], I),
+        "mfpff_element_matrices": ([VP, I, P], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -335,6 +336,16 @@ class Context:
             self._check(st)
         self.levels = [self.level_info(l) for l in range(len(self.levels))]
         return active, info.as_dict()
+
+    def element_matrices(self, level=-1):
+        """Unconstrained element matrices of a level, (n_cells, nl, nl) FP64 on the device."""
+        lv = self._lvl(level)
+        nl = (self.dim + 1) * (lv.k + 1) ** self.dim
+        nc = lv.N ** self.dim
+        em = torch.empty((nc, nl, nl), dtype=torch.float64, device="cuda")
+        self._check(self.lib.mfpff_element_matrices(self.h, level % len(self.levels),
+                                                    _ptr(em.view(-1), torch.float64, nc * nl * nl, "em")))
+        return em
 
     def pdas_solve(self, u, phi, phi_old, phi_tilde=None, active=None, max_newton=20, tol=1e-8,
                    raise_on_noconv=True):

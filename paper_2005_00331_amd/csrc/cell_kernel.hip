@@ -180,7 +180,12 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
     // ---------------- scatter
     if (valid) {
       const int o = c * P + p;
-      if (MODE == MODE_ELEM) {
+      if (MODE == MODE_ELEM && a.elem_mat) {
+        // column jcomp*P + jp of the cell's element matrix, rows (component, local node)
+        double* em = a.elem_mat + ((long long)cell * NCOL + p) * NCOL + jcomp * P + jp;
+#pragma unroll
+        for (int cc = 0; cc <= DIM; ++cc) em[(long long)cc * P * NCOL] = (double)R[cc * NPTS + o];
+      } else if (MODE == MODE_ELEM) {
         const long long jnode = node_of<DIM, K>(g, cell, jp);
         const uint8_t jm = a.mask ? a.mask[jnode] : (uint8_t)0;
         const bool colfixed = (jcomp < DIM) ? (jm & kMaskU) : (jm & kMaskPhi);

@@ -1233,6 +1233,21 @@ mfpff_status mfpff_diagonal(mfpff_ctx* c, int level, double* diag) {
   });
 }
 
+mfpff_status mfpff_element_matrices(mfpff_ctx* c, int level, double* em) {
+  return run(c, [&]() {
+    require_point(c);
+    require_level(c, level);
+    require_ptr(em, "em");
+    Level& L = c->lv[level];
+    CellArgs<double> a = cell_args<double>(c, L, L.lin, nullptr, nullptr, 1.0);
+    a.mask = nullptr;  // unconstrained
+    a.qd = nullptr;
+    a.elem_mat = em;
+    HIPCHK(launch_cell<double>(MODE_ELEM, a, c->tab64[L.g.k], c->s));
+    return MFPFF_OK;
+  });
+}
+
 mfpff_status mfpff_smooth(mfpff_ctx* c, int level, const double* r, double* z) {
   return run(c, [&]() {
     require_state(c);

@@ -100,6 +100,7 @@ struct CellArgs {
   T scale;             // contributions multiply by this (+1 apply, -1 residual form)
   double* partials;    // PVJP: 2 doubles per block
   double* dense;       // ELEM: row-major (d+1)*n_nodes square matrix
+  double* elem_mat;    // ELEM: element matrices [cell][row][column] instead of the dense scatter
   long long ld;        // ELEM: leading dimension
   const T* qd;         // 2D Q1/Q2: cached tangent coefficients (null: computed from u, phi, phi~)
   T* qd_out;           // MODE_QDATA: where the coefficients go

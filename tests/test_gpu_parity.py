@@ -154,3 +154,31 @@ def test_products_and_vcycle_are_bitwise_reproducible(name):
         b = host(ctx.apply_jacobian(-1, x, op=opn))
         assert np.array_equal(a, b), opn
     assert np.array_equal(host(ctx.vcycle(x)), host(ctx.vcycle(x)))
+
+
+@pytest.mark.parametrize("dim,N,k,split", [(2, 4, 1, "amor"), (2, 3, 2, "amor"), (2, 2, 4, "amor"),
+                                           (3, 2, 2, "amor"), (3, 2, 4, "amor"), (2, 3, 2, "miehe"),
+                                           (3, 2, 2, "miehe")])
+def test_element_matrices_and_sparse_product(dim, N, k, split):
+    # the unconstrained element matrices against the oracle's assembled Jacobian, and the
+    # assembled CSR product against the matrix-free product with nothing constrained
+    import torch
+    from oracle import fe
+    from oracle import operator as op
+    from paper_2005_00331_amd import Context, OP_G, problem_from
+    from paper_2005_00331_amd.assembly import assemble_csr
+    from synth import CONFIGS, make_inputs
+    cfg = (CONFIGS["C3"] if dim == 3 else CONFIGS["C2"]).with_(dim=dim, N=N, k=k, n_h_levels=1, p_coarse=(),
+                                                               split=split, dirichlet=False, vcycle_prec="f64")
+    inp = make_inputs(cfg)
+    mesh = fe.Mesh(dim, N, k)
+    ctx = Context(problem_from(cfg, [(N, k)]))
+    zeros = np.zeros(mesh.n_nodes, np.uint8)
+    ctx.set_point(dev(inp["u"]), dev(inp["phi"]), dev(inp["phi_old"]), dev(zeros), dev(inp["phi_tilde"]))
+    say(dim, N, k, split, "element matrices")
+    A = assemble_csr(ctx.element_matrices(-1), dim, N, k)
+    G = op.assemble_jacobian(mesh, op.material_of(cfg), inp["u"], inp["phi"], inp["phi_tilde"]).toarray()
+    assert np.abs(A.to_dense().cpu().numpy() - G).max() <= 1e-12 * np.abs(G).max()
+    x = dev(np.random.default_rng(3).standard_normal(mesh.n_dofs))
+    y = host(torch.mv(A, x))
+    assert rel_err(y, host(ctx.apply_jacobian(-1, x, op=OP_G))) <= 1e-12
