@@ -686,6 +686,17 @@ void coarse_join(mfpff_ctx* c) {
   for (int b = 0; b < 2; ++b) HIPCHK(hipStreamWaitEvent(c->s, c->ev_join[b], 0));
 }
 
+// timing event owned for one scope (destroyed on every exit path, exceptions included)
+struct ScopedEvent {
+  hipEvent_t e = nullptr;
+  ScopedEvent() { HIPCHK(hipEventCreate(&e)); }
+  ~ScopedEvent() {
+    if (e) (void)hipEventDestroy(e);
+  }
+  ScopedEvent(const ScopedEvent&) = delete;
+  ScopedEvent& operator=(const ScopedEvent&) = delete;
+};
+
 void require_state(mfpff_ctx* c) {
   if (!c->linearized) throw StatusError{MFPFF_ERR_STATE, "set_linearization has not been called"};
 }
@@ -1299,18 +1310,14 @@ mfpff_status mfpff_gmres_solve(mfpff_ctx* c, const double* b, double* x, mfpff_s
     require_state(c);
     require_ptr(b, "b");
     require_ptr(x, "x");
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
-    HIPCHK(hipEventRecord(e0, c->s));
+    ScopedEvent e0, e1;
+    HIPCHK(hipEventRecord(e0.e, c->s));
     mfpff_solve_info loc{};
     mfpff_status st = gmres(c, b, x, &loc);
-    HIPCHK(hipEventRecord(e1, c->s));
-    HIPCHK(hipEventSynchronize(e1));
+    HIPCHK(hipEventRecord(e1.e, c->s));
+    HIPCHK(hipEventSynchronize(e1.e));
     float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    HIPCHK(hipEventElapsedTime(&ms, e0.e, e1.e));
     loc.ms_solve = ms;
     if (info) *info = loc;
     if (st == MFPFF_ERR_NOCONV) c->err = "GMRES reached max_iter";
@@ -1400,12 +1407,10 @@ static mfpff_status linearise_solve_update(mfpff_ctx* c, double* u, double* phi,
                                            const uint8_t* active, hipEvent_t e0, mfpff_solve_info* loc) {
   Level& F = c->lv[c->L];
   const int d = c->dim;
-  hipEvent_t e1 = nullptr, e2 = nullptr;
-  HIPCHK(hipEventCreate(&e1));
-  HIPCHK(hipEventCreate(&e2));
+  ScopedEvent e1, e2;
   c->linearized = false;
   set_linearization(c, u, phi, phi_old, active, pt);
-  HIPCHK(hipEventRecord(e1, c->s));
+  HIPCHK(hipEventRecord(e1.e, c->s));
   // b = -P R
   k_copy<double>(c->b, c->R, F.n, c->s);
   k_mask_vec(c->b, F.mask, F.nn, d, -1.0, c->s);
@@ -1414,13 +1419,11 @@ static mfpff_status linearise_solve_update(mfpff_ctx* c, double* u, double* phi,
   k_axpy<double>(u, 1.0, c->dU, (long long)d * F.nn, c->s);
   k_axpy<double>(phi, 1.0, c->dU + (size_t)d * F.nn, F.nn, c->s);
   LAUNCHCHK();
-  HIPCHK(hipEventRecord(e2, c->s));
-  HIPCHK(hipEventSynchronize(e2));
+  HIPCHK(hipEventRecord(e2.e, c->s));
+  HIPCHK(hipEventSynchronize(e2.e));
   float ms1 = 0, ms2 = 0;
-  HIPCHK(hipEventElapsedTime(&ms1, e0, e1));
-  HIPCHK(hipEventElapsedTime(&ms2, e1, e2));
-  (void)hipEventDestroy(e1);
-  (void)hipEventDestroy(e2);
+  HIPCHK(hipEventElapsedTime(&ms1, e0, e1.e));
+  HIPCHK(hipEventElapsedTime(&ms2, e1.e, e2.e));
   loc->ms_setup = ms1;
   loc->ms_solve = ms2;
   return st;
@@ -1446,13 +1449,11 @@ mfpff_status mfpff_newton_step(mfpff_ctx* c, double* u, double* phi, const doubl
     require_ptr(phi_old, "phi_old");
     require_ptr(active, "active");
     const double* pt = phi_tilde ? phi_tilde : phi_old;
-    hipEvent_t e0 = nullptr;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventRecord(e0, c->s));
+    ScopedEvent e0;
+    HIPCHK(hipEventRecord(e0.e, c->s));
     residual_and_active(c, u, phi, phi_old, pt, active);
     mfpff_solve_info loc{};
-    const mfpff_status st = linearise_solve_update(c, u, phi, phi_old, pt, active, e0, &loc);
-    (void)hipEventDestroy(e0);
+    const mfpff_status st = linearise_solve_update(c, u, phi, phi_old, pt, active, e0.e, &loc);
     loc.n_active = count_active(c);
     if (info) *info = loc;
     if (st == MFPFF_ERR_NOCONV) c->err = "GMRES reached max_iter";
@@ -1479,9 +1480,8 @@ mfpff_status mfpff_pdas_solve(mfpff_ctx* c, double* u, double* phi, const double
     double r0 = -1.0;
     const auto t0 = std::chrono::steady_clock::now();
     for (int k = 0; k <= max_newton; ++k) {
-      hipEvent_t e0 = nullptr;
-      HIPCHK(hipEventCreate(&e0));
-      HIPCHK(hipEventRecord(e0, c->s));
+      ScopedEvent e0;
+      HIPCHK(hipEventRecord(e0.e, c->s));
       residual_and_active(c, u, phi, phi_old, pt, active);
       // stopping test: the active set repeats and ||P_k R_k|| <= tol ||P_0 R_0||
       k_pdas_check(c->pdas_part, c->R, active, c->act_prev, F.g, c->prob.dirichlet, c->s);
@@ -1497,18 +1497,13 @@ mfpff_status mfpff_pdas_solve(mfpff_ctx* c, double* u, double* phi, const double
       if (r0 < 0) r0 = rn;
       out.rel_residual = r0 > 0 ? rn / r0 : 0.0;
       if (k > 0 && nd == 0.0 && rn <= tol * r0) {
-        (void)hipEventDestroy(e0);
         st = MFPFF_OK;
         out.converged = 1;
         break;
       }
-      if (k == max_newton) {
-        (void)hipEventDestroy(e0);
-        break;
-      }
+      if (k == max_newton) break;
       mfpff_solve_info loc{};
-      const mfpff_status sst = linearise_solve_update(c, u, phi, phi_old, pt, active, e0, &loc);
-      (void)hipEventDestroy(e0);
+      const mfpff_status sst = linearise_solve_update(c, u, phi, phi_old, pt, active, e0.e, &loc);
       out.newton_steps = k + 1;
       out.gmres_iterations += loc.iterations;
       HIPCHK(hipMemcpyAsync(c->act_prev, active, F.nn, hipMemcpyDeviceToDevice, c->s));
