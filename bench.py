@@ -326,6 +326,23 @@ def main():
         pinfo["ms_wall"] = (time.perf_counter() - t0) * 1e3
         detail["active_set_loop"] = pinfo
         print(f"[bench] active-set loop: {pinfo}", file=sys.stderr, flush=True)
+        # load stepping (Section 5 loading, Section 3 extrapolation): three steps of the tension
+        # test's increment from rest, phi = 1 off the notch
+        from synth.fields import make_phi
+        lu = torch.zeros(cfg.dim * cfg.n_nodes, dtype=torch.float64, device="cuda")
+        lp_prev, lp_prev2 = torch.tensor(make_phi(cfg.with_(phi_mode="ones")), device="cuda"), None
+        du, ldir, steps_rec = 1e-5, [0.0] * (cfg.dim - 1) + [1.0], []
+        for t in range(1, 4):
+            lphi = lp_prev.clone()
+            _, linfo = ctx.load_step(lu, lphi, lp_prev, lp_prev2, [t * du * a for a in ldir], max_newton=20,
+                                     tol=1e-8, raise_on_noconv=False)
+            steps_rec.append({"u_top": t * du, "newton_steps": linfo["newton_steps"],
+                              "converged": linfo["converged"], "gmres_iterations": linfo["gmres_iterations"],
+                              "ms": linfo["ms_total"], "reaction_top": linfo["reaction_top"][-1]})
+            lp_prev2, lp_prev = lp_prev, lphi
+        detail["load_steps"] = {"du": du, "steps": steps_rec,
+                                "ms_per_load_step": sum(r["ms"] for r in steps_rec) / len(steps_rec)}
+        print(f"[bench] load steps: {steps_rec}", file=sys.stderr, flush=True)
         # the same Newton step with the spectral (Miehe) split of Section 2.1
         sctx, _, sstate = build_context(cfg.with_(split="miehe"))
         ssec, sinfos = time_newton(sctx, sstate, 2, 1)

@@ -242,6 +242,33 @@ mfpff_status mfpff_pdas_solve(mfpff_ctx* ctx, double* u, double* phi, const doub
                               const double* phi_tilde, uint8_t* active, int max_newton, double tol,
                               mfpff_pdas_info* info);
 
+/* Result of mfpff_load_step. */
+typedef struct {
+  mfpff_pdas_info pdas;             /* the active-set loop of the step (ms_total: the whole call) */
+  double reaction_top[3];           /* per component, the sum of the displacement residual rows
+                                       over the top face's nodes at the final iterate */
+  double reaction_bottom[3];        /* the same over the bottom face (unused entries: 0) */
+} mfpff_load_info;
+
+/* One load step of the single-edge-notched tests (Section 5: a displacement prescribed on the
+ * top boundary that grows with the step, the bottom held fixed), with the extrapolated phase
+ * field of Section 3 in the degradation g:
+ *   u := 0 on the bottom face and u := u_top on the top face, every component (the two faces
+ *        normal to the last axis, the faces the Dirichlet mask fixes);
+ *   phi~ := 2 phi_prev - phi_prev2 (linear extrapolation over two equal steps; phi_prev2 NULL,
+ *        the first step: phi~ := phi_prev);
+ *   Algorithm 1 as mfpff_pdas_solve from (u, phi) with phi_old = phi_prev and this phi~;
+ *   reactions from the residual at the final iterate.
+ * u (dim*n_nodes) and phi (n_nodes) are device arrays updated in place (on entry normally the
+ * previous step's solution, phi a copy of phi_prev); phi_prev, phi_prev2 (n_nodes, device) are read
+ * and must not be the array phi; u_top is a host array of dim values; active (n_nodes bytes,
+ * device) receives the final active set.  Status as mfpff_pdas_solve; MFPFF_ERR_ARG also when the
+ * problem has dirichlet = 0, u_top is not finite, or phi_prev or phi_prev2 is phi.  *info is filled
+ * whenever the loop ran.  Synchronises. */
+mfpff_status mfpff_load_step(mfpff_ctx* ctx, double* u, double* phi, const double* phi_prev,
+                             const double* phi_prev2, const double* u_top, uint8_t* active,
+                             int max_newton, double tol, mfpff_load_info* info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -82,6 +82,20 @@ class PdasInfo(ctypes.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class LoadInfo(ctypes.Structure):
+    _fields_ = [
+        ("pdas", PdasInfo),
+        ("reaction_top", ctypes.c_double * 3),
+        ("reaction_bottom", ctypes.c_double * 3),
+    ]
+
+    def as_dict(self, dim):
+        out = self.pdas.as_dict()
+        out["reaction_top"] = [self.reaction_top[a] for a in range(dim)]
+        out["reaction_bottom"] = [self.reaction_bottom[a] for a in range(dim)]
+        return out
+
+
 class LevelDesc(ctypes.Structure):
     _fields_ = [
         ("N", ctypes.c_int),
@@ -100,7 +114,7 @@ EXPORTS = [
     "mfpff_set_point",
     "mfpff_apply_jacobian", "mfpff_diagonal", "mfpff_smooth", "mfpff_transfer", "mfpff_coarse_solve",
     "mfpff_vcycle", "mfpff_gmres_solve", "mfpff_residual", "mfpff_residual_param_vjp", "mfpff_active_set",
-    "mfpff_newton_step", "mfpff_pdas_solve", "mfpff_element_matrices",
+    "mfpff_newton_step", "mfpff_pdas_solve", "mfpff_element_matrices", "mfpff_load_step",
 ]
 
 _lib = None
@@ -135,6 +149,7 @@ def load_library(path=LIB_PATH):
         "mfpff_newton_step": ([VP, P, P, P, P, P, ctypes.POINTER(SolveInfo)], I),
         "mfpff_pdas_solve": ([VP, P, P, P, P, P, I, D, ctypes.POINTER(PdasInfo)], I),
         "mfpff_element_matrices": ([VP, I, P], I),
+        "mfpff_load_step": ([VP, P, P, P, P, ctypes.POINTER(D), P, I, D, ctypes.POINTER(LoadInfo)], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -364,6 +379,31 @@ class Context:
             self._check(st)
         self.levels = [self.level_info(l) for l in range(len(self.levels))]
         return active, info.as_dict()
+
+    def load_step(self, u, phi, phi_prev, phi_prev2, u_top, active=None, max_newton=20, tol=1e-8,
+                  raise_on_noconv=True):
+        """One load step: u := 0 on the bottom face and u_top on the top face, phi~ from the two
+        previous phase fields (phi_prev2 None: phi~ = phi_prev), Algorithm 1 from (u, phi) with
+        phi_old = phi_prev (u, phi updated in place); returns the final active set and the
+        loop's counts with the face reactions."""
+        nn = self.n_nodes
+        if active is None:
+            active = torch.empty(nn, dtype=torch.uint8, device=u.device)
+        top = [float(v) for v in u_top]
+        if len(top) != self.dim:
+            raise ValueError(f"u_top needs {self.dim} values")
+        top_c = (ctypes.c_double * 3)(*(top + [0.0] * (3 - self.dim)))
+        info = LoadInfo()
+        st = self.lib.mfpff_load_step(self.h, _ptr(u, torch.float64, self.dim * nn, "u"),
+                                      _ptr(phi, torch.float64, nn, "phi"),
+                                      _ptr(phi_prev, torch.float64, nn, "phi_prev"),
+                                      _ptr(phi_prev2, torch.float64, nn, "phi_prev2", allow_none=True),
+                                      top_c, _ptr(active, torch.uint8, nn, "active"), int(max_newton), float(tol),
+                                      ctypes.byref(info))
+        if st != 5 or raise_on_noconv:
+            self._check(st)
+        self.levels = [self.level_info(l) for l in range(len(self.levels))]
+        return active, info.as_dict(self.dim)
 
 
 def problem_from(cfg, levels, vcycle_prec=None, dirichlet=None, **overrides):

@@ -142,6 +142,8 @@ struct mfpff_ctx {
   double* pvjp_part = nullptr;
   uint8_t* act_prev = nullptr;   // active-set loop: the previous step's active set
   double* pdas_part = nullptr;   // active-set loop: stopping-test partial sums
+  double* phit_ext = nullptr;    // load stepping: the extrapolated phi~
+  double* react = nullptr;       // load stepping: face reaction sums
   double* pvjp_out = nullptr;
   bool linearized = false;  // full linearisation (smoothers, coarse solve)
   bool has_point = false;   // fields and masks injected (products allowed)
@@ -1148,7 +1150,8 @@ void mfpff_destroy(mfpff_ctx* c) {
   }
   void* ps[] = {c->elem, c->finite_flag, c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
                 c->WpT, c->Gpu, c->cs_in, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lst, c->part, c->V,
-                c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out, c->act_prev, c->pdas_part};
+                c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out, c->act_prev, c->pdas_part,
+                c->phit_ext, c->react};
   for (void* p : ps) F(p);
   for (int i = 0; i < 5; ++i) F(c->s64[i]);
   if (c->hhost) (void)hipHostFree(c->hhost);
@@ -1429,6 +1432,59 @@ static mfpff_status linearise_solve_update(mfpff_ctx* c, double* u, double* phi,
   return st;
 }
 
+// Algorithm 1 to its stopping test from (u, phi) with U^old = phi_old and phi~ = pt; fills
+// everything of *out but ms_total.  On return c->R holds the residual at the final iterate.
+static mfpff_status pdas_loop(mfpff_ctx* c, double* u, double* phi, const double* phi_old, const double* pt,
+                              uint8_t* active, int max_newton, double tol, mfpff_pdas_info* out) {
+  Level& F = c->lv[c->L];
+  if (!c->act_prev) c->act_prev = dalloc<uint8_t>(F.nn);
+  if (!c->pdas_part) c->pdas_part = dalloc<double>((size_t)2 * pdas_check_blocks(F.nn));
+  const int nb = pdas_check_blocks(F.nn);
+  std::vector<double> ph((size_t)2 * nb);
+  mfpff_status st = MFPFF_ERR_NOCONV;
+  double r0 = -1.0;
+  for (int k = 0; k <= max_newton; ++k) {
+    ScopedEvent e0;
+    HIPCHK(hipEventRecord(e0.e, c->s));
+    residual_and_active(c, u, phi, phi_old, pt, active);
+    // stopping test: the active set repeats and ||P_k R_k|| <= tol ||P_0 R_0||
+    k_pdas_check(c->pdas_part, c->R, active, c->act_prev, F.g, c->prob.dirichlet, c->s);
+    LAUNCHCHK();
+    HIPCHK(hipMemcpyAsync(ph.data(), c->pdas_part, ph.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    double ss = 0, nd = 0;
+    for (int b = 0; b < nb; ++b) {
+      ss += ph[2 * b];
+      nd += ph[2 * b + 1];
+    }
+    const double rn = std::sqrt(ss);
+    if (r0 < 0) r0 = rn;
+    out->rel_residual = r0 > 0 ? rn / r0 : 0.0;
+    if (k > 0 && nd == 0.0 && rn <= tol * r0) {
+      st = MFPFF_OK;
+      out->converged = 1;
+      break;
+    }
+    if (k == max_newton) break;
+    mfpff_solve_info loc{};
+    const mfpff_status sst = linearise_solve_update(c, u, phi, phi_old, pt, active, e0.e, &loc);
+    out->newton_steps = k + 1;
+    out->gmres_iterations += loc.iterations;
+    HIPCHK(hipMemcpyAsync(c->act_prev, active, F.nn, hipMemcpyDeviceToDevice, c->s));
+    if (sst != MFPFF_OK) {
+      st = sst;
+      c->err = "GMRES reached max_iter inside the active-set loop";
+      break;
+    }
+  }
+  HIPCHK(hipStreamSynchronize(c->s));
+  std::vector<uint8_t> ah(F.nn);
+  HIPCHK(hipMemcpy(ah.data(), active, F.nn, hipMemcpyDeviceToHost));
+  for (auto v : ah) out->n_active += v ? 1 : 0;
+  if (st == MFPFF_ERR_NOCONV && !out->converged && c->err.empty()) c->err = "active-set loop reached max_newton";
+  return st;
+}
+
 static int count_active(mfpff_ctx* c) {
   Level& F = c->lv[c->L];
   std::vector<uint8_t> mh(F.nn);
@@ -1469,57 +1525,54 @@ mfpff_status mfpff_pdas_solve(mfpff_ctx* c, double* u, double* phi, const double
     require_ptr(phi_old, "phi_old");
     require_ptr(active, "active");
     if (max_newton < 0 || !(tol >= 0.0)) throw StatusError{MFPFF_ERR_ARG, "max_newton must be >= 0 and tol >= 0"};
-    const double* pt = phi_tilde ? phi_tilde : phi_old;
-    Level& F = c->lv[c->L];
-    if (!c->act_prev) c->act_prev = dalloc<uint8_t>(F.nn);
-    if (!c->pdas_part) c->pdas_part = dalloc<double>((size_t)2 * pdas_check_blocks(F.nn));
-    const int nb = pdas_check_blocks(F.nn);
-    std::vector<double> ph((size_t)2 * nb);
-    mfpff_pdas_info out{};
-    mfpff_status st = MFPFF_ERR_NOCONV;
-    double r0 = -1.0;
     const auto t0 = std::chrono::steady_clock::now();
-    for (int k = 0; k <= max_newton; ++k) {
-      ScopedEvent e0;
-      HIPCHK(hipEventRecord(e0.e, c->s));
-      residual_and_active(c, u, phi, phi_old, pt, active);
-      // stopping test: the active set repeats and ||P_k R_k|| <= tol ||P_0 R_0||
-      k_pdas_check(c->pdas_part, c->R, active, c->act_prev, F.g, c->prob.dirichlet, c->s);
-      LAUNCHCHK();
-      HIPCHK(hipMemcpyAsync(ph.data(), c->pdas_part, ph.size() * sizeof(double), hipMemcpyDeviceToHost, c->s));
-      HIPCHK(hipStreamSynchronize(c->s));
-      double ss = 0, nd = 0;
-      for (int b = 0; b < nb; ++b) {
-        ss += ph[2 * b];
-        nd += ph[2 * b + 1];
-      }
-      const double rn = std::sqrt(ss);
-      if (r0 < 0) r0 = rn;
-      out.rel_residual = r0 > 0 ? rn / r0 : 0.0;
-      if (k > 0 && nd == 0.0 && rn <= tol * r0) {
-        st = MFPFF_OK;
-        out.converged = 1;
-        break;
-      }
-      if (k == max_newton) break;
-      mfpff_solve_info loc{};
-      const mfpff_status sst = linearise_solve_update(c, u, phi, phi_old, pt, active, e0.e, &loc);
-      out.newton_steps = k + 1;
-      out.gmres_iterations += loc.iterations;
-      HIPCHK(hipMemcpyAsync(c->act_prev, active, F.nn, hipMemcpyDeviceToDevice, c->s));
-      if (sst != MFPFF_OK) {
-        st = sst;
-        c->err = "GMRES reached max_iter inside the active-set loop";
-        break;
-      }
-    }
-    HIPCHK(hipStreamSynchronize(c->s));
-    std::vector<uint8_t> ah(F.nn);
-    HIPCHK(hipMemcpy(ah.data(), active, F.nn, hipMemcpyDeviceToHost));
-    for (auto v : ah) out.n_active += v ? 1 : 0;
+    mfpff_pdas_info out{};
+    const mfpff_status st = pdas_loop(c, u, phi, phi_old, phi_tilde ? phi_tilde : phi_old, active, max_newton, tol, &out);
     out.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (info) *info = out;
-    if (st == MFPFF_ERR_NOCONV && !out.converged && c->err.empty()) c->err = "active-set loop reached max_newton";
+    return st;
+  });
+}
+
+mfpff_status mfpff_load_step(mfpff_ctx* c, double* u, double* phi, const double* phi_prev, const double* phi_prev2,
+                             const double* u_top, uint8_t* active, int max_newton, double tol, mfpff_load_info* info) {
+  return run(c, [&]() {
+    require_ptr(u, "u");
+    require_ptr(phi, "phi");
+    require_ptr(phi_prev, "phi_prev");
+    require_ptr(u_top, "u_top");
+    require_ptr(active, "active");
+    if (max_newton < 0 || !(tol >= 0.0)) throw StatusError{MFPFF_ERR_ARG, "max_newton must be >= 0 and tol >= 0"};
+    if (!c->prob.dirichlet) throw StatusError{MFPFF_ERR_ARG, "load stepping needs the Dirichlet faces (dirichlet = 1)"};
+    if (phi_prev == phi || phi_prev2 == phi)
+      throw StatusError{MFPFF_ERR_ARG, "phi_prev and phi_prev2 must not alias phi (phi is updated in place)"};
+    for (int a = 0; a < c->dim; ++a)
+      if (!std::isfinite(u_top[a])) throw StatusError{MFPFF_ERR_ARG, "u_top must be finite"};
+    const auto t0 = std::chrono::steady_clock::now();
+    Level& F = c->lv[c->L];
+    if (!c->phit_ext) c->phit_ext = dalloc<double>(F.nn);
+    if (!c->react) c->react = dalloc<double>(6);
+    k_impose_faces(u, F.g, u_top, c->s);
+    const double* pt = phi_prev;
+    if (phi_prev2) {
+      k_extrapolate(c->phit_ext, phi_prev, phi_prev2, F.nn, c->s);
+      pt = c->phit_ext;
+    }
+    LAUNCHCHK();
+    mfpff_load_info out{};
+    const mfpff_status st = pdas_loop(c, u, phi, phi_prev, pt, active, max_newton, tol, &out.pdas);
+    // c->R holds the residual at the final iterate (the loop tests before it steps)
+    k_face_reaction(c->react, c->R, F.g, c->s);
+    LAUNCHCHK();
+    double rh[6] = {0, 0, 0, 0, 0, 0};
+    HIPCHK(hipMemcpyAsync(rh, c->react, 2 * c->dim * sizeof(double), hipMemcpyDeviceToHost, c->s));
+    HIPCHK(hipStreamSynchronize(c->s));
+    for (int a = 0; a < c->dim; ++a) {
+      out.reaction_bottom[a] = rh[a];
+      out.reaction_top[a] = rh[c->dim + a];
+    }
+    out.pdas.ms_total = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    if (info) *info = out;
     return st;
   });
 }

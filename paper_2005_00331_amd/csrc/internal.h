@@ -181,6 +181,11 @@ void k_splitmix_start(double* v, const uint8_t* mask, long long nn, int dim, uns
 
 // Reductions: partial sums per block, then a one-block finish.
 int dot_blocks(long long n);
+// load stepping: boundary values on the two faces normal to the last axis (bottom 0, top
+// top[0..dim)), phi~ = 2 p1 - p2, and per-(face, component) reaction sums (2 * dim values)
+void k_impose_faces(double* u, const Geom& g, const double* top, hipStream_t s);
+void k_extrapolate(double* pt, const double* p1, const double* p2, long long n, hipStream_t s);
+void k_face_reaction(double* out, const double* R, const Geom& g, hipStream_t s);
 // stopping test of Algorithm 1: per-workgroup (sum of R^2 on the free dofs, changed nodes of act vs prev)
 int pdas_check_blocks(long long nn);
 void k_pdas_check(double* part, const double* R, const uint8_t* act, const uint8_t* prev, const Geom& g, int dirichlet,

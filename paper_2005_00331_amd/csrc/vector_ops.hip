@@ -288,6 +288,56 @@ void k_pdas_check(double* part, const double* R, const uint8_t* act, const uint8
                      prev, g, dirichlet);
 }
 
+// Load stepping (Section 5): every displacement component is 0 on the bottom face and
+// t du on the top face (the two faces normal to the last axis); thread i < n_face covers
+// bottom node i, thread n_face + i top node i.
+__global__ void impose_faces_kernel(double* u, Geom g, double t0, double t1, double t2) {
+  const long long nf = g.dim == 2 ? (long long)g.M : (long long)g.M * g.M;
+  const long long top_off = (long long)(g.M - 1) * nf;
+  GSTRIDE(i, 2 * nf) {
+    const bool top = i >= nf;
+    const long long node = (top ? i - nf + top_off : i);
+    u[node] = top ? t0 : 0.0;
+    u[g.n_nodes + node] = top ? t1 : 0.0;
+    if (g.dim == 3) u[2 * g.n_nodes + node] = top ? t2 : 0.0;
+  }
+}
+void k_impose_faces(double* u, const Geom& g, const double* top, hipStream_t s) {
+  const long long nf = g.dim == 2 ? (long long)g.M : (long long)g.M * g.M;
+  hipLaunchKernelGGL(impose_faces_kernel, dim3(grid_for(2 * nf)), dim3(kThreads), 0, s, u, g, top[0], top[1],
+                     g.dim == 3 ? top[2] : 0.0);
+}
+
+// phi~ = 2 phi_{n-1} - phi_{n-2}: linear extrapolation over two equal steps (Section 3)
+__global__ void extrapolate_kernel(double* pt, const double* p1, const double* p2, long long n) {
+  GSTRIDE(i, n) pt[i] = 2.0 * p1[i] - p2[i];
+}
+void k_extrapolate(double* pt, const double* p1, const double* p2, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(extrapolate_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, pt, p1, p2, n);
+}
+
+// reaction on a face: out[f * dim + c] = sum over the nodes of face f (0 bottom, 1 top) of the
+// displacement residual row of component c; one workgroup per (face, component), fixed order
+__global__ void face_reaction_kernel(double* out, const double* R, Geom g) {
+  __shared__ double sh[kThreads / 64];
+  const int f = blockIdx.x / g.dim, c = blockIdx.x % g.dim;
+  const long long nf = g.dim == 2 ? (long long)g.M : (long long)g.M * g.M;
+  const double* r = R + c * g.n_nodes + (f ? (long long)(g.M - 1) * nf : 0);
+  double s = 0;
+  for (long long i = threadIdx.x; i < nf; i += blockDim.x) s += r[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0;
+    for (int w = 0; w < kThreads / 64; ++w) a += sh[w];
+    out[blockIdx.x] = a;
+  }
+}
+void k_face_reaction(double* out, const double* R, const Geom& g, hipStream_t s) {
+  hipLaunchKernelGGL(face_reaction_kernel, dim3(2 * g.dim), dim3(kThreads), 0, s, out, R, g);
+}
+
 // SplitMix64 (Steele, Lea, Flood 2014): output n of stream st with seed s is
 // mix(s + (n + 1 + st * 2^40) * 0x9E3779B97F4A7C15), mapped to [-1, 1).
 __device__ __forceinline__ double splitmix_pm1(unsigned long long seed, unsigned long long st, unsigned long long n) {

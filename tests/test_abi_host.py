@@ -83,7 +83,7 @@ def _c_struct_fields(name):
         decl = " ".join(decl.split())
         if not decl:
             continue
-        m = re.match(r"(unsigned long long|long long|double|int) (.*)", decl)
+        m = re.match(r"(unsigned long long|long long|double|int|mfpff_\w+) (.*)", decl)
         assert m, decl
         for v in m.group(2).split(","):
             v = v.strip()
@@ -96,15 +96,18 @@ def test_problem_structure_matches_header():
     """The ctypes structures mirror the header field by field, in order and type."""
     import ctypes as C
     from paper_2005_00331_amd import binding
-    ctype = {"int": C.c_int, "double": C.c_double, "unsigned long long": C.c_ulonglong, "long long": C.c_longlong}
+    ctype = {"int": C.c_int, "double": C.c_double, "unsigned long long": C.c_ulonglong, "long long": C.c_longlong,
+             "mfpff_pdas_info": binding.PdasInfo}
     for cname, pyst in (("mfpff_problem", binding.Problem), ("mfpff_solve_info", binding.SolveInfo),
-                        ("mfpff_level_desc", binding.LevelDesc)):
+                        ("mfpff_level_desc", binding.LevelDesc), ("mfpff_pdas_info", binding.PdasInfo),
+                        ("mfpff_load_info", binding.LoadInfo)):
         cf = _c_struct_fields(cname)
         pf = pyst._fields_
         assert len(cf) == len(pf), cname
         for c, (pname, ptype) in zip(cf, pf):
             assert pname.rstrip("_") == c[1], (cname, pname, c)
             if len(c) == 3:
-                assert ptype._type_ is ctype[c[0]] and ptype._length_ == binding.MAX_LEVELS, (cname, pname)
+                n = int(c[2]) if c[2].isdigit() else getattr(binding, c[2].replace("MFPFF_", ""))
+                assert ptype._type_ is ctype[c[0]] and ptype._length_ == n, (cname, pname)
             else:
                 assert ptype is ctype[c[0]], (cname, pname, c[0])
