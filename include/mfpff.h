@@ -98,6 +98,10 @@ typedef struct {
   int max_iter;                     /* total GMRES iteration cap */
   double rtol;                      /* relative true-residual tolerance */
   int split;                        /* mfpff_split */
+  int pdas_project;                 /* active-set update of Algorithm 1: 0 keeps phi on A_k (delta
+                                       phi = 0, as the paper writes it); 1 first sets phi := phi_old
+                                       on A_k (the iterate on the obstacle, the primal-dual active
+                                       set update) and linearises there */
 } mfpff_problem;
 
 typedef struct {

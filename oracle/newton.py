@@ -7,7 +7,11 @@ Algorithm 1 (primal-dual active set).  Readings:
     the Newton step solves G^ dU = -P R and the active set is
         A = { phi-dofs i : -(M_L^-1 R)_i + c (phi - phi_old)_i > 0 },
     i.e. the multiplier -R_i wants phi to grow above phi_old;
-  * M is the row-sum-lumped phi mass matrix, c = 1.
+  * M is the row-sum-lumped phi mass matrix, c = 1;
+  * the Newton step keeps phi on A_k (delta phi = 0 there, as the algorithm is written) unless
+    cfg.pdas_project is set: then phi := phi_old on A_k first, the residual is evaluated again at
+    that point and the step is taken from there (the primal-dual active-set update of
+    Hintermueller, Ito and Kunisch, which puts the iterate on the obstacle on the active set).
 """
 import numpy as np
 
@@ -30,6 +34,10 @@ def newton_step(cfg, levels_nk, u, phi, phi_old, phi_t):
     m = op.material_of(cfg)
     R = op.residual(mesh, m, u, phi, phi_t)
     act, ind = active_set(mesh, R, phi, phi_old, cfg.as_c)
+    R_at_start = R
+    if getattr(cfg, "pdas_project", False):
+        phi = np.where(act != 0, phi_old, phi)
+        R = op.residual(mesh, m, u, phi, phi_t)
     hier = Hierarchy(cfg, levels_nk, u, phi, phi_t, act)
     fine = hier.levels[-1]
     b = -fine.pvec * R
@@ -37,7 +45,7 @@ def newton_step(cfg, levels_nk, u, phi, phi_old, phi_t):
     d, nn = cfg.dim, mesh.n_nodes
     u_new = u + dU[: d * nn].reshape(d, nn)
     phi_new = phi + dU[d * nn:]
-    return dict(R=R, active=act, indicator=ind, b=b, dU=dU, u=u_new, phi=phi_new, info=info, hier=hier)
+    return dict(R=R_at_start, active=act, indicator=ind, b=b, dU=dU, u=u_new, phi=phi_new, info=info, hier=hier)
 
 
 def pdas_solve(cfg, levels_nk, u, phi, phi_old, phi_t, max_newton=20, tol=1e-8):

@@ -51,6 +51,7 @@ class Problem(ctypes.Structure):
         ("max_iter", ctypes.c_int),
         ("rtol", ctypes.c_double),
         ("split", ctypes.c_int),
+        ("pdas_project", ctypes.c_int),
     ]
 
 
@@ -161,7 +162,7 @@ def load_library(path=LIB_PATH):
 
 def make_problem(dim, levels, *, dirichlet=True, lam=121.15e3, mu=80.77e3, Gc=2.7, eps, kappa=1e-10, as_c=1.0,
                  cheb_degree=5, cheb_lo=0.24, cheb_hi=1.2, lanczos_steps=15, lanczos_seed=20050331,
-                 vcycle_prec=F64, restart=30, max_iter=300, rtol=1e-8, split="amor"):
+                 vcycle_prec=F64, restart=30, max_iter=300, rtol=1e-8, split="amor", pdas_project=False):
     """levels: list of (N, k) from the coarsest to the finest."""
     p = Problem()
     p.dim = dim
@@ -178,6 +179,7 @@ def make_problem(dim, levels, *, dirichlet=True, lam=121.15e3, mu=80.77e3, Gc=2.
     if split not in SPLITS:
         raise ValueError(f"split must be one of {sorted(SPLITS)}")
     p.split = SPLITS[split]
+    p.pdas_project = 1 if pdas_project else 0
     return p
 
 
@@ -416,6 +418,6 @@ def problem_from(cfg, levels, vcycle_prec=None, dirichlet=None, **overrides):
               eps=cfg.eps, kappa=cfg.kappa, as_c=cfg.as_c, cheb_degree=cfg.cheb_degree, cheb_lo=cfg.cheb_lo,
               cheb_hi=cfg.cheb_hi, lanczos_steps=cfg.lanczos_steps, lanczos_seed=cfg.lanczos_seed,
               vcycle_prec=vp, restart=cfg.restart, max_iter=cfg.max_iter, rtol=cfg.rtol,
-              split=getattr(cfg, "split", "amor"))
+              split=getattr(cfg, "split", "amor"), pdas_project=getattr(cfg, "pdas_project", False))
     kw.update(overrides)
     return make_problem(cfg.dim, levels, **kw)

@@ -985,6 +985,7 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
   if (p.restart < 1 || p.restart > 64 || p.max_iter < 0 || !(p.rtol >= 0.0)) return MFPFF_ERR_ARG;
   if (p.vcycle_prec != MFPFF_F64 && p.vcycle_prec != MFPFF_F32) return MFPFF_ERR_ARG;
   if (p.split != MFPFF_SPLIT_AMOR && p.split != MFPFF_SPLIT_MIEHE) return MFPFF_ERR_ARG;
+  if (p.pdas_project != 0 && p.pdas_project != 1) return MFPFF_ERR_ARG;
   if (!(p.eps > 0.0) || !(p.kappa >= 0.0) || !(p.cheb_hi > p.cheb_lo) || !(p.cheb_lo > 0.0)) return MFPFF_ERR_ARG;
   for (int l = 0; l < p.n_levels; ++l) {
     if (p.level_N[l] < 1 || p.level_k[l] < 1 || p.level_k[l] > kMaxDeg) return MFPFF_ERR_ARG;
@@ -1389,9 +1390,8 @@ mfpff_status mfpff_active_set(mfpff_ctx* c, const double* R, const double* phi, 
 }  // extern "C"
 
 namespace {
-// residual at (u, phi; phi~) into c->R and the active set of Algorithm 1 from it
-static void residual_and_active(mfpff_ctx* c, const double* u, const double* phi, const double* phi_old, const double* pt,
-                                uint8_t* active) {
+// residual at (u, phi; phi~) into c->R
+static void residual_into_R(mfpff_ctx* c, const double* u, const double* phi, const double* pt) {
   Level& F = c->lv[c->L];
   k_fill<double>(c->R, 0.0, F.n, c->s);
   CellArgs<double> a = cell_args<double>(c, F, F.lin, nullptr, c->R, 1.0);
@@ -1400,18 +1400,32 @@ static void residual_and_active(mfpff_ctx* c, const double* u, const double* phi
   a.phit = pt;
   a.mask = nullptr;
   HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
+}
+
+// residual at (u, phi; phi~) into c->R and the active set of Algorithm 1 from it
+static void residual_and_active(mfpff_ctx* c, const double* u, const double* phi, const double* phi_old, const double* pt,
+                                uint8_t* active) {
+  Level& F = c->lv[c->L];
+  residual_into_R(c, u, phi, pt);
   k_active_set(active, c->R, phi, phi_old, c->ml, F.nn, c->dim, c->prob.as_c, c->s);
   LAUNCHCHK();
 }
 
 // linearise at (u, phi, active), solve G^ dU = -P R (R in c->R), update u and phi; fills
-// iterations, residual and times of *loc
+// iterations, residual and times of *loc.  With pdas_project, phi := phi_old on the active set
+// first and R is evaluated again there, so that delta phi = 0 on A keeps the iterate on the
+// obstacle.
 static mfpff_status linearise_solve_update(mfpff_ctx* c, double* u, double* phi, const double* phi_old, const double* pt,
                                            const uint8_t* active, hipEvent_t e0, mfpff_solve_info* loc) {
   Level& F = c->lv[c->L];
   const int d = c->dim;
   ScopedEvent e1, e2;
   c->linearized = false;
+  if (c->prob.pdas_project) {
+    k_project_active(phi, phi_old, active, F.nn, c->s);
+    LAUNCHCHK();
+    residual_into_R(c, u, phi, pt);
+  }
   set_linearization(c, u, phi, phi_old, active, pt);
   HIPCHK(hipEventRecord(e1.e, c->s));
   // b = -P R

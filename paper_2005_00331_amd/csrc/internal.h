@@ -181,6 +181,8 @@ void k_splitmix_start(double* v, const uint8_t* mask, long long nn, int dim, uns
 
 // Reductions: partial sums per block, then a one-block finish.
 int dot_blocks(long long n);
+// phi_i := phi_old_i on the active set (the projected active-set update)
+void k_project_active(double* phi, const double* phi_old, const uint8_t* act, long long n, hipStream_t s);
 // load stepping: boundary values on the two faces normal to the last axis (bottom 0, top
 // top[0..dim)), phi~ = 2 p1 - p2, and per-(face, component) reaction sums (2 * dim values)
 void k_impose_faces(double* u, const Geom& g, const double* top, hipStream_t s);

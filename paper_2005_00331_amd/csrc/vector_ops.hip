@@ -288,6 +288,15 @@ void k_pdas_check(double* part, const double* R, const uint8_t* act, const uint8
                      prev, g, dirichlet);
 }
 
+// primal-dual active-set update: the iterate is put on the obstacle on the active set,
+// phi_i := phi_old_i where act_i != 0
+__global__ void project_active_kernel(double* phi, const double* phi_old, const uint8_t* act, long long n) {
+  GSTRIDE(i, n) if (act[i]) phi[i] = phi_old[i];
+}
+void k_project_active(double* phi, const double* phi_old, const uint8_t* act, long long n, hipStream_t s) {
+  hipLaunchKernelGGL(project_active_kernel, dim3(grid_for(n)), dim3(kThreads), 0, s, phi, phi_old, act, n);
+}
+
 // Load stepping (Section 5): every displacement component is 0 on the bottom face and
 // t du on the top face (the two faces normal to the last axis); thread i < n_face covers
 // bottom node i, thread n_face + i top node i.

@@ -118,25 +118,31 @@ def test_active_set_loop_matches_oracle(name, kw):
     assert rel_err(host(u).ravel(), ref["u"].ravel()) <= 1e-6 and rel_err(host(phi), ref["phi"]) <= 1e-6
 
 
-# (workload, overrides, split, displacement increment per step): three load steps each, at Q1
-# from phi = 1 off the notch.  At Q2 the same start makes the loop's path, and with it the
-# converged state, depend on rounding (test_load_step_boundary_terms covers Q2 without a loop).
+# (workload, overrides, split, displacement increment per step, projected update): three load
+# steps each from phi = 1 off the notch.  With Algorithm 1's update as written (delta phi = 0 on
+# A_k) the converged state depends on the Newton path, which at Q2 rounding decides from this
+# start, so those cases run at Q1 (test_load_step_boundary_terms covers Q2 without a loop); with
+# the projected update the converged state is unique and Q2 cases run too.
 LOAD_CASES = [
-    ("C1", dict(N=8, n_h_levels=2), "amor", 2e-3),
-    ("C1", dict(N=8, n_h_levels=2), "miehe", 2e-3),
-    ("C1", dict(dim=3, N=4, n_h_levels=2), "amor", 1e-3),
+    ("C1", dict(N=8, n_h_levels=2), "amor", 2e-3, False),
+    ("C1", dict(N=8, n_h_levels=2), "miehe", 2e-3, False),
+    ("C1", dict(dim=3, N=4, n_h_levels=2), "amor", 1e-3, False),
+    ("C2", dict(N=8, n_h_levels=2), "amor", 5e-4, True),
+    ("C2", dict(N=16, n_h_levels=3), "amor", 2e-4, True),
+    ("C2", dict(N=8, n_h_levels=2), "miehe", 5e-4, True),
+    ("C3", dict(N=4, n_h_levels=2), "amor", 5e-4, True),
 ]
 
 
-@pytest.mark.parametrize("name,kw,split,du", LOAD_CASES)
-def test_load_steps_match_oracle(name, kw, split, du):
+@pytest.mark.parametrize("name,kw,split,du,project", LOAD_CASES)
+def test_load_steps_match_oracle(name, kw, split, du, project):
     """Three load steps, each compared at its converged state: u, phi, the reactions and the
     final active set off indicator ties (|indicator| within rounding of zero), where either
     decision is right."""
     import torch
     from oracle import loading
     from synth.fields import make_phi
-    cfg = CONFIGS[name].with_(split=split, phi_mode="ones", **kw)
+    cfg = CONFIGS[name].with_(split=split, phi_mode="ones", pdas_project=project, **kw)
     levels = level_list(cfg)
     mesh = Mesh(cfg.dim, cfg.N, cfg.k)
     direction = np.zeros(cfg.dim)
@@ -148,7 +154,7 @@ def test_load_steps_match_oracle(name, kw, split, du):
     phi_prev, phi_prev2 = dev(phi0), None
     ref_prev = phi0
     for t, rec in enumerate(ref, start=1):
-        say(name, kw, split, "load step", t)
+        say(name, kw, split, "projected" if project else "as written", "load step", t)
         phi = phi_prev.clone()
         act, info = ctx.load_step(u, phi, phi_prev, phi_prev2, t * du * direction, tol=1e-10)
         _, ind = newton.active_set(mesh, rec["R"], rec["phi"], ref_prev, cfg.as_c)

@@ -221,3 +221,35 @@ def test_active_set_loop_stops_at_a_fixed_point_with_a_superlinear_tail(name, kw
     assert np.linalg.norm(pvec * R) <= 1e-8 * out["norms"][0]
     r = out["norms"]
     assert r[-1] / r[-2] <= 1e-3 and r[-1] / r[-2] < r[-2] / r[-3]
+
+
+def test_projected_active_set_loop_reaches_the_kkt_point():
+    """With the projected update (phi := phi_old on A_k before the step) the loop ends at a point of
+    the variational inequality of the irreversibility constraint phi <= phi_old: phi <= phi_old
+    everywhere, phi = phi_old with a multiplier -R_phi > 0 on the active set, and R_phi = 0 (to the
+    tolerance) off it; and that point does not depend on how ties of the first active set are
+    broken (two starts that differ by 1e-13 in u)."""
+    from oracle import loading
+    from oracle.fe import Mesh
+    from synth.fields import make_phi
+    cfg = CONFIGS["C2"].with_(N=8, n_h_levels=2, phi_mode="ones", pdas_project=True)
+    levels = level_list(cfg)
+    mesh = Mesh(cfg.dim, cfg.N, cfg.k)
+    phi0 = make_phi(cfg)
+    nn, d = mesh.n_nodes, cfg.dim
+    outs = []
+    for seed in (1, 2):
+        u0 = 1e-13 * np.random.default_rng(seed).standard_normal((d, nn))
+        rec = loading.load_step(cfg, levels, u0, phi0, phi0, None, [0.0, 5e-4], tol=1e-10)
+        assert rec["converged"]
+        act = rec["active"] != 0
+        Rp = rec["R"][d * nn:]
+        r0 = rec["norms"][0]
+        assert np.all(rec["phi"] <= phi0 + 1e-12)
+        assert np.array_equal(rec["phi"][act], phi0[act])
+        assert np.all(Rp[act] < 0)
+        assert np.abs(Rp[~act]).max() <= 1e-8 * r0
+        outs.append(rec)
+    a, b = outs
+    assert np.abs(a["phi"] - b["phi"]).max() <= 1e-8
+    assert np.linalg.norm(a["u"] - b["u"]) <= 1e-8 * np.linalg.norm(a["u"])
