@@ -139,6 +139,48 @@ def time_apply_cold(ctx, reps=10):
     return sorted(times)[len(times) // 2]
 
 
+def time_autograd(cfg, reps=5, warmup=2):
+    """The residual as a torch.autograd.Function (forward R(u, phi; Gc, eps), hand-written backward:
+    the point's coefficient cache, the transposed product and the two parameter cotangents) on the
+    workload's seeded state and cotangent; medians of wall times with the device synchronised
+    around each part, and the ratio of forward + backward to one finest-level product."""
+    import torch
+    from paper_2005_00331_amd import Context, problem_from
+    from paper_2005_00331_amd.autograd import residual
+    from synth import make_inputs
+    ctx = Context(problem_from(cfg, [(cfg.N, cfg.k)]))
+    inp = make_inputs(cfg, ("cotangent",))
+
+    def d(a):
+        return torch.from_numpy(a.ravel().copy()).cuda()
+    u0, phi0, pt, v = d(inp["u"]), d(inp["phi"]), d(inp["phi_tilde"]), d(inp["cotangent"])
+    Gc = torch.tensor(cfg.Gc, dtype=torch.float64, requires_grad=True)
+    eps = torch.tensor(cfg.eps, dtype=torch.float64, requires_grad=True)
+    fwd, bwd = [], []
+    for rep in range(warmup + reps):
+        u = u0.clone().requires_grad_(True)
+        phi = phi0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        R = residual(u, phi, Gc, eps, pt, ctx)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        R.backward(v)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if rep >= warmup:
+            fwd.append(t1 - t0)
+            bwd.append(t2 - t1)
+    tf, tb = sorted(fwd)[len(fwd) // 2], sorted(bwd)[len(bwd) // 2]
+    t_apply = time_apply(ctx)
+    out = {"workload": f"{cfg.name}: 3D {cfg.N}^3 cells Q{cfg.k}, {ctx.n_dofs} dofs, no constraints",
+           "ms_forward": tf * 1e3, "ms_backward": tb * 1e3,
+           "dofs_per_s_forward_backward": ctx.n_dofs / (tf + tb), "apply_us": t_apply * 1e6,
+           "forward_backward_in_products": (tf + tb) / t_apply}
+    ctx.close()
+    return out
+
+
 def time_solve(cfg, prec):
     """One linear solve of the workload's seeded right-hand side: set_linearization, then
     FGMRES to the workload's rtol (after one untimed warm-up solve). FP64 GMRES either way;
@@ -310,6 +352,8 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D runs (C3 solves, C4 products)")
     ap.add_argument("--spmv", action="store_true",
                     help="instead: matrix-free product against the assembled CSR product (rocSPARSE) at p = 1..4")
+    ap.add_argument("--autograd", action="store_true",
+                    help="instead: time the C5 residual forward and backward (autograd) and print that record")
     ap.add_argument("--apply-only", action="store_true",
                     help="only time the finest-level cell kernel (for kernel-trace and counter runs)")
     args = ap.parse_args()
@@ -322,6 +366,9 @@ def main():
     torch.cuda.set_device(0)
     if args.spmv:
         spmv_study()
+        return
+    if args.autograd:
+        print(json.dumps(time_autograd(CONFIGS["C5"])), flush=True)
         return
     cfg = CONFIGS[args.workload]
     print(f"[bench] workload {cfg.name}: {cfg.dim}D N={cfg.N} Q{cfg.k}, {cfg.n_dofs} dofs", file=sys.stderr, flush=True)
@@ -412,6 +459,9 @@ def main():
         c4 = time_products_3d(CONFIGS["C4"])
         print(f"[bench] C4 products: {c4}", file=sys.stderr, flush=True)
         detail["c4_products"] = c4
+        c5 = time_autograd(CONFIGS["C5"])
+        print(f"[bench] C5 residual forward/backward: {c5}", file=sys.stderr, flush=True)
+        detail["c5_autograd"] = c5
     out = {
         "metric": METRIC,
         "value": ctx.n_dofs / sec,

@@ -161,7 +161,7 @@ __global__ __launch_bounds__(kThreads) void cell_kernel(CellArgs<T> a, const Tab
                                                              MODE == MODE_QDATA ? a.qd_out + qoff : nullptr);
     if constexpr (MODE == MODE_QDATA) return;
 
-    if constexpr (MODE == MODE_APPLY || MODE == MODE_APPLY_T || MODE == MODE_BLOCK) {
+    if constexpr (MODE == MODE_APPLY || MODE == MODE_APPLY_T || MODE == MODE_BLOCK || MODE == MODE_RESIDUAL) {
       if (a.elem) {
         // one coalesced copy of the block's results, laid out [block][component][point][cell of
         // the block] so that the node gather reads runs of consecutive cells

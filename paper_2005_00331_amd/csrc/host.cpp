@@ -326,6 +326,31 @@ void launch_fused(mfpff_ctx* c, const Level& L, int mode, int epi, CellArgs<T> a
   HIPCHK(launch_gather_3d<T>(epi, (const T*)c->elem, a, e, c->s));
 }
 
+// residual R(u, phi; phi~) on the finest level into R (F.n values): in 3D the cell kernel writes
+// the element buffer and the node gather adds the cell contributions of every node in a fixed
+// order; in 2D the cell kernel adds them into R
+void residual_launch(mfpff_ctx* c, const double* u, const double* phi, const double* pt, double* R) {
+  Level& F = c->lv[c->L];
+  CellArgs<double> a = cell_args<double>(c, F, F.lin, nullptr, R, 1.0);
+  a.u = u;
+  a.phi = phi;
+  a.phit = pt;
+  a.mask = nullptr;
+  if (c->dim == 3) {
+    a.elem = (double*)c->elem;
+    HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
+    // the gather reads x at every node before it writes y there (same thread); with no mask
+    // the value is not used, so R itself serves
+    a.x = R;
+    Epilogue<double> e{};
+    e.y = R;
+    HIPCHK(launch_gather_3d<double>(EPI_APPLY, (const double*)c->elem, a, e, c->s));
+    return;
+  }
+  k_fill<double>(R, 0.0, F.n, c->s);
+  HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
+}
+
 // y = op(G^) x on level l, or y = b - G^ x when b != null (op = G);
 // accumulate: y += P op(G) P x without initialising y (atomic cell kernel)
 template <typename T>
@@ -1335,14 +1360,7 @@ mfpff_status mfpff_residual(mfpff_ctx* c, const double* u, const double* phi, co
     require_ptr(phi, "phi");
     require_ptr(phi_tilde, "phi_tilde");
     require_ptr(R, "R");
-    Level& F = c->lv[c->L];
-    k_fill<double>(R, 0.0, F.n, c->s);
-    CellArgs<double> a = cell_args<double>(c, F, F.lin, nullptr, R, 1.0);
-    a.u = u;
-    a.phi = phi;
-    a.phit = phi_tilde;
-    a.mask = nullptr;
-    HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
+    residual_launch(c, u, phi, phi_tilde, R);
     return MFPFF_OK;
   });
 }
@@ -1392,14 +1410,7 @@ mfpff_status mfpff_active_set(mfpff_ctx* c, const double* R, const double* phi, 
 namespace {
 // residual at (u, phi; phi~) into c->R
 static void residual_into_R(mfpff_ctx* c, const double* u, const double* phi, const double* pt) {
-  Level& F = c->lv[c->L];
-  k_fill<double>(c->R, 0.0, F.n, c->s);
-  CellArgs<double> a = cell_args<double>(c, F, F.lin, nullptr, c->R, 1.0);
-  a.u = u;
-  a.phi = phi;
-  a.phit = pt;
-  a.mask = nullptr;
-  HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
+  residual_launch(c, u, phi, pt, c->R);
 }
 
 // residual at (u, phi; phi~) into c->R and the active set of Algorithm 1 from it

@@ -586,11 +586,19 @@ void k_scale_rsqrt_dev(double* y, const double* x, const double* sq, long long n
 }
 __global__ void sum_pvjp_kernel(double* out, const double* part, int nb) {
   __shared__ double sh[8];
-  for (int j = 0; j < 2; ++j) {
-    double acc = 0;
-    for (int b = threadIdx.x; b < nb; b += blockDim.x) acc += part[2 * b + j];
-    const double s = block_sum(acc, sh);
-    if (threadIdx.x == 0) out[j] = s;
+  // both sums in one pass over the partials, loads of several iterations in flight
+  double a0 = 0, a1 = 0;
+#pragma unroll 8
+  for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+    const double2 v = reinterpret_cast<const double2*>(part)[b];
+    a0 += v.x;
+    a1 += v.y;
+  }
+  const double s0 = block_sum(a0, sh);
+  const double s1 = block_sum(a1, sh);
+  if (threadIdx.x == 0) {
+    out[0] = s0;
+    out[1] = s1;
   }
 }
 void k_sum_pvjp(double* out2, const double* part, int nb, hipStream_t s) {
