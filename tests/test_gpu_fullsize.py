@@ -101,3 +101,44 @@ def test_c2_newton_step_fullsize():
     r = b - host(ctx.apply_jacobian(-1, dev(dU), op=OP_G))
     assert np.linalg.norm(r) <= 1.01 * cfg.rtol * np.linalg.norm(b)
     assert np.all(dU[pvec == 0] == 0)
+
+
+def test_c2_load_steps_fullsize():
+    """The benchmark's load steps at full size (projected active-set update): after the load-free
+    relaxation step (face values only) and after each of two loaded steps, properties that hold at
+    any size and do not depend on the Newton path: the prescribed face values; the top and bottom
+    reactions cancel
+    (the basis sums to one and the free rows vanish); the KKT conditions of phi <= phi_old
+    (phi = phi_old on the active set, phi <= phi_old elsewhere); and Clapeyron's identity
+    u_top . F_top = 2 E_el(u; phi~) with E_el from the oracle's energy functional at phi~."""
+    import torch
+    from oracle import loading
+    from paper_2005_00331_amd import Context, problem_from
+    from synth.fields import make_phi
+    cfg = CONFIGS["C2"].with_(pdas_project=True)
+    levels = level_list(cfg)
+    mesh = Mesh(cfg.dim, cfg.N, cfg.k)
+    m = op.material_of(cfg)
+    ctx = Context(problem_from(cfg, levels))
+    u = torch.zeros(cfg.dim * cfg.n_nodes, dtype=torch.float64, device="cuda")
+    p_prev, p_prev2 = dev(make_phi(cfg.with_(phi_mode="ones"))), None
+    top, bot = loading.face_nodes(mesh, True), loading.face_nodes(mesh, False)
+    du = 1e-5
+    for t in range(3):
+        say("C2 load step full size", t)
+        phi = p_prev.clone()
+        act, info = ctx.load_step(u, phi, p_prev, p_prev2, [0.0, t * du], max_newton=30, tol=1e-8,
+                                  raise_on_noconv=(t > 0))
+        uh, ph, pold, a = host(u).reshape(cfg.dim, -1), host(phi), host(p_prev), host(act) != 0
+        assert np.all(uh[:, bot] == 0.0) and np.all(uh[0, top] == 0.0) and np.all(uh[1, top] == t * du)
+        if t > 0:
+            assert info["converged"] == 1
+            assert np.array_equal(ph[a], pold[a]) and np.all(ph <= pold + 1e-12)
+            Ft, Fb = np.array(info["reaction_top"]), np.array(info["reaction_bottom"])
+            assert np.abs(Ft + Fb).max() <= 1e-6 * abs(Ft[1])
+            pt = 2 * pold - host(p_prev2) if p_prev2 is not None else pold
+            E = op.energy(mesh, m, uh, pt) - op.energy(mesh, m, np.zeros_like(uh), pt)
+            W = t * du * Ft[1]
+            say("reaction", Ft[1], "2 E_el", 2 * E, "u_top F_top", W)
+            assert abs(W - 2 * E) <= 1e-6 * abs(W)
+        p_prev2, p_prev = (None, phi) if t == 0 else (p_prev, phi)
