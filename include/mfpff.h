@@ -120,18 +120,24 @@ typedef struct {
   int lanczos_steps_u, lanczos_steps_phi;
 } mfpff_level_desc;
 
-/* Build the level hierarchy, 1D tables and all device storage for a problem
- * (the mesh set-up of the solver).  `hip_stream` is a hipStream_t (NULL:
+/* Build the level hierarchy (the Q_k meshes of Section 3.1 and the multigrid levels of
+ * Section 3.3), 1D tables and all device storage for a problem (the mesh set-up of the solver).  `hip_stream` is a hipStream_t (NULL:
  * the default stream).  On success *out owns every device allocation.
  * MFPFF_ERR_ARG for an invalid description, including a level with 2^31 or
  * more dofs; MFPFF_ERR_OOM when device memory runs out. */
-mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx** out);
+mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream, mfpff_ctx** out);
 
 /* Release a context and everything it owns.  NULL is ignored. */
 void mfpff_destroy(mfpff_ctx* ctx);
 
 /* Message describing the last failure on this context ("" if none). */
 const char* mfpff_last_error(const mfpff_ctx* ctx);
+
+/* Number of nodes and of dofs ((dim+1) * n_nodes, component-blocked) of level `level`
+ * (0 = coarsest .. n_levels-1 = finest).  Host only: no device work, no synchronisation.
+ * MFPFF_ERR_ARG for a NULL argument or a level out of range (no message is stored, the
+ * context being read-only here). */
+mfpff_status mfpff_sizes(const mfpff_ctx* ctx, int level, size_t* n_nodes, size_t* n_dofs);
 
 /* Sizes and smoother data of one level (synchronises).  Before any
  * linearisation lambda_u = lambda_phi = 1 and the step counts are 0. */

@@ -111,11 +111,11 @@ class LevelDesc(ctypes.Structure):
 
 
 EXPORTS = [
-    "mfpff_create", "mfpff_destroy", "mfpff_last_error", "mfpff_level_info", "mfpff_set_linearization",
+    "mfpff_setup_mesh_levels", "mfpff_destroy", "mfpff_last_error", "mfpff_level_info", "mfpff_set_linearization",
     "mfpff_set_point",
     "mfpff_apply_jacobian", "mfpff_diagonal", "mfpff_smooth", "mfpff_transfer", "mfpff_coarse_solve",
     "mfpff_vcycle", "mfpff_gmres_solve", "mfpff_residual", "mfpff_residual_param_vjp", "mfpff_active_set",
-    "mfpff_newton_step", "mfpff_pdas_solve", "mfpff_element_matrices", "mfpff_load_step",
+    "mfpff_newton_step", "mfpff_pdas_solve", "mfpff_element_matrices", "mfpff_load_step", "mfpff_sizes",
 ]
 
 _lib = None
@@ -131,7 +131,7 @@ def load_library(path=LIB_PATH):
     lib = ctypes.CDLL(path)
     P, I, D, VP = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_void_p
     sig = {
-        "mfpff_create": ([ctypes.POINTER(Problem), VP, ctypes.POINTER(VP)], I),
+        "mfpff_setup_mesh_levels": ([ctypes.POINTER(Problem), VP, ctypes.POINTER(VP)], I),
         "mfpff_destroy": ([VP], None),
         "mfpff_last_error": ([VP], ctypes.c_char_p),
         "mfpff_level_info": ([VP, I, ctypes.POINTER(LevelDesc)], I),
@@ -151,6 +151,7 @@ def load_library(path=LIB_PATH):
         "mfpff_pdas_solve": ([VP, P, P, P, P, P, I, D, ctypes.POINTER(PdasInfo)], I),
         "mfpff_element_matrices": ([VP, I, P], I),
         "mfpff_load_step": ([VP, P, P, P, P, ctypes.POINTER(D), P, I, D, ctypes.POINTER(LoadInfo)], I),
+        "mfpff_sizes": ([VP, I, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], I),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -212,9 +213,9 @@ class Context:
         self.stream = s
         self.problem = problem
         h = ctypes.c_void_p()
-        st = self.lib.mfpff_create(ctypes.byref(problem), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
+        st = self.lib.mfpff_setup_mesh_levels(ctypes.byref(problem), ctypes.c_void_p(s.cuda_stream), ctypes.byref(h))
         if st != 0:
-            raise MfpffError(st, "mfpff_create failed")
+            raise MfpffError(st, "mfpff_setup_mesh_levels failed")
         self.h = h
         self.dim = problem.dim
         self.levels = [self.level_info(l) for l in range(problem.n_levels)]
@@ -240,6 +241,13 @@ class Context:
         return self.levels[level if level >= 0 else len(self.levels) + level]
 
     # ---- entry points
+    def sizes(self, level):
+        """(n_nodes, n_dofs) of a level (0 = coarsest), from the host."""
+        nn, nd = ctypes.c_size_t(), ctypes.c_size_t()
+        level = level % len(self.levels)
+        self._check(self.lib.mfpff_sizes(self.h, level, ctypes.byref(nn), ctypes.byref(nd)))
+        return nn.value, nd.value
+
     def level_info(self, level):
         d = LevelDesc()
         self._check(self.lib.mfpff_level_info(self.h, level, ctypes.byref(d)))

@@ -1000,7 +1000,7 @@ mfpff_status run(mfpff_ctx* c, const std::function<mfpff_status()>& fn) {
 
 extern "C" {
 
-mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx** out) {
+mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream, mfpff_ctx** out) {
   if (!prob || !out) return MFPFF_ERR_ARG;
   *out = nullptr;
   const mfpff_problem& p = *prob;
@@ -1136,7 +1136,7 @@ mfpff_status mfpff_create(const mfpff_problem* prob, void* hip_stream, mfpff_ctx
     return MFPFF_OK;
   });
   if (st != MFPFF_OK) {
-    fprintf(stderr, "mfpff_create: %s\n", c->err.c_str());
+    fprintf(stderr, "mfpff_setup_mesh_levels: %s\n", c->err.c_str());
     mfpff_destroy(c);
     return st;
   }
@@ -1194,6 +1194,13 @@ void mfpff_destroy(mfpff_ctx* c) {
 }
 
 const char* mfpff_last_error(const mfpff_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+mfpff_status mfpff_sizes(const mfpff_ctx* c, int level, size_t* n_nodes, size_t* n_dofs) {
+  if (!c || !n_nodes || !n_dofs || level < 0 || level > c->L) return MFPFF_ERR_ARG;
+  *n_nodes = (size_t)c->lv[level].nn;
+  *n_dofs = (size_t)c->lv[level].n;
+  return MFPFF_OK;
+}
 
 mfpff_status mfpff_level_info(mfpff_ctx* c, int level, mfpff_level_desc* out) {
   return run(c, [&]() {

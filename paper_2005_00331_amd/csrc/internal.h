@@ -8,7 +8,7 @@ namespace mfpff {
 constexpr int kMaxDeg = 4;
 constexpr int kThreads = 256;
 // Index arithmetic in the kernels divides in 32 bits (a 64-bit division by a runtime value costs
-// ~100 instructions on gfx950); mfpff_create rejects levels with 2^31 or more dofs.
+// ~100 instructions on gfx950); mfpff_setup_mesh_levels rejects levels with 2^31 or more dofs.
 __host__ __device__ __forceinline__ unsigned udiv(unsigned long long a, unsigned long long b) {
   return (unsigned)a / (unsigned)b;
 }

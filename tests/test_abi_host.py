@@ -27,9 +27,9 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = declared()
-    for n in ["mfpff_create", "mfpff_set_linearization", "mfpff_apply_jacobian", "mfpff_vcycle",
+    for n in ["mfpff_setup_mesh_levels", "mfpff_set_linearization", "mfpff_apply_jacobian", "mfpff_vcycle",
               "mfpff_gmres_solve", "mfpff_residual", "mfpff_residual_param_vjp", "mfpff_newton_step",
-              "mfpff_destroy", "mfpff_last_error"]:
+              "mfpff_destroy", "mfpff_last_error", "mfpff_sizes"]:
         assert n in names
 
 
@@ -53,12 +53,12 @@ def test_invalid_problems_rejected_without_device(lib):
                        ("split", 2)]:
         p = binding.make_problem(2, [(4, 1), (8, 1)], eps=0.25)
         setattr(p, field, bad)
-        assert lib.mfpff_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+        assert lib.mfpff_setup_mesh_levels(ctypes.byref(p), None, ctypes.byref(h)) == 1
     p = binding.make_problem(2, [(4, 1), (8, 2)], eps=0.25)       # neither an h- nor a p-step
-    assert lib.mfpff_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    assert lib.mfpff_setup_mesh_levels(ctypes.byref(p), None, ctypes.byref(h)) == 1
     p = binding.make_problem(2, [(8, 5)], eps=0.25)                # degree above 4
-    assert lib.mfpff_create(ctypes.byref(p), None, ctypes.byref(h)) == 1
-    assert lib.mfpff_create(None, None, ctypes.byref(h)) == 1
+    assert lib.mfpff_setup_mesh_levels(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    assert lib.mfpff_setup_mesh_levels(None, None, ctypes.byref(h)) == 1
     assert good.dim == 2
 
 
@@ -70,6 +70,8 @@ def test_null_context_paths(lib):
     L.mfpff_destroy(None)
     d = binding.LevelDesc()
     assert L.mfpff_level_info(None, 0, ctypes.byref(d)) == 1
+    nn, nd = ctypes.c_size_t(), ctypes.c_size_t()
+    assert L.mfpff_sizes(None, 0, ctypes.byref(nn), ctypes.byref(nd)) == 1
 
 
 def _c_struct_fields(name):

@@ -202,3 +202,23 @@ def test_smallest_meshes(dim, levels):
         xl = x[: lev.mesh.n_dofs]
         assert rel_err(host(ctx.apply_jacobian(l, dev(xl), op=OP_G)), lev.A @ xl) <= 1e-12
     assert rel_err(host(ctx.vcycle(dev(x))), H.vcycle(x)) <= 1e-10
+
+
+def test_sizes_match_the_level_descriptions():
+    """mfpff_sizes (host only) against mfpff_level_info and the mesh formula (k N + 1)^d nodes,
+    (d + 1) dofs per node, on an h- and p-coarsened hierarchy; out-of-range levels are rejected."""
+    import ctypes
+    from paper_2005_00331_amd import MfpffError
+    cfg = CONFIGS["C4"].with_(N=4, n_h_levels=2)
+    levels = level_list(cfg)
+    ctx = _ctx(cfg, levels)
+    say("sizes")
+    for l, (N, k) in enumerate(levels):
+        nn, nd = ctx.sizes(l)
+        d = ctx.level_info(l)
+        assert (nn, nd) == (d.n_nodes, d.n_dofs) == ((k * N + 1) ** 3, 4 * (k * N + 1) ** 3)
+    a, b = ctypes.c_size_t(), ctypes.c_size_t()
+    assert ctx.lib.mfpff_sizes(ctx.h, len(levels), ctypes.byref(a), ctypes.byref(b)) == 1
+    assert ctx.lib.mfpff_sizes(ctx.h, -1, ctypes.byref(a), ctypes.byref(b)) == 1
+    with pytest.raises(MfpffError):
+        ctx._check(ctx.lib.mfpff_sizes(ctx.h, 0, None, ctypes.byref(b)))
