@@ -65,8 +65,9 @@ typedef enum { MFPFF_F64 = 0, MFPFF_F32 = 1 } mfpff_prec;
  * E^+ = K/2 <tr e>_+^2 + mu dev e : dev e with K = lambda + 2 mu / dim.  MIEHE: spectral,
  * E^+ = lambda/2 <tr e>_+^2 + mu e^+ : e^+ with e^+ the positive part of the strain from its
  * eigensystem; the tangent differentiates e^+ in the eigenbasis (Section 3.5) with divided
- * differences, which equal Algorithm 2 on distinct eigenvalues. */
-typedef enum { MFPFF_SPLIT_AMOR = 0, MFPFF_SPLIT_MIEHE = 1 } mfpff_split;
+ * differences, which equal Algorithm 2 on distinct eigenvalues.  NONE: the isotropic model of
+ * Section 5 (no split): E^+ = lambda/2 tr(e)^2 + mu e : e, E^- = 0. */
+typedef enum { MFPFF_SPLIT_AMOR = 0, MFPFF_SPLIT_MIEHE = 1, MFPFF_SPLIT_NONE = 2 } mfpff_split;
 
 typedef enum {
   MFPFF_OP_G = 0,         /* y = G^ x */

@@ -71,6 +71,21 @@ def amor_split(grad_u, lam, mu):
     return dict(e=e, t=t, H=H, K=K, sig_p=sig_p, sig_m=sig_m, E_p=E_p, E_m=E_m)
 
 
+def isotropic_split(grad_u, lam, mu):
+    """The model without a split (the isotropic case of Section 5): the whole solid energy and Hooke's
+    stress are degraded, E^+ = E_s = lambda/2 tr(e)^2 + mu e:e, sigma^+ = lambda tr(e) I + 2 mu e,
+    E^- = 0, sigma^- = 0.  Same keys as amor_split, with H = 1 everywhere, so that dsigma gives
+    g(phi~) (lambda tr(de) I + 2 mu de)."""
+    d = grad_u.shape[-1]
+    e = sym(grad_u)
+    t = trace(e)
+    I = eye_like(e)
+    sig_p = lam * t[..., None, None] * I + 2.0 * mu * e
+    E_p = 0.5 * lam * t ** 2 + mu * np.einsum("...ij,...ij->...", e, e)
+    return dict(e=e, t=t, H=np.ones_like(t), K=lam + 2.0 * mu / d, sig_p=sig_p, sig_m=np.zeros_like(sig_p),
+                E_p=E_p, E_m=np.zeros_like(E_p))
+
+
 def dsigma(de, H, gt, K, mu):
     """Directional derivative of g(phi~) sigma^+ + sigma^- in strain direction de.
 

@@ -33,7 +33,7 @@ class Material:
     Gc: float
     eps: float
     kappa: float
-    split: str = "amor"   # "amor" (volumetric/deviatoric) or "miehe" (spectral)
+    split: str = "amor"   # "amor" (volumetric/deviatoric), "miehe" (spectral) or "none" (isotropic)
 
 
 def material_of(cfg, N=None) -> Material:
@@ -57,8 +57,8 @@ class CellData:
         self.phi = pl @ self.N.T                            # (nc, Q)
         self.grad_phi = np.einsum("qpa,np->nqa", self.gradN, pl)
         self.phi_t = phi_t[self.nodes] @ self.N.T
-        self.split = (mat.miehe_split(self.grad_u, m.lam, m.mu) if m.split == "miehe"
-                      else mat.amor_split(self.grad_u, m.lam, m.mu))
+        split = {"miehe": mat.miehe_split, "none": mat.isotropic_split}.get(m.split, mat.amor_split)
+        self.split = split(self.grad_u, m.lam, m.mu)
         self.gt = mat.g(self.phi_t, m.kappa)
         self.dg = mat.dg(self.phi, m.kappa)
         self.ddg = mat.ddg(self.phi, m.kappa)

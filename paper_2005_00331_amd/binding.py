@@ -16,7 +16,7 @@ MAX_LEVELS = 16
 
 F64, F32 = 0, 1
 OP_G, OP_GT, OP_BLOCKDIAG = 0, 1, 2
-SPLITS = {"amor": 0, "miehe": 1}   # mfpff_split
+SPLITS = {"amor": 0, "miehe": 1, "none": 2}   # mfpff_split
 OP_ACCUMULATE = 16
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_STATE", 3: "ERR_OOM", 4: "ERR_HIP", 5: "ERR_NOCONV", 6: "ERR_NUMERIC"}

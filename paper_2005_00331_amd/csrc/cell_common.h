@@ -162,7 +162,7 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
         for (int j = 0; j < DIM; ++j) e[i][j] = T(0.5) * (gu[i][j] + gu[j][i]);
         t += e[i][i];
       }
-      const bool H = t >= T(0);
+      const bool H = t >= T(0) || mp.split == SPLIT_NONE;
       const T tp = H ? t : T(0);
       T devdev = 0;
 #pragma unroll
@@ -326,7 +326,7 @@ __device__ const T* cell_compute(T* buf0, T* buf1, const SharedTables<K + 1, T>&
       t += e[i][i];
     }
     // tension/compression split of the trace: branch-free selects
-    const bool H = t >= T(0);
+    const bool H = t >= T(0) || mp.split == SPLIT_NONE;
     const T tp = H ? t : T(0);
     const T tm = H ? T(0) : t;
     T devdev = 0;

@@ -292,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void diag_kernel(CellArgs<T> a, const Tab
     T t = 0;
 #pragma unroll
     for (int i = 0; i < DIM; ++i) t += gu[i][i];
-    const bool H = t >= T(0);
+    const bool H = t >= T(0) || a.m.split == SPLIT_NONE;
     const T tp = H ? t : T(0);
     T devdev = 0;
 #pragma unroll

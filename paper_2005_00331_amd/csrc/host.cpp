@@ -1009,7 +1009,7 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
   if (p.cheb_degree < 1 || p.cheb_degree > 32 || p.lanczos_steps < 0 || p.lanczos_steps > 64) return MFPFF_ERR_ARG;
   if (p.restart < 1 || p.restart > 64 || p.max_iter < 0 || !(p.rtol >= 0.0)) return MFPFF_ERR_ARG;
   if (p.vcycle_prec != MFPFF_F64 && p.vcycle_prec != MFPFF_F32) return MFPFF_ERR_ARG;
-  if (p.split != MFPFF_SPLIT_AMOR && p.split != MFPFF_SPLIT_MIEHE) return MFPFF_ERR_ARG;
+  if (p.split != MFPFF_SPLIT_AMOR && p.split != MFPFF_SPLIT_MIEHE && p.split != MFPFF_SPLIT_NONE) return MFPFF_ERR_ARG;
   if (p.pdas_project != 0 && p.pdas_project != 1) return MFPFF_ERR_ARG;
   if (!(p.eps > 0.0) || !(p.kappa >= 0.0) || !(p.cheb_hi > p.cheb_lo) || !(p.cheb_lo > 0.0)) return MFPFF_ERR_ARG;
   for (int l = 0; l < p.n_levels; ++l) {

@@ -19,7 +19,9 @@
 
 namespace mfpff {
 
-enum SplitKind : int { SPLIT_AMOR = 0, SPLIT_MIEHE = 1 };
+// SPLIT_NONE: the isotropic model without a split (the whole energy degraded); it runs the
+// volumetric/deviatoric code with the tension branch taken at every point
+enum SplitKind : int { SPLIT_AMOR = 0, SPLIT_MIEHE = 1, SPLIT_NONE = 2 };
 
 // Voigt order of symmetric tensors: 2D (xx, yy, xy); 3D (xx, yy, zz, xy, xz, yz); strains in
 // engineering form (shear entries doubled) so that the tangent matrix is symmetric

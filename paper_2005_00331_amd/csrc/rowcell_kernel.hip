@@ -318,7 +318,7 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
     const T exx = gu00[q0] * ih, eyy = gu11[q0] * ih;
     const T exy = T(0.5) * (gu01[q0] + gu10[q0]) * ih;
     const T t = exx + eyy;
-    const bool H = t >= T(0);
+    const bool H = t >= T(0) || a.m.split == SPLIT_NONE;
     const T tp = H ? t : T(0);
     const T dxx = exx - T(0.5) * t, dyy = eyy - T(0.5) * t;
     const T Ep = T(0.5) * Kb * tp * tp + mu * (dxx * dxx + dyy * dyy + T(2) * exy * exy);

@@ -36,7 +36,7 @@ class Config:
     phi_mode: str = "smooth"  # "ones" (1 off the notch) or "smooth"
     u_mode: str = "smooth"    # "iid" (U[0,1e-3] per node) or "smooth"
     dirichlet: bool = True    # delta u = 0 on the two faces normal to the last axis
-    split: str = "amor"       # tension/compression split: "amor" (workloads) or "miehe" (spectral)
+    split: str = "amor"       # tension/compression split: "amor" (workloads), "miehe" (spectral), "none" (isotropic)
     pdas_project: bool = False  # Algorithm 1 as written (delta phi = 0 on A) or phi := phi_old on A first
     seed_index: int = 0
     lanczos_seed: int = 20050331

@@ -52,6 +52,11 @@ CASES = {
     "3d_q4_miehe": ("C4", [(2, 2), (2, 4), (4, 4)], dict(split="miehe")),
     "2d_q2_miehe_f32": ("C2", [(5, 2), (10, 2)], dict(vcycle_prec="f32", split="miehe")),
     "3d_q2_miehe_f32": ("C3", [(2, 2), (4, 2)], dict(vcycle_prec="f32", split="miehe")),
+    # isotropic model (no split)
+    "2d_q1_none": ("C1", [(6, 1), (12, 1)], dict(split="none")),
+    "2d_q2_none": ("C2", [(5, 1), (5, 2), (10, 2)], dict(split="none")),
+    "2d_q3_none": ("C2", [(3, 1), (3, 3), (6, 3)], dict(split="none")),
+    "3d_q2_none": ("C3", [(2, 1), (2, 2), (4, 2)], dict(vcycle_prec="f64", split="none")),
     "3d_q3_f32": ("C4", [(3, 1), (3, 3)], dict(vcycle_prec="f32")),
     "3d_q4_f32": ("C4", [(2, 1), (2, 2), (2, 4), (4, 4)], dict(vcycle_prec="f32")),
     "2d_q2_f32": ("C2", [(5, 2), (10, 2)], dict(vcycle_prec="f32")),

@@ -19,7 +19,8 @@ def _ctx(cfg, levels, **kw):
 
 
 @pytest.mark.parametrize("name,kw", [("C1", {}), ("C2", dict(N=10)), ("C5", dict(N=4)), ("C4", dict(N=3, k=3)),
-                                     ("C2", dict(N=10, split="miehe")), ("C5", dict(N=4, split="miehe"))])
+                                     ("C2", dict(N=10, split="miehe")), ("C5", dict(N=4, split="miehe")),
+                                     ("C2", dict(N=10, split="none")), ("C5", dict(N=4, split="none"))])
 def test_residual_and_param_vjp(name, kw):
     cfg = CONFIGS[name].with_(n_h_levels=1, p_coarse=(), **kw)
     inp = make_inputs(cfg, ("cotangent",))
