@@ -223,3 +223,33 @@ def test_load_step_argument_errors():
     free = _ctx(cfg, levels, dirichlet=False)
     with pytest.raises(MfpffError, match="dirichlet"):
         free.load_step(u, phi, prev, None, [0.0, 1e-5])
+
+
+def test_package_docstring_example():
+    """The load-stepping loop of the package docstring, on a small mesh: after the load-free
+    relaxation step every loaded step converges, the top reaction is upward and grows linearly with
+    the load at these small loads, and the phase field never exceeds its previous value (projected
+    update)."""
+    import torch
+    from paper_2005_00331_amd import Context, make_problem
+    from synth.fields import make_phi
+    levels = [(4, 2), (8, 2)]
+    cfg = CONFIGS["C2"].with_(N=8, n_h_levels=2, phi_mode="ones")
+    ctx = Context(make_problem(2, levels, eps=2 / 8, split="amor", pdas_project=True))
+    nn = ctx.n_nodes
+    u = torch.zeros(2 * nn, dtype=torch.float64, device="cuda")
+    phi0 = dev(make_phi(cfg))
+    say("docstring example")
+    phi_prev = phi0.clone()
+    ctx.load_step(u, phi_prev, phi0, None, [0.0, 0.0], raise_on_noconv=False)
+    phi_prev2 = None
+    loads = []
+    for t in range(1, 4):
+        phi = phi_prev.clone()
+        active, info = ctx.load_step(u, phi, phi_prev, phi_prev2, [0.0, t * 1e-5])
+        assert info["converged"] == 1
+        assert bool((phi <= phi_prev + 1e-12).all())
+        loads.append(info["reaction_top"][1])
+        phi_prev2, phi_prev = phi_prev, phi
+    assert 0 < loads[0] < loads[1] < loads[2]
+    assert abs(loads[1] - 2 * loads[0]) <= 1e-3 * loads[1] and abs(loads[2] - 3 * loads[0]) <= 1e-3 * loads[2]
