@@ -1465,7 +1465,8 @@ static mfpff_status linearise_solve_update(mfpff_ctx* c, double* u, double* phi,
 }
 
 // Algorithm 1 to its stopping test from (u, phi) with U^old = phi_old and phi~ = pt; fills
-// everything of *out but ms_total.  On return c->R holds the residual at the final iterate.
+// everything of *out but ms_total.  On return c->R holds the residual at the final iterate,
+// except after a failed linear solve (then it is the residual before that step's update).
 static mfpff_status pdas_loop(mfpff_ctx* c, double* u, double* phi, const double* phi_old, const double* pt,
                               uint8_t* active, int max_newton, double tol, mfpff_pdas_info* out) {
   Level& F = c->lv[c->L];
@@ -1593,7 +1594,9 @@ mfpff_status mfpff_load_step(mfpff_ctx* c, double* u, double* phi, const double*
     LAUNCHCHK();
     mfpff_load_info out{};
     const mfpff_status st = pdas_loop(c, u, phi, phi_prev, pt, active, max_newton, tol, &out.pdas);
-    // c->R holds the residual at the final iterate (the loop tests before it steps)
+    // reactions from the residual at the returned state (after a failed linear solve the loop's
+    // last residual belongs to the state before that step's update)
+    residual_into_R(c, u, phi, pt);
     k_face_reaction(c->react, c->R, F.g, c->s);
     LAUNCHCHK();
     double rh[6] = {0, 0, 0, 0, 0, 0};
