@@ -99,6 +99,29 @@ def test_newton_step_small():
     assert np.linalg.norm(dU - out["dU"]) <= 1e-5 * np.linalg.norm(out["dU"])
 
 
+def test_projected_newton_step_matches_oracle():
+    """One Newton step with the projected update from a state with phi below phi_old: the active
+    set, phi = phi_old on it, and the step on the free dofs against the oracle's."""
+    import torch
+    cfg = CONFIGS["C2"].with_(N=16, n_h_levels=3, pdas_project=True)
+    levels = level_list(cfg)
+    inp = make_inputs(cfg)
+    phi_old = inp["phi"] + np.random.default_rng(7).uniform(0.0, 0.02, inp["phi"].size)
+    out = newton.newton_step(cfg, levels, inp["u"], inp["phi"], phi_old, inp["phi_tilde"])
+    ctx = _ctx(cfg, levels)
+    u, phi = dev(inp["u"]), dev(inp["phi"])
+    say("projected newton step")
+    act, info = ctx.newton_step(u, phi, dev(phi_old), dev(inp["phi_tilde"]))
+    act = host(act)
+    ind = out["indicator"]
+    tie = np.abs(ind) <= 1e-12 * np.abs(ind).max()
+    assert not tie.any() and np.array_equal(act, out["active"]) and act.sum() > 100
+    a = act != 0
+    assert np.array_equal(host(phi)[a], phi_old[a])
+    assert info["converged"] == 1
+    assert rel_err(host(u).ravel(), out["u"].ravel()) <= 1e-5 and rel_err(host(phi), out["phi"]) <= 1e-5
+
+
 @pytest.mark.parametrize("name,kw", [("C1", {}), ("C2", dict(N=16, n_h_levels=3)),
                                      ("C2", dict(N=16, n_h_levels=3, split="miehe"))])
 def test_active_set_loop_matches_oracle(name, kw):
