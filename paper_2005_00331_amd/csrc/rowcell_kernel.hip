@@ -73,7 +73,12 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   const int N = g.N;
   const long long M = g.M, nn = g.n_nodes;
   const int ntx = (N + kRowOwn - 1) / kRowOwn;
-  const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  // XCD-aware tile order: hardware block b runs on XCD b % 8, and each XCD takes a contiguous
+  // range of tiles, so tiles that share halo nodes share that XCD's L2 (the cached coefficients
+  // stay indexed by the hardware block, the same in the writing and the reading launch)
+  const unsigned G = gridDim.x, bb = blockIdx.x, xcd = bb % 8, per = G / 8, rem = G % 8;
+  const int lt = (int)(xcd * per + min(xcd, rem) + bb / 8);
+  const int tx = lt % ntx, ty = lt / ntx;
   const int cx0 = tx * kRowOwn, cy0 = ty * kRowOwn;
   const int cx1 = min(cx0 + kRowOwn, N), cy1 = min(cy0 + kRowOwn, N);
   const int cx = cx0 - 1 + li, cy = cy0 - 1 + lj;

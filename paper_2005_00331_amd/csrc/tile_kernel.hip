@@ -47,7 +47,11 @@ __global__ __launch_bounds__(kThreads) void tile_kernel_2d(CellArgs<T> a, Epilog
   const int N = g.N;
   const long long M = g.M, nn = g.n_nodes;
   const int ntx = (N + TT - 1) / TT;
-  const int tx = blockIdx.x % ntx, ty = blockIdx.x / ntx;
+  // XCD-aware tile order: hardware block b runs on XCD b % 8, and each XCD takes a contiguous range
+  // of tiles, so tiles that share halo nodes share that XCD's L2
+  const unsigned G = gridDim.x, bb = blockIdx.x, xcd = bb % 8, per = G / 8, rem = G % 8;
+  const int lt = (int)(xcd * per + min(xcd, rem) + bb / 8);
+  const int tx = lt % ntx, ty = lt / ntx;
   const int cx0 = tx * TT, cy0 = ty * TT;
   const int cx1 = min(cx0 + TT, N), cy1 = min(cy0 + TT, N);
   const int ccx0 = max(cx0 - 1, 0), ccy0 = max(cy0 - 1, 0);
