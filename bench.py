@@ -352,6 +352,9 @@ def main():
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D runs (C3 solves, C4 products)")
     ap.add_argument("--spmv", action="store_true",
                     help="instead: matrix-free product against the assembled CSR product (rocSPARSE) at p = 1..4")
+    ap.add_argument("--load-steps", action="store_true",
+                    help="instead: the C2 load steps (relaxation step, then three loaded steps) with both "
+                         "active-set updates, printed as one record")
     ap.add_argument("--autograd", action="store_true",
                     help="instead: time the C5 residual forward and backward (autograd) and print that record")
     ap.add_argument("--apply-only", action="store_true",
@@ -369,6 +372,17 @@ def main():
         return
     if args.autograd:
         print(json.dumps(time_autograd(CONFIGS["C5"])), flush=True)
+        return
+    if args.load_steps:
+        from paper_2005_00331_amd import Context, problem_from
+        from synth import level_list
+        cfg = CONFIGS["C2"]
+        rec = {}
+        for name, project in (("as_written", False), ("projected", True)):
+            ctx = Context(problem_from(cfg.with_(pdas_project=project), level_list(cfg)))
+            rec[name] = load_steps_detail(ctx, cfg)
+            ctx.close()
+        print(json.dumps(rec), flush=True)
         return
     cfg = CONFIGS[args.workload]
     print(f"[bench] workload {cfg.name}: {cfg.dim}D N={cfg.N} Q{cfg.k}, {cfg.n_dofs} dofs", file=sys.stderr, flush=True)
