@@ -155,6 +155,8 @@ LOAD_CASES = [
     ("C2", dict(N=16, n_h_levels=3), "amor", 2e-4, True),
     ("C2", dict(N=8, n_h_levels=2), "miehe", 5e-4, True),
     ("C3", dict(N=4, n_h_levels=2), "amor", 5e-4, True),
+    ("C3", dict(N=4, n_h_levels=2), "miehe", 5e-4, True),
+    ("C2", dict(N=8, n_h_levels=2), "none", 5e-4, True),
 ]
 
 
