@@ -26,7 +26,8 @@ def sample_nodes(cfg, n_random, seed):
 
 
 @pytest.mark.parametrize("name,n_random,split", [("C2", 40, "amor"), ("C3", 24, "amor"), ("C4", 8, "amor"),
-                                                 ("C5", 24, "amor"), ("C2", 24, "miehe"), ("C3", 12, "miehe")])
+                                                 ("C5", 24, "amor"), ("C2", 24, "miehe"), ("C3", 12, "miehe"),
+                                                 ("C2", 24, "none"), ("C3", 12, "none")])
 def test_fullsize_sampled_rows(name, n_random, split):
     from paper_2005_00331_amd import OP_G, OP_GT, Context, problem_from
     cfg = CONFIGS[name].with_(split=split)

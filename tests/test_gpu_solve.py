@@ -55,7 +55,9 @@ def test_active_set_matches_oracle_rule():
                                           ("C3", dict(N=4, n_h_levels=2), "f64"),
                                           ("C3", dict(N=4, n_h_levels=2), "f32"),
                                           ("C2", dict(N=16, n_h_levels=3, split="miehe"), "f64"),
-                                          ("C3", dict(N=4, n_h_levels=2, split="miehe"), "f32")])
+                                          ("C3", dict(N=4, n_h_levels=2, split="miehe"), "f32"),
+                                          ("C2", dict(N=16, n_h_levels=3, split="none"), "f64"),
+                                          ("C3", dict(N=4, n_h_levels=2, split="none"), "f32")])
 def test_fgmres_solve(name, kw, prec):
     cfg = CONFIGS[name].with_(**kw)
     levels = level_list(cfg)
