@@ -97,9 +97,18 @@ def test_autograd_fullsize_c5():
     _autograd_fd(cfg, 1e-8, 5e-3)
 
 
-def test_transposed_product_matches_assembled_transpose():
+@pytest.mark.parametrize("split", ["none", "miehe"])
+def test_autograd_reduced_size_other_splits(split):
+    # the isotropic model has no branch: full directions are exact; the spectral split has
+    # eigenvalue branches, so only phi-only directions (R is linear in phi at fixed u) are exact
+    cfg = CONFIGS["C5"].with_(N=6, split=split)
+    _param_fd(cfg, *_autograd_fd(cfg, 1e-6, 1e-6, phi_only=(split == "miehe")))
+
+
+@pytest.mark.parametrize("split", ["amor", "miehe", "none"])
+def test_transposed_product_matches_assembled_transpose(split):
     from paper_2005_00331_amd import OP_GT
-    cfg = CONFIGS["C5"].with_(N=5)
+    cfg = CONFIGS["C5"].with_(N=5, split=split)
     inp = make_inputs(cfg)
     mesh = fe.Mesh(cfg.dim, cfg.N, cfg.k)
     G = op.assemble_jacobian(mesh, op.material_of(cfg), inp["u"], inp["phi"], inp["phi_tilde"])
