@@ -253,3 +253,111 @@ def test_projected_active_set_loop_reaches_the_kkt_point():
     a, b = outs
     assert np.abs(a["phi"] - b["phi"]).max() <= 1e-8
     assert np.linalg.norm(a["u"] - b["u"]) <= 1e-8 * np.linalg.norm(a["u"])
+
+
+# ------------------------------------------------------------- V-cycle as composed (Section 3.3)
+def _cheb_block_matrix(lev, lam, s, lo_f, hi_f):
+    """Dense linear map r -> diag(C_u, C_phi) r from the closed form of the Jacobi-scaled Chebyshev
+    polynomial (not from the recurrence): with X = D^-1/2 A_bb D^-1/2 = Q diag(mu) Q^T,
+    C_b = D^-1/2 Q diag((1 - T_s((theta - mu)/delta) / T_s(theta/delta)) / mu) Q^T D^-1/2."""
+    A = lev.A.toarray()
+    n, nu = A.shape[0], lev.nu
+    C = np.zeros((n, n))
+    T = np.polynomial.chebyshev.Chebyshev.basis(s)
+    for sl, lm in ((slice(0, nu), lam[0]), (slice(nu, n), lam[1])):
+        Abb = A[sl, sl]
+        dh = 1.0 / np.sqrt(lev.D[sl])
+        X = dh[:, None] * Abb * dh[None, :]
+        mu, Q = np.linalg.eigh(0.5 * (X + X.T))
+        lo, hi = lo_f * lm, hi_f * lm
+        th, de = 0.5 * (hi + lo), 0.5 * (hi - lo)
+        f = (1.0 - T((th - mu) / de) / T(th / de)) / mu
+        C[sl, sl] = dh[:, None] * (Q * f) @ Q.T * dh[None, :]
+    return C
+
+
+def _vcycle_error_operator(H, l):
+    """E_l = (I - C_l G_l)(I - P_l B_{l-1} P_l^T G_l)(I - C_l G_l) with B_{l-1} = (I - E_{l-1}) G_{l-1}^-1
+    and B_0 = G_0^-1 (the exact coarse solve): the textbook error propagation of a V-cycle with one
+    pre- and one post-smoothing step, returned together with B_l."""
+    lev = H.levels[l]
+    A = lev.A.toarray()
+    n = A.shape[0]
+    if l == 0:
+        B = np.linalg.inv(A)
+        return np.zeros((n, n)), B
+    _, Bc = _vcycle_error_operator(H, l - 1)
+    P = H.P[l].toarray()
+    C = _cheb_block_matrix(lev, H.lam[l], H.cfg.cheb_degree, H.cfg.cheb_lo, H.cfg.cheb_hi)
+    I = np.eye(n)
+    S = I - C @ A
+    E = S @ (I - P @ Bc @ P.T @ A) @ S
+    return E, (I - E) @ np.linalg.inv(A)
+
+
+def _vcycle_columns(H, vc):
+    A = H.levels[-1].A
+    n = A.shape[0]
+    I = np.eye(n)
+    return np.column_stack([I[:, j] - vc(A @ I[:, j]) for j in range(n)])
+
+
+class _NoPostSmoothing(mg.Hierarchy):
+    # planted mistake: the post-smoothing step is dropped
+    def vcycle(self, b, l=None):
+        l = self.L if l is None else l
+        lev = self.levels[l]
+        if l == 0:
+            return self.coarse.solve(b)
+        x = mg.chebyshev_block(lev, self.lam[l], b, self.cfg.cheb_degree, self.cfg.cheb_lo, self.cfg.cheb_hi)
+        r = b - lev.A @ x
+        return x + self.P[l] @ self.vcycle(self.P[l].T @ r, l - 1)
+
+
+class _BlockResidual(mg.Hierarchy):
+    # planted mistake: the coarse-correction residual uses diag(G_uu, G_phiphi) instead of G
+    def vcycle(self, b, l=None):
+        l = self.L if l is None else l
+        lev = self.levels[l]
+        if l == 0:
+            return self.coarse.solve(b)
+        s, lo, hi = self.cfg.cheb_degree, self.cfg.cheb_lo, self.cfg.cheb_hi
+        x = mg.chebyshev_block(lev, self.lam[l], b, s, lo, hi)
+        r = b - lev.Ablk @ x
+        x = x + self.P[l] @ self.vcycle(self.P[l].T @ r, l - 1)
+        r = b - lev.A @ x
+        return x + mg.chebyshev_block(lev, self.lam[l], r, s, lo, hi)
+
+
+VCYCLE_PIN_CASES = {
+    # the 2D Q1 workload at full size (32x32, two levels), notch and ~10% active set
+    "c1": ("C1", {}, None),
+    # 2D Q2, three h-levels (2x2 .. 8x8), smooth phi with the notch, ~5% active set
+    "q2_three_levels": ("C2", dict(N=8, n_h_levels=3), None),
+    # 2D Q2 with a p-step: 4x4 Q1 -> 4x4 Q2 -> 8x8 Q2
+    "q2_pstep": ("C2", dict(N=8, n_h_levels=2, p_coarse=(1,)), None),
+    # 3D Q1, two levels (2^3 -> 4^3)
+    "3d_q1": ("C3", dict(N=4, k=1, n_h_levels=2, vcycle_prec="f64"), None),
+}
+
+
+@pytest.mark.parametrize("case", list(VCYCLE_PIN_CASES))
+def test_vcycle_equals_its_error_propagation_operator(case):
+    """The oracle's V-cycle, column by column, against E_l composed densely from its factors: the
+    Chebyshev smoother from its closed form, the masked transfers, the exact coarse inverse.  Two
+    planted mistakes (no post-smoothing; the block-diagonal operator in the coarse-correction
+    residual) must fail the same comparison."""
+    name, kw, _ = VCYCLE_PIN_CASES[case]
+    cfg = CONFIGS[name].with_(**kw)
+    inp = make_inputs(cfg)
+    lv = level_list(cfg)
+    H = mg.Hierarchy(cfg, lv, inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
+    E, _ = _vcycle_error_operator(H, H.L)
+    got = _vcycle_columns(H, H.vcycle)
+    scale = np.abs(E).max()
+    assert np.abs(got - E).max() <= 1e-12 * max(scale, 1.0)
+    if case in ("q2_three_levels", "3d_q1"):
+        for bad in (_NoPostSmoothing, _BlockResidual):
+            Hb = bad(cfg, lv, inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
+            wrong = _vcycle_columns(Hb, Hb.vcycle)
+            assert np.abs(wrong - E).max() > 1e-3 * max(scale, 1.0)
