@@ -148,21 +148,27 @@ def constrain(G, pvec):
     return (Pm @ G @ Pm + sp.diags(1.0 - pvec)).tocsr()
 
 
+def cell_residuals(mesh, m: Material, u, phi, phi_t, cells):
+    """Element residual vectors of eq. (residual) for the given cells: (nc, (d+1)P) in local
+    (component, node) order, and the (nc, P) node ids.  The assembled residual is their sum."""
+    tb = TensorBasis(mesh.dim, mesh.k)
+    d = mesh.dim
+    cd = CellData(mesh, tb, m, u, phi, phi_t, cells)
+    s = cd.split
+    stress = cd.gt[..., None, None] * s["sig_p"] + s["sig_m"]               # (nc, Q, d, d)
+    Ru = np.einsum("q,nqij,qcpij->ncp", cd.JxW, stress, cd.Eb)              # (nc, d, P)
+    Rp = (np.einsum("q,nq,qp->np", cd.JxW, cd.dg * s["E_p"] - m.Gc * (1.0 - cd.phi) / m.eps, cd.N)
+          + m.Gc * m.eps * np.einsum("q,nqa,qpa->np", cd.JxW, cd.grad_phi, cd.gradN))
+    nc = len(cells)
+    return np.concatenate([Ru.reshape(nc, d * mesh.P), Rp], axis=1), cd.nodes
+
+
 def residual(mesh, m: Material, u, phi, phi_t):
     """Assembled residual vector of eq. (residual), unconstrained."""
-    tb = TensorBasis(mesh.dim, mesh.k)
-    d, P, nn = mesh.dim, mesh.P, mesh.n_nodes
     R = np.zeros(mesh.n_dofs)
     for cells in _chunks(mesh.n_cells, 4 * _chunk_size(mesh)):
-        cd = CellData(mesh, tb, m, u, phi, phi_t, cells)
-        s = cd.split
-        stress = cd.gt[..., None, None] * s["sig_p"] + s["sig_m"]               # (nc, Q, d, d)
-        Ru = np.einsum("q,nqij,qcpij->ncp", cd.JxW, stress, cd.Eb)              # (nc, d, P)
-        Rp = (np.einsum("q,nq,qp->np", cd.JxW, cd.dg * s["E_p"] - m.Gc * (1.0 - cd.phi) / m.eps, cd.N)
-              + m.Gc * m.eps * np.einsum("q,nqa,qpa->np", cd.JxW, cd.grad_phi, cd.gradN))
-        for c in range(d):
-            R[c * nn:(c + 1) * nn] += np.bincount(cd.nodes.ravel(), Ru[:, c, :].ravel(), minlength=nn)
-        R[d * nn:] += np.bincount(cd.nodes.ravel(), Rp.ravel(), minlength=nn)
+        Re, nodes = cell_residuals(mesh, m, u, phi, phi_t, cells)
+        R += np.bincount(local_dofs(mesh, nodes).ravel(), Re.ravel(), minlength=mesh.n_dofs)
     return R
 
 
@@ -242,17 +248,8 @@ def residual_rows(mesh, m: Material, u, phi, phi_t, nodes):
     """Rows of the residual at the given nodes from the touching cells only."""
     nodes = np.asarray(nodes)
     cells = mesh.cells_of_nodes(nodes)
-    tb = TensorBasis(mesh.dim, mesh.k)
     d, nn = mesh.dim, mesh.n_nodes
-    R = np.zeros(mesh.n_dofs)
-    cd = CellData(mesh, tb, m, u, phi, phi_t, cells)
-    s = cd.split
-    stress = cd.gt[..., None, None] * s["sig_p"] + s["sig_m"]
-    Ru = np.einsum("q,nqij,qcpij->ncp", cd.JxW, stress, cd.Eb)
-    Rp = (np.einsum("q,nq,qp->np", cd.JxW, cd.dg * s["E_p"] - m.Gc * (1.0 - cd.phi) / m.eps, cd.N)
-          + m.Gc * m.eps * np.einsum("q,nqa,qpa->np", cd.JxW, cd.grad_phi, cd.gradN))
-    for c in range(d):
-        np.add.at(R, c * nn + cd.nodes.ravel(), Ru[:, c, :].ravel())
-    np.add.at(R, d * nn + cd.nodes.ravel(), Rp.ravel())
+    Re, cn = cell_residuals(mesh, m, u, phi, phi_t, cells)
+    R = np.bincount(local_dofs(mesh, cn).ravel(), Re.ravel(), minlength=mesh.n_dofs)
     rows = np.stack([c * nn + nodes for c in range(d + 1)])
     return R[rows]

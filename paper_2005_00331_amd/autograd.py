@@ -5,8 +5,13 @@ replaces phi in the degradation of the displacement equation, Section
 3.2).  Backward, written by hand: the transposed Jacobian of eq. (G)
 applied to the cotangent (unconstrained, since the residual itself has no
 constraints) and the two parameter cotangents <v, dR/dGc>, <v, dR/deps>.
-The context must be created without Dirichlet rows; the backward sets its
-point with an empty active set, so that its operator is the plain Jacobian.
+The context must be created without Dirichlet rows (dirichlet = 0): the
+forward raises otherwise, since the product of such a context has identity
+rows and columns at the Dirichlet dofs and would give a wrong u gradient.
+The backward sets the context's point with an empty active set, so that its
+operator is the plain Jacobian; this drops the context's linearisation, and
+a V-cycle or GMRES solve on it afterwards needs set_linearization again (the
+library reports MFPFF_ERR_STATE until then).
 """
 import torch
 
@@ -19,6 +24,9 @@ class ResidualFn(torch.autograd.Function):
         """u: (dim*n_nodes,), phi, phi_tilde: (n_nodes,), Gc/eps: 0-d tensors that
         must equal the values the solver was created with."""
         p = solver.problem
+        if p.dirichlet:
+            raise ValueError("the residual's backward needs a context created with dirichlet = 0 "
+                             "(a Dirichlet context's transposed product has identity rows at the fixed dofs)")
         if abs(float(Gc) - p.Gc) > 0 or abs(float(eps) - p.eps) > 0:
             raise ValueError("Gc and eps must match the solver's problem description")
         R = solver.residual(u.detach(), phi.detach(), phi_tilde.detach())

@@ -85,16 +85,77 @@ def test_autograd_reduced_size_exact():
     _param_fd(cfg, *_autograd_fd(cfg, 1e-6, 1e-6, count_kinks=True))
 
 
+def _fullsize_gradient_and_differences(cfg, hstep):
+    """Backward of <v, R> at the workload state, and per direction the central difference of
+    <v, R> (GPU residuals) and <G^T v, d>."""
+    from paper_2005_00331_amd.autograd import residual
+    inp = make_inputs(cfg, ("cotangent", "directions"))
+    ctx = _ctx(cfg, [(cfg.N, cfg.k)])
+    nn = cfg.n_nodes
+    u = dev(inp["u"]).requires_grad_(True)
+    phi = dev(inp["phi"]).requires_grad_(True)
+    Gc = torch.tensor(cfg.Gc, dtype=torch.float64)
+    eps = torch.tensor(cfg.eps, dtype=torch.float64)
+    pt = dev(inp["phi_tilde"])
+    v = dev(inp["cotangent"])
+    (residual(u, phi, Gc, eps, pt, ctx) * v).sum().backward()
+    g = torch.cat([u.grad, phi.grad]).cpu().numpy()
+    U = np.concatenate([inp["u"].ravel(), inp["phi"]])
+    fd, ad = [], []
+    for dvec in inp["directions"]:
+        Up, Um = U + hstep * dvec, U - hstep * dvec
+        Rp = ctx.residual(dev(Up[: cfg.dim * nn]), dev(Up[cfg.dim * nn:]), pt)
+        Rm = ctx.residual(dev(Um[: cfg.dim * nn]), dev(Um[cfg.dim * nn:]), pt)
+        fd.append(float(((Rp - Rm) * v).sum()) / (2 * hstep))
+        ad.append(float(g @ dvec))
+    ctx.close()
+    return inp, U, fd, ad
+
+
 def test_autograd_fullsize_c5():
     # 48^3 Q2 (3,650,692 dofs).
     # phi-only directions leave tr e unchanged and R is linear in phi: exact up to rounding.
     cfg = CONFIGS["C5"]
     _param_fd(cfg, *_autograd_fd(cfg, 1e-6, 1e-8, phi_only=True), eps_tol=1e-6)
-    # Full directions: <v, G d> is a random-sign sum over ~3e6 quadrature points (it grows
-    # like sqrt(n)) while each point whose tension/compression branch flips between
-    # U +- h d adds an O(1) term, so the gap scales with h (7e-2 at h = 1e-6, 8e-4 at
-    # h = 1e-8).  Bound at h = 1e-8; the exactness is checked at 6^3 with no flips.
-    _autograd_fd(cfg, 1e-8, 5e-3)
+
+
+def test_autograd_fullsize_c5_full_directions_crossings_excluded():
+    """32 full directions at h = 1e-6 (1e-3 N(0,1) on u, N(0,1) on phi).  Every quadrature point
+    whose branch (sign of tr e) changes between U +- h d is counted; the oracle's share of those
+    points' cells is taken out of both the difference and the tangent; what remains must agree
+    to 1e-8.  A point that crosses makes the difference an average of two tangents, an O(1) term
+    against a random-sign sum over ~3e6 points, hence the separate bookkeeping."""
+    import fdcheck
+    cfg = CONFIGS["C5"]
+    h = 1e-6
+    inp, U, fd, ad = _fullsize_gradient_and_differences(cfg, h)
+    mesh = fe.Mesh(cfg.dim, cfg.N, cfg.k)
+    res = fdcheck.excluded_gaps(mesh, op.material_of(cfg), U, inp["phi_tilde"], inp["cotangent"],
+                                inp["directions"], h, fd, ad)
+    for j, (npts, ncells, full, rest) in enumerate(res):
+        say("C5 direction", j, "crossing points", npts, "cells", ncells, "gap", f"{full:.2e}",
+            "gap without crossing cells", f"{rest:.2e}")
+    say("C5 crossing points in total", sum(r[0] for r in res), "worst gap", max(r[2] for r in res),
+        "worst gap without crossing cells", max(r[3] for r in res))
+    assert max(r[3] for r in res) <= 1e-8
+    # secondary: a step 100x smaller leaves few crossings, and the raw gap is already small
+    inp, U, fd, ad = _fullsize_gradient_and_differences(cfg, 1e-8)
+    assert max(abs(f - a) / abs(a) for f, a in zip(fd, ad)) <= 5e-3
+
+
+def test_autograd_rejects_a_dirichlet_context():
+    # a context with Dirichlet rows (the default of the workloads) would give identity rows in
+    # the transposed product, so the u gradient would be wrong there: the forward refuses it
+    from paper_2005_00331_amd.autograd import residual
+    cfg = CONFIGS["C5"].with_(N=3, dirichlet=True)
+    inp = make_inputs(cfg)
+    ctx = _ctx(cfg, [(cfg.N, cfg.k)])
+    u = dev(inp["u"]).requires_grad_(True)
+    Gc = torch.tensor(cfg.Gc, dtype=torch.float64)
+    eps = torch.tensor(cfg.eps, dtype=torch.float64)
+    with pytest.raises(ValueError, match="dirichlet"):
+        residual(u, dev(inp["phi"]), Gc, eps, dev(inp["phi_tilde"]), ctx)
+    ctx.close()
 
 
 @pytest.mark.parametrize("split", ["none", "miehe"])

@@ -305,3 +305,43 @@ def test_parameter_vjp_against_differences(dim, N, k):
     m0 = op.Material(MAT.lam, MAT.mu, MAT.Gc, MAT.eps - he, MAT.kappa)
     fd = v @ (op.residual(mesh, m1, u, phi, phit) - op.residual(mesh, m0, u, phi, phit)) / (2 * he)
     assert abs(fd - deps) <= 1e-7 * abs(deps)
+
+
+def test_fd_gap_with_branch_crossing_cells_excluded():
+    """The crossing-cell exclusion used by the full-size autograd check, run on the oracle itself:
+    with a step large enough that many points change branch, the central difference misses the
+    tangent by far more than rounding, and taking the crossing cells out of both sides brings the
+    gap down to rounding.  A step so small that no point crosses changes nothing."""
+    import fdcheck
+    from synth import CONFIGS, make_inputs
+    Mesh = fe.Mesh
+    cfg = CONFIGS["C5"].with_(N=6)
+    inp = make_inputs(cfg, ("cotangent", "directions"))
+    mesh = Mesh(cfg.dim, cfg.N, cfg.k)
+    m = op.material_of(cfg)
+    d, nn = cfg.dim, cfg.n_nodes
+    U = np.concatenate([inp["u"].ravel(), inp["phi"]])
+    pt, v = inp["phi_tilde"], inp["cotangent"]
+    G = op.assemble_jacobian(mesh, m, inp["u"], inp["phi"], pt)
+    gT = G.T @ v
+    # displacement-only directions: on a fixed branch R is then at most quadratic along the line,
+    # so the central difference is exact up to rounding at any step
+    dirs = inp["directions"][:6].copy()
+    dirs[:, d * nn:] = 0.0
+
+    def full_sums(h):
+        fd, ad = [], []
+        for dv in dirs:
+            Rp = op.residual(mesh, m, (U + h * dv)[: d * nn].reshape(d, nn), (U + h * dv)[d * nn:], pt)
+            Rm = op.residual(mesh, m, (U - h * dv)[: d * nn].reshape(d, nn), (U - h * dv)[d * nn:], pt)
+            fd.append(float(v @ (Rp - Rm)) / (2 * h))
+            ad.append(float(gT @ dv))
+        return fd, ad
+
+    h = 2e-3   # moves u by ~2e-6 per node: about 100 of the 5,832 points change branch
+    res = fdcheck.excluded_gaps(mesh, m, U, pt, v, dirs, h, *full_sums(h))
+    assert all(r[0] > 0 and r[1] < mesh.n_cells // 2 for r in res)
+    assert min(r[2] for r in res) > 1e-3                       # crossings spoil the difference
+    assert max(r[3] for r in res) <= 1e-11                     # and nothing else does
+    res = fdcheck.excluded_gaps(mesh, m, U, pt, v, dirs, 1e-6, *full_sums(1e-6))
+    assert all(r[0] == 0 and r[3] == r[2] and r[2] <= 1e-8 for r in res)
