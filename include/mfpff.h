@@ -205,6 +205,20 @@ mfpff_status mfpff_residual_param_vjp(mfpff_ctx* ctx, const double* u, const dou
                                       const double* phi_tilde, const double* v,
                                       double* dGc_host, double* deps_host);
 
+/* The same parameter cotangents as mfpff_residual_param_vjp, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the per-block partial sums live in a static device array of the library (2 MiB per
+ * device, held until the process ends) instead of the context's buffer.  This call performs no
+ * hipMalloc, hipFree or other allocation.  Limit: the finest level may need at most 131072
+ * partial-sum blocks of the cotangent kernel (about 1.2 M cells in 3D Q2, 3.7 M in 2D Q2); larger
+ * contexts get MFPFF_ERR_ARG with a message.  Every call on one device shares that array, so calls
+ * that overlap on one device (several host threads, or contexts on different streams whose work
+ * overlaps) race; calls queued on one stream do not.  Results are bit-identical to
+ * mfpff_residual_param_vjp.  Synchronises. */
+mfpff_status mfpff_residual_param_vjp_noalloc(mfpff_ctx* ctx, const double* u, const double* phi,
+                                              const double* phi_tilde, const double* v,
+                                              double* dGc_host, double* deps_host);
+
 /* Active set of Algorithm 1 from the residual R (as returned by
  * mfpff_residual): active_i = [ -(M_L^-1 R_phi)_i + c (phi - phi_old)_i > 0 ],
  * M_L the row-sum-lumped phi mass matrix. */

@@ -115,6 +115,7 @@ EXPORTS = [
     "mfpff_set_point",
     "mfpff_apply_jacobian", "mfpff_diagonal", "mfpff_smooth", "mfpff_transfer", "mfpff_coarse_solve",
     "mfpff_vcycle", "mfpff_gmres_solve", "mfpff_residual", "mfpff_residual_param_vjp", "mfpff_active_set",
+    "mfpff_residual_param_vjp_noalloc",
     "mfpff_newton_step", "mfpff_pdas_solve", "mfpff_element_matrices", "mfpff_load_step", "mfpff_sizes",
 ]
 
@@ -146,6 +147,7 @@ def load_library(path=LIB_PATH):
         "mfpff_gmres_solve": ([VP, P, P, ctypes.POINTER(SolveInfo)], I),
         "mfpff_residual": ([VP, P, P, P, P], I),
         "mfpff_residual_param_vjp": ([VP, P, P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)], I),
+        "mfpff_residual_param_vjp_noalloc": ([VP, P, P, P, P, ctypes.POINTER(D), ctypes.POINTER(D)], I),
         "mfpff_active_set": ([VP, P, P, P, P], I),
         "mfpff_newton_step": ([VP, P, P, P, P, P, ctypes.POINTER(SolveInfo)], I),
         "mfpff_pdas_solve": ([VP, P, P, P, P, P, I, D, ctypes.POINTER(PdasInfo)], I),
@@ -334,6 +336,15 @@ class Context:
         nn = self.n_nodes
         a, b = ctypes.c_double(), ctypes.c_double()
         self._check(self.lib.mfpff_residual_param_vjp(
+            self.h, _ptr(u, torch.float64, self.dim * nn, "u"), _ptr(phi, torch.float64, nn, "phi"),
+            _ptr(phi_tilde, torch.float64, nn, "phi_tilde"), _ptr(v, torch.float64, self.n_dofs, "v"),
+            ctypes.byref(a), ctypes.byref(b)))
+        return a.value, b.value
+
+    def residual_param_vjp_noalloc(self, u, phi, phi_tilde, v):
+        nn = self.n_nodes
+        a, b = ctypes.c_double(), ctypes.c_double()
+        self._check(self.lib.mfpff_residual_param_vjp_noalloc(
             self.h, _ptr(u, torch.float64, self.dim * nn, "u"), _ptr(phi, torch.float64, nn, "phi"),
             _ptr(phi_tilde, torch.float64, nn, "phi_tilde"), _ptr(v, torch.float64, self.n_dofs, "v"),
             ctypes.byref(a), ctypes.byref(b)))

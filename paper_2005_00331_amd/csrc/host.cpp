@@ -14,6 +14,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <functional>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -90,6 +91,7 @@ enum { WB = 0, WX = 1, WR = 2, WT = 3, WD = 4, WZ = 5, WZ2 = 6, NW = 7 };
 struct mfpff_ctx {
   mfpff_problem prob{};
   hipStream_t s = nullptr;
+  int device = -1;  // HIP device current at set-up (the stream's device)
   int dim = 2, L = 0;  // L = index of the finest level
   bool f32 = false;
   std::vector<Level> lv;
@@ -979,6 +981,40 @@ void set_linearization(mfpff_ctx* c, const double* u, const double* phi, const d
 
 }  // namespace
 
+// Static scratch of mfpff_residual_param_vjp_noalloc: the per-block partial sums of the
+// parameter-cotangent kernel (two doubles per block, at most kNoAllocMaxBlocks blocks) followed by
+// the two totals.  Every device the library runs on holds one copy (2 MiB) until the process
+// ends.  Host code never passes the name `scratch` to a kernel or a copy (on the host it is a
+// stand-in, not a device address): mfpff_setup_mesh_levels resolves its device address once per
+// device with hipGetSymbolAddress, and the entry point uses that address.
+namespace {
+constexpr long long kNoAllocMaxBlocks = 1LL << 17;
+constexpr int kNoAllocMaxDevices = 64;
+}  // namespace
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxBlocks + 2];
+namespace {
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kNoAllocMaxDevices] = {};
+
+// Resolve the device address of `scratch` on device `dev` (the current device) once.
+hipError_t noalloc_scratch_init(int dev) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return hipSuccess;  // the no-alloc entry point then refuses
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[dev]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_scratch_dev[dev] = static_cast<double*>(ptr);
+  return hipSuccess;
+}
+
+double* noalloc_scratch(int dev) {
+  if (dev < 0 || dev >= kNoAllocMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_dev[dev];
+}
+}  // namespace
+
 namespace {
 mfpff_status run(mfpff_ctx* c, const std::function<mfpff_status()>& fn) {
   if (!c) return MFPFF_ERR_ARG;
@@ -995,6 +1031,35 @@ mfpff_status run(mfpff_ctx* c, const std::function<mfpff_status()>& fn) {
     c->err = e.what();
     return MFPFF_ERR_ARG;
   }
+}
+}  // namespace
+
+namespace {
+// Parameter cotangents <v, dR/dGc>, <v, dR/deps> of eq. (residual) on the finest level: the cell
+// kernel writes two partial sums per block into `partials`, one workgroup adds them in a fixed
+// order into out2[0..1], and the pair is copied to the host (synchronises the stream).
+void param_vjp(mfpff_ctx* c, const double* u, const double* phi, const double* phi_tilde, const double* v,
+               double* partials, double* out2d, double* dGc_host, double* deps_host) {
+  require_ptr(phi, "phi");
+  require_ptr(v, "v");
+  require_ptr(dGc_host, "dGc_host");
+  require_ptr(deps_host, "deps_host");
+  Level& F = c->lv[c->L];
+  CellArgs<double> a = cell_args<double>(c, F, F.lin, v, nullptr, 1.0);
+  a.u = u;
+  a.phi = phi;
+  a.phit = phi_tilde;
+  a.mask = nullptr;
+  a.partials = partials;
+  HIPCHK(launch_cell<double>(MODE_PVJP, a, c->tab64[F.g.k], c->s));
+  const long long nb = cell_blocks(F.g, MODE_PVJP);
+  k_sum_pvjp(out2d, partials, (int)nb, c->s);
+  LAUNCHCHK();
+  double out2[2];
+  HIPCHK(hipMemcpyAsync(out2, out2d, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  *dGc_host = out2[0];
+  *deps_host = out2[1];
 }
 }  // namespace
 
@@ -1030,6 +1095,8 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
   if (const char* ev = getenv("MFPFF_NO_GRAPH")) c->graph_ok = !(ev[0] == '1');
   mfpff_status st = run(c, [&]() -> mfpff_status {
     const int d = c->dim;
+    HIPCHK(hipGetDevice(&c->device));
+    HIPCHK(noalloc_scratch_init(c->device));
     c->lv.resize(p.n_levels);
     size_t elem_bytes = 0;
     for (int l = 0; l < p.n_levels; ++l) {
@@ -1375,26 +1442,23 @@ mfpff_status mfpff_residual(mfpff_ctx* c, const double* u, const double* phi, co
 mfpff_status mfpff_residual_param_vjp(mfpff_ctx* c, const double* u, const double* phi, const double* phi_tilde,
                                       const double* v, double* dGc_host, double* deps_host) {
   return run(c, [&]() {
-    require_ptr(phi, "phi");
-    require_ptr(v, "v");
-    require_ptr(dGc_host, "dGc_host");
-    require_ptr(deps_host, "deps_host");
-    Level& F = c->lv[c->L];
-    CellArgs<double> a = cell_args<double>(c, F, F.lin, v, nullptr, 1.0);
-    a.u = u;
-    a.phi = phi;
-    a.phit = phi_tilde;
-    a.mask = nullptr;
-    a.partials = c->pvjp_part;
-    HIPCHK(launch_cell<double>(MODE_PVJP, a, c->tab64[F.g.k], c->s));
-    const long long nb = cell_blocks(F.g, MODE_PVJP);
-    k_sum_pvjp(c->pvjp_out, c->pvjp_part, (int)nb, c->s);
-    LAUNCHCHK();
-    double out2[2];
-    HIPCHK(hipMemcpyAsync(out2, c->pvjp_out, 2 * sizeof(double), hipMemcpyDeviceToHost, c->s));
-    HIPCHK(hipStreamSynchronize(c->s));
-    *dGc_host = out2[0];
-    *deps_host = out2[1];
+    param_vjp(c, u, phi, phi_tilde, v, c->pvjp_part, c->pvjp_out, dGc_host, deps_host);
+    return MFPFF_OK;
+  });
+}
+
+mfpff_status mfpff_residual_param_vjp_noalloc(mfpff_ctx* c, const double* u, const double* phi,
+                                              const double* phi_tilde, const double* v, double* dGc_host,
+                                              double* deps_host) {
+  return run(c, [&]() {
+    const long long nb = cell_blocks(c->lv[c->L].g, MODE_PVJP);
+    if (nb > kNoAllocMaxBlocks)
+      throw StatusError{MFPFF_ERR_ARG, "mfpff_residual_param_vjp_noalloc: the finest level needs " +
+                                           std::to_string(nb) + " partial-sum blocks, the static scratch holds " +
+                                           std::to_string(kNoAllocMaxBlocks)};
+    double* sp = noalloc_scratch(c->device);
+    if (!sp) throw StatusError{MFPFF_ERR_STATE, "mfpff_residual_param_vjp_noalloc: no static scratch on this device"};
+    param_vjp(c, u, phi, phi_tilde, v, sp, sp + 2 * kNoAllocMaxBlocks, dGc_host, deps_host);
     return MFPFF_OK;
   });
 }
