@@ -25,6 +25,7 @@ sys.path.insert(0, ROOT)
 METRIC = "Jacobian-apply DoFs/s and GMG-GMRES time per Newton step, FP64 vs mixed"
 HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "rowcell_apply_c2_f64_counters.txt")
+N_ROTATE = 8   # contexts the HBM-resident product timing rotates through
 KERNEL_SRC = os.path.join(ROOT, "paper_2005_00331_amd", "csrc", "rowcell_kernel.hip")
 
 
@@ -139,6 +140,76 @@ def time_apply_cold(ctx, reps=10):
     return sorted(times)[len(times) // 2]
 
 
+def product_contexts(cfg, n_ctx):
+    """n_ctx single-level contexts of the workload's finest level at its seeded point (no active
+    set), each with its own trial and result vector: together several times the 256 MB
+    last-level cache, so that rotating through them makes every product read its operands from
+    HBM."""
+    import torch
+    from paper_2005_00331_amd import Context, problem_from
+    from synth import make_inputs
+    inp = make_inputs(cfg)
+
+    def d(a):
+        return torch.from_numpy(a.ravel().copy()).cuda()
+    st = {k: d(v) for k, v in inp.items()}
+    out = []
+    for _ in range(n_ctx):
+        ctx = Context(problem_from(cfg, [(cfg.N, cfg.k)]))
+        zeros = torch.zeros(ctx.n_nodes, dtype=torch.uint8, device="cuda")
+        ctx.set_point(st["u"], st["phi"], st["phi_old"], zeros, st["phi_tilde"])
+        x = torch.randn(ctx.n_dofs, dtype=torch.float64, device="cuda")
+        out.append((ctx, x, torch.zeros_like(x)))
+    return out
+
+
+def time_apply_rotating(ctxs, rounds=10):
+    """Average duration of one finest-level FP64 product over rounds x len(ctxs) back-to-back
+    launches that rotate through independent contexts (HIP events on the library's stream, around
+    the whole sequence): each launch finds its operands evicted from the last-level cache by the
+    others, so this is the HBM-resident figure without per-launch event overhead."""
+    import torch
+    from paper_2005_00331_amd import F64, OP_G
+    for ctx, x, y in ctxs:
+        ctx.apply_jacobian(-1, x, y, prec=F64, op=OP_G)
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    for _ in range(rounds):
+        for ctx, x, y in ctxs:
+            ctx.apply_jacobian(-1, x, y, prec=F64, op=OP_G)
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / (rounds * len(ctxs))
+
+
+def host_cpu():
+    """Host processor model (from /proc/cpuinfo) and os.cpu_count()."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return model, os.cpu_count()
+
+
+def bytes_per_iteration(dim, k, cheb_degree, restart, vcycle_bytes_scale=1.0):
+    """Algorithmic HBM bytes per dof of one FGMRES(m) iteration, the lower bound a solve is held
+    to: one product (x, y, u, phi, phi~, mask), a V-cycle of 2 s smoothing products plus about
+    32 B/dof of Chebyshev vector traffic per product on every level (level sizes summed
+    geometrically: 4/3 in 2D, 8/7 in 3D), about 20 B/dof of transfers, and CGS2 over on average
+    m/2 basis vectors (two passes reading the basis, about 32 B/dof per vector).
+    vcycle_bytes_scale = 0.5 for an FP32 V-cycle."""
+    apply_b = ((dim + 1) * 2 + dim + 2) * 8 / (dim + 1)
+    lsum = 4 / 3 if dim == 2 else 8 / 7
+    vc = (2 * cheb_degree * (apply_b + 32) * lsum + 20) * vcycle_bytes_scale
+    return apply_b + vc + 32 * restart / 2
+
+
 def time_autograd(cfg, reps=5, warmup=2):
     """The residual as a torch.autograd.Function (forward R(u, phi; Gc, eps), hand-written backward:
     the point's coefficient cache, the transposed product and the two parameter cotangents) on the
@@ -181,17 +252,19 @@ def time_autograd(cfg, reps=5, warmup=2):
     return out
 
 
-def time_solve(cfg, prec):
-    """One linear solve of the workload's seeded right-hand side: set_linearization, then
-    FGMRES to the workload's rtol (after one untimed warm-up solve). FP64 GMRES either way;
-    prec selects the V-cycle precision."""
+def time_solve(cfg, prec, warm=True):
+    """One linear solve of the workload's seeded right-hand side at its seeded state and active
+    set: set_linearization, then FGMRES to the workload's rtol (after one untimed warm-up solve
+    when warm). FP64 GMRES either way; prec selects the V-cycle precision. The time is set against
+    the HBM lower bound iterations x bytes_per_iteration x n_dofs / 8 TB/s."""
     import torch
     from synth import make_inputs
     ctx, levels, state = build_context(cfg, prec=prec)
     rhs = torch.from_numpy(make_inputs(cfg, ("rhs",))["rhs"]).cuda()
     args = (state["u"], state["phi"], state["phi_old"], state["active"], state["phi_tilde"])
-    ctx.set_linearization(*args)
-    ctx.gmres_solve(rhs, raise_on_noconv=False)
+    if warm:
+        ctx.set_linearization(*args)
+        ctx.gmres_solve(rhs, raise_on_noconv=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     ctx.set_linearization(*args)
@@ -201,8 +274,13 @@ def time_solve(cfg, prec):
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ctx.close()
+    b_it = bytes_per_iteration(cfg.dim, cfg.k, cfg.cheb_degree, cfg.restart, 0.5 if prec == "f32" else 1.0)
+    bound_ms = st["iterations"] * b_it * cfg.n_dofs / (HBM_PEAK_GBS * 1e9) * 1e3
     return {"ms_setup": (t1 - t0) * 1e3, "ms_solve": (t2 - t1) * 1e3, "ms_total": (t2 - t0) * 1e3,
-            "gmres_iterations": st["iterations"], "converged": st["converged"], "rel_residual": st["rel_residual"]}
+            "gmres_iterations": st["iterations"], "converged": st["converged"], "rel_residual": st["rel_residual"],
+            "active_fraction": float(state["active"].float().mean()),
+            "bytes_per_dof_per_iteration": b_it, "hbm_bound_ms": bound_ms,
+            "solve_frac_of_hbm_bound": bound_ms / ((t2 - t1) * 1e3)}
 
 
 def contraction_flops_3d(cfg):
@@ -220,11 +298,16 @@ def time_products_3d(cfg):
     ctx.set_linearization(state["u"], state["phi"], state["phi_old"], state["active"], state["phi_tilde"])
     fl = contraction_flops_3d(cfg)
     res = {"workload": f"{cfg.name}: 3D {cfg.N}^3 cells Q{cfg.k}, {cfg.n_dofs} dofs, finest-level product "
-                       f"(line kernel + node gather)", "contraction_gflop": fl / 1e9}
+                       f"(line kernel + node gather)", "contraction_gflop": fl / 1e9,
+           "note": "operands, coefficient cache and element buffer exceed the 256 MB last-level cache, so "
+                   "back-to-back launches read from HBM; frac_of_peak counts only the contraction flops"}
     for f32, tag, peak in ((False, "f64", 78.6), (True, "f32", 157.3)):
         t = time_apply(ctx, f32=f32)
+        byts = algorithmic_bytes_per_apply(cfg.dim, ctx.n_nodes, 4 if f32 else 8)
         res[tag] = {"apply_us": t * 1e6, "dofs_per_s": ctx.n_dofs / t, "contraction_tflops": fl / t / 1e12,
-                    "frac_of_peak": fl / t / 1e12 / peak, "peak_tflops": peak}
+                    "frac_of_peak": fl / t / 1e12 / peak, "peak_tflops": peak,
+                    "algorithmic_bytes": byts, "hbm_GBps": byts / t / 1e9,
+                    "hbm_frac": byts / t / 1e9 / HBM_PEAK_GBS}
     ctx.close()
     return res
 
@@ -302,6 +385,7 @@ def cpu_baseline(cfg_name):
         blas_threads = max([i.get("num_threads", 1) for i in threadpool_info()] or [1])
     except Exception:
         blas_threads = os.cpu_count()
+    model, ncpu = host_cpu()
     base = CONFIGS[cfg_name]
     cfg = base.with_(N=base.N // 2, n_h_levels=base.n_h_levels - 1)   # same coarse grid, 1/4 of the dofs
     inp = make_inputs(cfg)
@@ -313,7 +397,8 @@ def cpu_baseline(cfg_name):
                        f"{cfg.N}x{cfg.N} Q{cfg.k}, {cfg.n_dofs} dofs, {t:.1f} s, {out['info']['iterations']} GMRES "
                        f"iterations; sparse products single-threaded, dense coarse factorisation on "
                        f"{blas_threads} BLAS threads"),
-            "seconds": t, "iterations": out["info"]["iterations"]}
+            "seconds": t, "iterations": out["info"]["iterations"], "host_model": model, "host_cpu_count": ncpu,
+            "blas_threads": int(blas_threads), "sparse_threads": 1}
 
 
 def load_steps_detail(ctx, cfg, n_steps=3, du=1e-5):
@@ -357,6 +442,9 @@ def main():
                          "active-set updates, printed as one record")
     ap.add_argument("--autograd", action="store_true",
                     help="instead: time the C5 residual forward and backward (autograd) and print that record")
+    ap.add_argument("--solve", metavar="WORKLOAD",
+                    help="instead: one linear solve (set-up plus FGMRES) of the named workload's seeded system with "
+                         "the FP64 and the FP32 V-cycle, printed as one record")
     ap.add_argument("--apply-only", action="store_true",
                     help="only time the finest-level cell kernel (for kernel-trace and counter runs)")
     args = ap.parse_args()
@@ -365,13 +453,22 @@ def main():
               f"(the multi-GPU sharding is a design in DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import torch
-    from synth import CONFIGS
+    from synth import CONFIGS, level_list
     torch.cuda.set_device(0)
     if args.spmv:
         spmv_study()
         return
     if args.autograd:
         print(json.dumps(time_autograd(CONFIGS["C5"])), flush=True)
+        return
+    if args.solve:
+        cfg = CONFIGS[args.solve].with_(max_iter=5000)
+        rec = {"workload": f"{cfg.name}: {cfg.dim}D {cfg.N}^{cfg.dim} cells Q{cfg.k}, {cfg.n_dofs} dofs, levels "
+                           f"{level_list(cfg)}, seeded state, active set and right-hand side, rtol {cfg.rtol}"}
+        for prec in ("f64", "f32"):
+            rec[prec + "_vcycle"] = time_solve(cfg, prec, warm=False)
+            print(f"[bench] {cfg.name} solve, {prec} V-cycle: {rec[prec + '_vcycle']}", file=sys.stderr, flush=True)
+        print(json.dumps(rec), flush=True)
         return
     if args.load_steps:
         from paper_2005_00331_amd import Context, problem_from
@@ -395,24 +492,38 @@ def main():
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        t_apply = time_apply(ctx)
-        byts = algorithmic_bytes_per_apply(cfg.dim, ctx.n_nodes, 8)
-        print(json.dumps({"apply_us": t_apply * 1e6, "GB/s": byts / t_apply / 1e9, "bytes_per_launch": byts}), flush=True)
         ctx.close()
+        ctxs = product_contexts(cfg, N_ROTATE)
+        t_apply = time_apply_rotating(ctxs)
+        byts = algorithmic_bytes_per_apply(cfg.dim, ctxs[0][0].n_nodes, 8)
+        print(json.dumps({"apply_us": t_apply * 1e6, "GB/s": byts / t_apply / 1e9, "bytes_per_launch": byts,
+                          "timing": f"rotating through {N_ROTATE} contexts"}), flush=True)
+        for c, _, _ in ctxs:
+            c.close()
         return
     sec, infos = time_newton(ctx, state, args.steps, args.warmup)
     print(f"[bench] newton step {sec * 1e3:.2f} ms, iters {[i['iterations'] for i in infos]}", file=sys.stderr,
           flush=True)
-    t_apply = time_apply(ctx)
+    t_warm = time_apply(ctx)
     elem = 8
     byts = algorithmic_bytes_per_apply(cfg.dim, ctx.n_nodes, elem)
-    achieved = byts / t_apply / 1e9
-    print(f"[bench] finest cell kernel {t_apply * 1e6:.1f} us, {achieved:.0f} GB/s", file=sys.stderr, flush=True)
+    print(f"[bench] finest cell kernel, cache-resident {t_warm * 1e6:.1f} us", file=sys.stderr, flush=True)
     t_cold = time_apply_cold(ctx)
     print(f"[bench] finest cell kernel after a cache flush {t_cold * 1e6:.1f} us", file=sys.stderr, flush=True)
+    ctxs = product_contexts(cfg, N_ROTATE)
+    t_apply = time_apply_rotating(ctxs)
+    for c, _, _ in ctxs:
+        c.close()
+    del ctxs
+    torch.cuda.empty_cache()
+    achieved = byts / t_apply / 1e9
+    print(f"[bench] finest cell kernel from HBM (rotating) {t_apply * 1e6:.1f} us, {achieved:.0f} GB/s", file=sys.stderr,
+          flush=True)
     detail = {
         "apply_dofs_per_s": ctx.n_dofs / t_apply,
         "apply_us": t_apply * 1e6,
+        "apply_us_cache_resident": t_warm * 1e6,
+        "apply_GBps_cache_resident": byts / t_warm / 1e9,
         "apply_us_after_cache_flush": t_cold * 1e6,
         "apply_GBps_after_cache_flush": byts / t_cold / 1e9,
         "gmres_iterations": infos[-1]["iterations"],
@@ -420,7 +531,14 @@ def main():
         "ms_solve": infos[-1]["ms_solve"],
         "rel_residual": infos[-1]["rel_residual"],
         "n_active": infos[-1]["n_active"],
+        "active_fraction": infos[-1]["n_active"] / ctx.n_nodes,
     }
+    # the linear solve alone at the workload's seeded active set (about 5 % of the phi-dofs), both
+    # V-cycle precisions: the Newton step's own active set comes from the rule of Algorithm 1
+    for prec in ("f64", "f32"):
+        detail[f"linear_solve_seeded_active_{prec}_vcycle"] = time_solve(cfg, prec)
+        print(f"[bench] {cfg.name} linear solve at the seeded active set, {prec} V-cycle: "
+              f"{detail[f'linear_solve_seeded_active_{prec}_vcycle']}", file=sys.stderr, flush=True)
     if not args.no_mixed:
         mctx, _, mstate = build_context(cfg, prec="f32")
         msec, minfos = time_newton(mctx, mstate, 2, 1)
@@ -464,12 +582,22 @@ def main():
     if not args.no_3d:
         c3 = CONFIGS["C3"]
         res = {"workload": f"C3: 3D {c3.N}^3 cells Q{c3.k}, {c3.n_dofs} dofs, seeded random right-hand side, "
-                           f"Chebyshev degree {c3.cheb_degree}, {c3.n_h_levels}-level GMG-GMRES({c3.restart}), "
-                           f"rtol {c3.rtol}"}
+                           f"seeded 5 % active set, Chebyshev degree {c3.cheb_degree}, {c3.n_h_levels}-level "
+                           f"GMG-GMRES({c3.restart}), rtol {c3.rtol}"}
         for prec in ("f64", "f32"):
             res[prec + "_vcycle"] = time_solve(c3, prec)
-            print(f"[bench] C3 solve, {prec} V-cycle: {res[prec + '_vcycle']}", file=sys.stderr, flush=True)
+            print(f"[bench] C3 solve, phi = 1 off the notch, {prec} V-cycle: {res[prec + '_vcycle']}", file=sys.stderr,
+                  flush=True)
+        # the smooth seeded phi field in [0, 1] off the notch (the survey's input recipe for C2-C5)
+        c3s = c3.with_(phi_mode="smooth", max_iter=2000)
+        for prec in ("f64", "f32"):
+            res["smooth_phi_" + prec + "_vcycle"] = time_solve(c3s, prec, warm=False)
+            print(f"[bench] C3 solve, smooth phi, {prec} V-cycle: {res['smooth_phi_' + prec + '_vcycle']}",
+                  file=sys.stderr, flush=True)
         detail["c3_solve"] = res
+        c3p = time_products_3d(c3)
+        print(f"[bench] C3 products: {c3p}", file=sys.stderr, flush=True)
+        detail["c3_products"] = c3p
         c4 = time_products_3d(CONFIGS["C4"])
         print(f"[bench] C4 products: {c4}", file=sys.stderr, flush=True)
         detail["c4_products"] = c4
@@ -491,16 +619,19 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{cfg.name}: {cfg.dim}D {cfg.N}^{cfg.dim} cells Q{cfg.k}, {cfg.n_dofs} dofs, one "
                                f"semi-smooth Newton step, {len(levels)}-level GMG-GMRES({cfg.restart}), rtol {cfg.rtol}",
-                   "levels": levels, "n_dofs": ctx.n_dofs, "vcycle_prec": cfg.vcycle_prec},
+                   "levels": levels, "n_dofs": ctx.n_dofs, "vcycle_prec": cfg.vcycle_prec,
+                   "active_fraction": detail["active_fraction"],
+                   "active_set": "Algorithm 1's rule at the seeded state"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(cfg),
                      "kernel": ((f"rowcell_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>" if cfg.k <= 2 else
                                  f"tile_kernel_2d<{cfg.k},double,APPLY,EPI_APPLY>") if cfg.dim == 2 else
                                 f"linecell_kernel<{cfg.k},double,APPLY> + gather3d_kernel") + " on the finest level",
                      "bytes_per_launch": byts,
-                     "timing": "50 back-to-back launches on the same operands, which stay in the 256 MB "
-                               "last-level cache; detail.apply_us_after_cache_flush is the median after a "
-                               "1 GiB flush"},
+                     "timing": f"{N_ROTATE} x 10 back-to-back launches rotating through {N_ROTATE} independent "
+                               "contexts (about 53 MB of operands each, together above the 256 MB last-level "
+                               "cache), HIP events around the sequence; detail.apply_us_cache_resident is the "
+                               "same product repeated on one context"},
         "detail": detail,
     }
     ctx.close()
