@@ -122,29 +122,33 @@ typedef struct {
 } mfpff_level_desc;
 
 /* Build the level hierarchy (the Q_k meshes of Section 3.1 and the multigrid levels of
- * Section 3.3), 1D tables and all device storage for a problem (the mesh set-up of the solver).  `hip_stream` is a hipStream_t (NULL:
- * the default stream).  On success *out owns every device allocation.
- * MFPFF_ERR_ARG for an invalid description, including a level with 2^31 or
+ * Section 3.3), 1D tables and all device storage for a problem (the mesh set-up of the solver).
+ * `prob` is read during the call only; `hip_stream` is a hipStream_t (NULL: the default stream)
+ * on the current device, which every later call of the context uses.  On success *out owns every
+ * device allocation.  MFPFF_ERR_ARG for an invalid description, including a level with 2^31 or
  * more dofs; MFPFF_ERR_OOM when device memory runs out. */
 mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream, mfpff_ctx** out);
 
-/* Release a context and everything it owns.  NULL is ignored. */
+/* Release a context and everything it owns.  NULL is ignored.  (Library housekeeping; no passage
+ * of the paper.) */
 void mfpff_destroy(mfpff_ctx* ctx);
 
-/* Message describing the last failure on this context ("" if none). */
+/* Message describing the last failure on this context ("" if none).  (Library housekeeping.) */
 const char* mfpff_last_error(const mfpff_ctx* ctx);
 
 /* Number of nodes and of dofs ((dim+1) * n_nodes, component-blocked) of level `level`
- * (0 = coarsest .. n_levels-1 = finest).  Host only: no device work, no synchronisation.
+ * (0 = coarsest .. n_levels-1 = finest): the Q_k nodal dofs of Section 3.1 on that level.  Host only: no device work, no synchronisation.
  * MFPFF_ERR_ARG for a NULL argument or a level out of range (no message is stored, the
  * context being read-only here). */
 mfpff_status mfpff_sizes(const mfpff_ctx* ctx, int level, size_t* n_nodes, size_t* n_dofs);
 
-/* Sizes and smoother data of one level (synchronises).  Before any
- * linearisation lambda_u = lambda_phi = 1 and the step counts are 0. */
+/* Sizes and smoother data of one level (synchronises): the largest-eigenvalue estimates that set
+ * the Chebyshev interval of Section 3.3.  Before any linearisation lambda_u = lambda_phi = 1 and
+ * the step counts are 0.  MFPFF_ERR_ARG for a NULL argument or a level out of range. */
 mfpff_status mfpff_level_info(mfpff_ctx* ctx, int level, mfpff_level_desc* out);
 
-/* Freeze the linearisation point of eq. (G): u (dim*n_nodes), phi, phi_old
+/* Freeze the linearisation point of eq. (G) and set up the multigrid preconditioner of
+ * Section 3.3 (Algorithm 1 calls this once per Newton step): u (dim*n_nodes), phi, phi_old
  * and phi_tilde (n_nodes each; phi_tilde NULL means phi_old) and the active
  * set (n_nodes bytes) on the finest level.  Injects fields and masks to every
  * coarser level, builds the diagonals, the Chebyshev intervals (CG-Lanczos
@@ -156,7 +160,7 @@ mfpff_status mfpff_set_linearization(mfpff_ctx* ctx, const double* u, const doub
                                      const double* phi_old, const uint8_t* active,
                                      const double* phi_tilde);
 
-/* Product-only linearisation: the same fields, active set and Dirichlet rows
+/* Product-only linearisation of eq. (G): the same fields, active set and Dirichlet rows
  * as mfpff_set_linearization, injected to every level, but no diagonals,
  * smoother intervals or coarse factorisation.  Enough for
  * mfpff_apply_jacobian (any op) on every level; mfpff_vcycle, mfpff_smooth,
@@ -166,41 +170,62 @@ mfpff_status mfpff_set_linearization(mfpff_ctx* ctx, const double* u, const doub
 mfpff_status mfpff_set_point(mfpff_ctx* ctx, const double* u, const double* phi, const double* phi_old,
                              const uint8_t* active, const double* phi_tilde);
 
-/* y = op(G^_level) x on one level.  x, y: n_dofs of that level, FP64 or FP32
- * per `prec` (FP32 uses the FP32 copy of the level data).  x and y must not
- * alias.  `op` is an mfpff_op value, optionally or-ed with MFPFF_OP_ACCUMULATE. */
+/* y = op(G^_level) x on one level: the product with the Jacobian of eq. (G), constrained as in
+ * Algorithm 1 (fixed dofs get identity rows and columns), evaluated cell by cell by sum
+ * factorisation without a stored matrix (Section 3.4).  x, y: n_dofs of that level (device),
+ * FP64 or FP32 per `prec` (FP32 uses the FP32 copy of the level data).  x and y must not alias.
+ * `op` is an mfpff_op value (G^, its transpose, or the block-diagonal operator of the smoother),
+ * optionally or-ed with MFPFF_OP_ACCUMULATE.  MFPFF_ERR_STATE before a point is set,
+ * MFPFF_ERR_ARG for a level out of range, a NULL pointer, or an unknown op or precision. */
 mfpff_status mfpff_apply_jacobian(mfpff_ctx* ctx, int level, const void* x, void* y, int prec, int op);
 
-/* Diagonal of G^_level (1 at fixed dofs), FP64, n_dofs of the level. */
+/* Diagonal of G^_level (1 at fixed dofs), FP64, n_dofs of the level (device): the Jacobi scaling
+ * of the Chebyshev-Jacobi smoother of Section 3.3, which needs only the diagonal and the product.
+ * MFPFF_ERR_STATE before mfpff_set_linearization. */
 mfpff_status mfpff_diagonal(mfpff_ctx* ctx, int level, double* diag);
 
-/* z = diag(C_u, C_phi) r on level >= 1: the block Chebyshev-Jacobi polynomial
- * of the smoother applied to r from a zero start (FP64). */
+/* z = diag(C_u, C_phi) r on level >= 1: the block-diagonal Chebyshev-Jacobi smoother of
+ * Section 3.3 (one polynomial per block on [0.24, 1.2] lambda_max), applied to r from a zero start
+ * (FP64, device vectors of the level's n_dofs).  MFPFF_ERR_STATE before mfpff_set_linearization,
+ * MFPFF_ERR_ARG for level 0 or out of range. */
 mfpff_status mfpff_smooth(mfpff_ctx* ctx, int level, const double* r, double* z);
 
-/* Masked transfer between level-1 and level (level >= 1): direction 0 is
- * prolongation (in: level-1 vector, out: level vector), 1 is restriction
- * (the transpose).  FP64. */
+/* Masked transfer between level-1 and level (level >= 1) of the geometric multigrid of
+ * Section 3.3: direction 0 is prolongation (in: level-1 vector, out: level vector), 1 is
+ * restriction (the transpose).  The interpolation is the Kronecker product of the 1D Lagrange
+ * interpolation matrices, per component, with fixed dofs zeroed on both sides.  FP64, device
+ * vectors.  MFPFF_ERR_STATE before a point is set, MFPFF_ERR_ARG for a bad level or direction. */
 mfpff_status mfpff_transfer(mfpff_ctx* ctx, int level, int direction, const double* in, double* out);
 
-/* Exact FP64 solve with the coarsest level operator (block lower triangular). */
+/* Exact FP64 solve with the coarsest level operator, using the block lower-triangular structure
+ * of eq. (G) that Section 3.3 points out: x_u = G^_uu^-1 r_u, x_phi = G^_phiphi^-1 (r_phi -
+ * G^_phiu x_u) (the paper runs Chebyshev over the whole spectrum there instead).  r, x: device,
+ * n_dofs of level 0.  MFPFF_ERR_STATE before mfpff_set_linearization. */
 mfpff_status mfpff_coarse_solve(mfpff_ctx* ctx, const double* r, double* x);
 
-/* One V-cycle of the monolithic multigrid on the finest level: z = V(r). */
+/* One V-cycle of the monolithic geometric multigrid of Section 3.3 on the finest level:
+ * z = V(r), pre- and post-smoothing on every level, exact coarse solve.  r, z: device, finest
+ * n_dofs, FP64 (the levels run in the problem's V-cycle precision, with casts at the ends).
+ * MFPFF_ERR_STATE before mfpff_set_linearization. */
 mfpff_status mfpff_vcycle(mfpff_ctx* ctx, const double* r, double* z);
 
-/* Right-preconditioned flexible GMRES(m), classical Gram-Schmidt twice, x0 = 0,
- * until ||b - G^ x|| <= rtol ||b|| (FP64 outer iteration; V-cycle precision per
- * the problem).  MFPFF_ERR_NOCONV leaves the last iterate in x.  Synchronises. */
+/* The linear solve of each Newton step of Algorithm 1 (Section 3.3: GMRES preconditioned by the
+ * multigrid V-cycle): right-preconditioned flexible GMRES(m), classical Gram-Schmidt twice,
+ * x0 = 0, until ||b - G^ x|| <= rtol ||b|| (FP64 outer iteration; V-cycle precision per the
+ * problem).  b, x: device, finest n_dofs.  MFPFF_ERR_NOCONV leaves the last iterate in x (info
+ * filled); MFPFF_ERR_STATE before mfpff_set_linearization.  Synchronises. */
 mfpff_status mfpff_gmres_solve(mfpff_ctx* ctx, const double* b, double* x, mfpff_solve_info* info);
 
 /* Residual of eq. (residual) on the finest level at (u, phi) with phi~ in
- * the degradation of the displacement equation; unconstrained (no masks). */
+ * the degradation of the displacement equation; unconstrained (no masks).  u (dim*n_nodes), phi,
+ * phi_tilde (n_nodes) and R (n_dofs): device.  Needs no linearisation. */
 mfpff_status mfpff_residual(mfpff_ctx* ctx, const double* u, const double* phi,
                             const double* phi_tilde, double* R);
 
-/* Parameter cotangents of the residual: dGc = <v, dR/dGc>, deps = <v, dR/deps>
- * (host doubles).  Synchronises. */
+/* Parameter cotangents of the residual of eq. (residual) at (u, phi; phi~):
+ * dGc = <v, dR/dGc>, deps = <v, dR/deps> (only the phase-field rows depend on Gc and eps).  u, phi,
+ * phi_tilde, v: device (v: n_dofs); dGc_host, deps_host: host doubles.  The point is passed
+ * explicitly, so the result does not depend on an earlier call.  Synchronises. */
 mfpff_status mfpff_residual_param_vjp(mfpff_ctx* ctx, const double* u, const double* phi,
                                       const double* phi_tilde, const double* v,
                                       double* dGc_host, double* deps_host);
