@@ -57,7 +57,11 @@ def test_active_set_matches_oracle_rule():
                                           ("C2", dict(N=16, n_h_levels=3, split="miehe"), "f64"),
                                           ("C3", dict(N=4, n_h_levels=2, split="miehe"), "f32"),
                                           ("C2", dict(N=16, n_h_levels=3, split="none"), "f64"),
-                                          ("C3", dict(N=4, n_h_levels=2, split="none"), "f32")])
+                                          ("C3", dict(N=4, n_h_levels=2, split="none"), "f32"),
+                                          # Q4 with p-coarsening Q4 -> Q2 -> Q1 on the coarsest mesh
+                                          ("C4", dict(dim=2, N=8, n_h_levels=2), "f64"),
+                                          ("C4", dict(dim=2, N=8, n_h_levels=2), "f32"),
+                                          ("C4", dict(dim=2, N=8, n_h_levels=2, phi_mode="ones"), "f64")])
 def test_fgmres_solve(name, kw, prec):
     cfg = CONFIGS[name].with_(**kw)
     levels = level_list(cfg)
@@ -65,7 +69,9 @@ def test_fgmres_solve(name, kw, prec):
     H = mg.Hierarchy(cfg, levels, inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
     A = H.levels[-1].A
     b = H.levels[-1].pvec * inp["rhs"]
+    cfg = cfg.with_(max_iter=max(cfg.max_iter, 2000))
     xo, info_o = krylov.fgmres(lambda v: A @ v, H.vcycle, b, cfg.restart, cfg.rtol, cfg.max_iter)
+    assert info_o["converged"]
     from helpers import gpu_context
     say(name, kw, prec, "gmres")
     ctx = gpu_context(cfg, levels, inp, vcycle_prec=prec)
@@ -75,7 +81,9 @@ def test_fgmres_solve(name, kw, prec):
     say(name, prec, "gpu iters", info["iterations"], "oracle iters", info_o["iterations"], "true res", res)
     assert info["converged"] == 1 and res <= cfg.rtol * 1.001
     if prec == "f64":
-        assert abs(info["iterations"] - info_o["iterations"]) <= 1
+        # long restarted runs (the Q4 cases take 300-750 iterations) may drift by a few iterations
+        # with rounding; short ones must agree to one
+        assert abs(info["iterations"] - info_o["iterations"]) <= max(1, int(0.02 * info_o["iterations"]))
     assert np.linalg.norm(x - xo) <= 1e-5 * np.linalg.norm(xo)
 
 
