@@ -69,6 +69,12 @@ typedef enum { MFPFF_F64 = 0, MFPFF_F32 = 1 } mfpff_prec;
  * Section 5 (no split): E^+ = lambda/2 tr(e)^2 + mu e : e, E^- = 0. */
 typedef enum { MFPFF_SPLIT_AMOR = 0, MFPFF_SPLIT_MIEHE = 1, MFPFF_SPLIT_NONE = 2 } mfpff_split;
 
+/* Engine of the sum-factorised 1D contractions (Section 3.4) of the 3D products at degree 3
+ * and 4 with the volumetric/deviatoric split: the vector unit (one thread per node line), or
+ * the matrix cores (MFMA blocks of 4 x 4; both give the same operator up to rounding).  Other
+ * degrees and splits always use the vector unit. */
+typedef enum { MFPFF_CONTRACT_VALU = 0, MFPFF_CONTRACT_MFMA = 1 } mfpff_contraction;
+
 typedef enum {
   MFPFF_OP_G = 0,         /* y = G^ x */
   MFPFF_OP_GT = 1,        /* y = G^T-hat x (transpose: coupling moves to the u rows) */
@@ -103,6 +109,8 @@ typedef struct {
                                        phi = 0, as the paper writes it); 1 first sets phi := phi_old
                                        on A_k (the iterate on the obstacle, the primal-dual active
                                        set update) and linearises there */
+  int contraction;                  /* mfpff_contraction: engine of the 1D contractions of the 3D
+                                       products at degree 3 and 4 (volumetric/deviatoric split) */
 } mfpff_problem;
 
 typedef struct {

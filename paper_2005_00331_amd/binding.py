@@ -17,6 +17,7 @@ MAX_LEVELS = 16
 F64, F32 = 0, 1
 OP_G, OP_GT, OP_BLOCKDIAG = 0, 1, 2
 SPLITS = {"amor": 0, "miehe": 1, "none": 2}   # mfpff_split
+CONTRACTIONS = {"valu": 0, "mfma": 1}          # mfpff_contraction
 OP_ACCUMULATE = 16
 
 STATUS = {0: "OK", 1: "ERR_ARG", 2: "ERR_STATE", 3: "ERR_OOM", 4: "ERR_HIP", 5: "ERR_NOCONV", 6: "ERR_NUMERIC"}
@@ -52,6 +53,7 @@ class Problem(ctypes.Structure):
         ("rtol", ctypes.c_double),
         ("split", ctypes.c_int),
         ("pdas_project", ctypes.c_int),
+        ("contraction", ctypes.c_int),
     ]
 
 
@@ -165,7 +167,8 @@ def load_library(path=LIB_PATH):
 
 def make_problem(dim, levels, *, dirichlet=True, lam=121.15e3, mu=80.77e3, Gc=2.7, eps, kappa=1e-10, as_c=1.0,
                  cheb_degree=5, cheb_lo=0.24, cheb_hi=1.2, lanczos_steps=15, lanczos_seed=20050331,
-                 vcycle_prec=F64, restart=30, max_iter=300, rtol=1e-8, split="amor", pdas_project=False):
+                 vcycle_prec=F64, restart=30, max_iter=300, rtol=1e-8, split="amor", pdas_project=False,
+                 contraction="valu"):
     """levels: list of (N, k) from the coarsest to the finest."""
     p = Problem()
     p.dim = dim
@@ -183,6 +186,9 @@ def make_problem(dim, levels, *, dirichlet=True, lam=121.15e3, mu=80.77e3, Gc=2.
         raise ValueError(f"split must be one of {sorted(SPLITS)}")
     p.split = SPLITS[split]
     p.pdas_project = 1 if pdas_project else 0
+    if contraction not in CONTRACTIONS:
+        raise ValueError(f"contraction must be one of {sorted(CONTRACTIONS)}")
+    p.contraction = CONTRACTIONS[contraction]
     return p
 
 
@@ -437,6 +443,7 @@ def problem_from(cfg, levels, vcycle_prec=None, dirichlet=None, **overrides):
               eps=cfg.eps, kappa=cfg.kappa, as_c=cfg.as_c, cheb_degree=cfg.cheb_degree, cheb_lo=cfg.cheb_lo,
               cheb_hi=cfg.cheb_hi, lanczos_steps=cfg.lanczos_steps, lanczos_seed=cfg.lanczos_seed,
               vcycle_prec=vp, restart=cfg.restart, max_iter=cfg.max_iter, rtol=cfg.rtol,
-              split=getattr(cfg, "split", "amor"), pdas_project=getattr(cfg, "pdas_project", False))
+              split=getattr(cfg, "split", "amor"), pdas_project=getattr(cfg, "pdas_project", False),
+              contraction=getattr(cfg, "contraction", "valu"))
     kw.update(overrides)
     return make_problem(cfg.dim, levels, **kw)

@@ -5,7 +5,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
-SOURCES = ["cell_kernel.hip", "tile_kernel.hip", "rowcell_kernel.hip", "linecell_kernel.hip", "vector_ops.hip", "transfer.hip", "dense.hip", "tables.cpp", "host.cpp"]
+SOURCES = ["cell_kernel.hip", "tile_kernel.hip", "rowcell_kernel.hip", "linecell_kernel.hip", "mfma_kernel.hip", "vector_ops.hip", "transfer.hip", "dense.hip", "tables.cpp", "host.cpp"]
 LIB = os.path.join(HERE, "libmfpff.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("MFPFF_ARCH", "gfx950")

@@ -424,8 +424,10 @@ static hipError_t launch_dk(int mode, const CellArgs<T>& a, const Tables<T>* tab
   if (nb > 0x7fffffffLL) return hipErrorInvalidValue;
   dim3 grid((unsigned)nb), block(kThreads);
   const bool qd = DIM == 3 && a.qd != nullptr;
-  if (qd && a.elem && (mode == MODE_APPLY || mode == MODE_APPLY_T || mode == MODE_BLOCK))
+  if (qd && a.elem && (mode == MODE_APPLY || mode == MODE_APPLY_T || mode == MODE_BLOCK)) {
+    if (a.mfma && K >= 3 && a.m.split == SPLIT_AMOR) return launch_mfmacell<T>(mode, a, tab, s);
     return launch_linecell<T>(mode, a, tab, s);
+  }
   switch (mode) {
     case MODE_APPLY:
       if (qd) hipLaunchKernelGGL((cell_kernel<DIM, K, T, MODE_APPLY, true>), grid, block, 0, s, a, tab);

@@ -286,6 +286,7 @@ CellArgs<T> cell_args(mfpff_ctx* c, const Level& L, const T* lin, const T* x, T*
   a.mask = L.mask;
   a.scale = scale;
   a.qd = level_qd<T>(L);
+  a.mfma = c->prob.contraction == MFPFF_CONTRACT_MFMA;
   return a;
 }
 
@@ -1076,6 +1077,7 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
   if (p.vcycle_prec != MFPFF_F64 && p.vcycle_prec != MFPFF_F32) return MFPFF_ERR_ARG;
   if (p.split != MFPFF_SPLIT_AMOR && p.split != MFPFF_SPLIT_MIEHE && p.split != MFPFF_SPLIT_NONE) return MFPFF_ERR_ARG;
   if (p.pdas_project != 0 && p.pdas_project != 1) return MFPFF_ERR_ARG;
+  if (p.contraction != MFPFF_CONTRACT_VALU && p.contraction != MFPFF_CONTRACT_MFMA) return MFPFF_ERR_ARG;
   if (!(p.eps > 0.0) || !(p.kappa >= 0.0) || !(p.cheb_hi > p.cheb_lo) || !(p.cheb_lo > 0.0)) return MFPFF_ERR_ARG;
   for (int l = 0; l < p.n_levels; ++l) {
     if (p.level_N[l] < 1 || p.level_k[l] < 1 || p.level_k[l] > kMaxDeg) return MFPFF_ERR_ARG;

@@ -105,6 +105,8 @@ struct CellArgs {
   const T* qd;         // 2D Q1/Q2: cached tangent coefficients (null: computed from u, phi, phi~)
   T* qd_out;           // MODE_QDATA: where the coefficients go
   T* elem;             // 3D operator modes: cell results [cell][component][point] instead of atomics
+  int mfma;            // 3D products at degree >= 3 (volumetric/deviatoric split): contractions on the
+                       // matrix cores (mfma_kernel.hip) instead of the vector unit (linecell_kernel.hip)
 };
 
 // Fused vector epilogues of the owner-computes kernels (tile_kernel.hip)
@@ -132,6 +134,10 @@ long long elem_len(const Geom& g);  // values in the element buffer of one level
 template <typename T>
 hipError_t launch_linecell(int mode, const CellArgs<T>& a, const Tables<T>* tab_dev, hipStream_t s);
 long long cell_qdata_len(const Geom& g, int split);  // 3D: values of the cached tangent coefficients of one level
+// the same 3D products at degree 3 and 4 with the 1D contractions on the matrix cores (MFMA),
+// volumetric/deviatoric split only (mfma_kernel.hip); a.qd and a.elem required
+template <typename T>
+hipError_t launch_mfmacell(int mode, const CellArgs<T>& a, const Tables<T>* tab_dev, hipStream_t s);
 template <typename T>
 hipError_t launch_tile_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<T>* tab, hipStream_t s);
 long long tile_blocks_2d(const Geom& g);

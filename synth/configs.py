@@ -38,6 +38,7 @@ class Config:
     dirichlet: bool = True    # delta u = 0 on the two faces normal to the last axis
     split: str = "amor"       # tension/compression split: "amor" (workloads), "miehe" (spectral), "none" (isotropic)
     pdas_project: bool = False  # Algorithm 1 as written (delta phi = 0 on A) or phi := phi_old on A first
+    contraction: str = "valu"   # 3D products at degree 3/4: 1D contractions on the vector unit or the matrix cores ("mfma")
     seed_index: int = 0
     lanczos_seed: int = 20050331
 

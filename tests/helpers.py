@@ -60,6 +60,15 @@ CASES = {
     "3d_q3_f32": ("C4", [(3, 1), (3, 3)], dict(vcycle_prec="f32")),
     "3d_q4_f32": ("C4", [(2, 1), (2, 2), (2, 4), (4, 4)], dict(vcycle_prec="f32")),
     "2d_q2_f32": ("C2", [(5, 2), (10, 2)], dict(vcycle_prec="f32")),
+    # 3D Q3/Q4 products with the 1D contractions on the matrix cores (MFMA); 27-cell levels leave
+    # a ragged last workgroup (the ragged Q4 case p-coarsens straight to Q1: a 3^3 Q2 coarse level
+    # with the notch band would have cond(G^_uu) = 1.3e11, too ill-conditioned for the coarse-solve bound)
+    "3d_q3_mfma": ("C4", [(3, 1), (3, 3)], dict(contraction="mfma")),
+    "3d_q4_mfma": ("C4", [(2, 2), (2, 4), (4, 4)], dict(contraction="mfma")),
+    "3d_q4_mfma_ragged": ("C4", [(3, 1), (3, 4)], dict(contraction="mfma")),
+    "3d_q3_mfma_f32": ("C4", [(3, 1), (3, 3)], dict(vcycle_prec="f32", contraction="mfma")),
+    "3d_q4_mfma_f32": ("C4", [(2, 1), (2, 2), (2, 4), (4, 4)], dict(vcycle_prec="f32", contraction="mfma")),
+    "3d_q4_mfma_ragged_f32": ("C4", [(3, 1), (3, 4)], dict(vcycle_prec="f32", contraction="mfma")),
 }
 
 

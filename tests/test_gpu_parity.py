@@ -120,7 +120,8 @@ def test_coarse_solve_and_vcycle(name):
     assert e <= 1e-10, (name, e)
 
 
-@pytest.mark.parametrize("name", ["3d_q2_f32", "3d_q3_f32", "3d_q4_f32", "2d_q2_f32", "2d_q2_miehe_f32", "3d_q2_miehe_f32"])
+@pytest.mark.parametrize("name", ["3d_q2_f32", "3d_q3_f32", "3d_q4_f32", "2d_q2_f32", "2d_q2_miehe_f32", "3d_q2_miehe_f32",
+                                  "3d_q3_mfma_f32", "3d_q4_mfma_f32", "3d_q4_mfma_ragged_f32"])
 def test_fp32_level_products(name):
     import torch
     from paper_2005_00331_amd import F32, OP_BLOCKDIAG, OP_G
@@ -182,3 +183,24 @@ def test_element_matrices_and_sparse_product(dim, N, k, split):
     x = dev(np.random.default_rng(3).standard_normal(mesh.n_dofs))
     y = host(torch.mv(A, x))
     assert rel_err(y, host(ctx.apply_jacobian(-1, x, op=OP_G))) <= 1e-12
+
+
+@pytest.mark.parametrize("k,N", [(3, 5), (4, 3)])
+def test_mfma_products_match_the_vector_unit(k, N):
+    # the matrix-core and the vector-unit contractions give the same products up to rounding,
+    # in FP64 and FP32, for every operator mode
+    import torch
+    from paper_2005_00331_amd import F32, F64, OP_BLOCKDIAG, OP_G, OP_GT, Context, problem_from
+    from synth import CONFIGS, make_inputs
+    cfg = CONFIGS["C4"].with_(N=N, k=k, n_h_levels=1, p_coarse=(), vcycle_prec="f32")
+    inp = make_inputs(cfg)
+    ctxs = [Context(problem_from(cfg, [(N, k)], contraction=c)) for c in ("valu", "mfma")]
+    for ctx in ctxs:
+        ctx.set_linearization(dev(inp["u"]), dev(inp["phi"]), dev(inp["phi_old"]), dev(inp["active"]),
+                              dev(inp["phi_tilde"]))
+    x = np.random.default_rng(14).standard_normal(ctxs[0].n_dofs)
+    for prec, dt, tol in ((F64, torch.float64, 1e-13), (F32, torch.float32, 1e-5)):
+        for opn in (OP_G, OP_GT, OP_BLOCKDIAG):
+            say("mfma vs valu", k, N, prec, opn)
+            ys = [host(c.apply_jacobian(-1, dev(x, dt), prec=prec, op=opn)) for c in ctxs]
+            assert rel_err(ys[1], ys[0]) <= tol
