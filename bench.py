@@ -296,9 +296,10 @@ def time_products_3d(cfg):
     """Finest-level product of a 3D workload in FP64 and FP32 after set_linearization."""
     ctx, levels, state = build_context(cfg, prec="f32")
     ctx.set_linearization(state["u"], state["phi"], state["phi_old"], state["active"], state["phi_tilde"])
+    engine = "matrix cores (MFMA)" if cfg.contraction == "mfma" and cfg.k >= 3 else "vector unit"
     fl = contraction_flops_3d(cfg)
     res = {"workload": f"{cfg.name}: 3D {cfg.N}^3 cells Q{cfg.k}, {cfg.n_dofs} dofs, finest-level product "
-                       f"(line kernel + node gather)", "contraction_gflop": fl / 1e9,
+                       f"(cell kernel + node gather)", "contractions_on": engine, "contraction_gflop": fl / 1e9,
            "note": "operands, coefficient cache and element buffer exceed the 256 MB last-level cache, so "
                    "back-to-back launches read from HBM; frac_of_peak counts only the contraction flops"}
     for f32, tag, peak in ((False, "f64", 78.6), (True, "f32", 157.3)):
@@ -445,6 +446,10 @@ def main():
     ap.add_argument("--solve", metavar="WORKLOAD",
                     help="instead: one linear solve (set-up plus FGMRES) of the named workload's seeded system with "
                          "the FP64 and the FP32 V-cycle, printed as one record")
+    ap.add_argument("--restart", type=int, default=None, help="with --solve: FGMRES restart length (default: the workload's)")
+    ap.add_argument("--cheb-degree", type=int, default=None, help="with --solve: Chebyshev degree (default: the workload's)")
+    ap.add_argument("--contraction", default=None, choices=("valu", "mfma"),
+                    help="with --solve or --apply-only: 3D Q3/Q4 contractions on the vector unit or the matrix cores")
     ap.add_argument("--apply-only", action="store_true",
                     help="only time the finest-level cell kernel (for kernel-trace and counter runs)")
     args = ap.parse_args()
@@ -463,8 +468,12 @@ def main():
         return
     if args.solve:
         cfg = CONFIGS[args.solve].with_(max_iter=5000)
+        for key, val in (("restart", args.restart), ("cheb_degree", args.cheb_degree), ("contraction", args.contraction)):
+            if val is not None:
+                cfg = cfg.with_(**{key: val})
         rec = {"workload": f"{cfg.name}: {cfg.dim}D {cfg.N}^{cfg.dim} cells Q{cfg.k}, {cfg.n_dofs} dofs, levels "
-                           f"{level_list(cfg)}, seeded state, active set and right-hand side, rtol {cfg.rtol}"}
+                           f"{level_list(cfg)}, seeded state, active set and right-hand side, rtol {cfg.rtol}",
+               "restart": cfg.restart, "cheb_degree": cfg.cheb_degree, "contraction": cfg.contraction}
         for prec in ("f64", "f32"):
             rec[prec + "_vcycle"] = time_solve(cfg, prec, warm=False)
             print(f"[bench] {cfg.name} solve, {prec} V-cycle: {rec[prec + '_vcycle']}", file=sys.stderr, flush=True)
@@ -485,21 +494,26 @@ def main():
     print(f"[bench] workload {cfg.name}: {cfg.dim}D N={cfg.N} Q{cfg.k}, {cfg.n_dofs} dofs", file=sys.stderr, flush=True)
     ctx, levels, state = build_context(cfg)
     if args.apply_only:
-        zeros = torch.zeros(ctx.n_nodes, dtype=torch.uint8, device="cuda")
-        ctx.set_point(state["u"], state["phi"], state["phi_old"], zeros, state["phi_tilde"])
         # calibration for the traffic counters: one plain device copy of 64 MiB
         src = torch.ones(8 << 20, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         ctx.close()
-        ctxs = product_contexts(cfg, N_ROTATE)
-        t_apply = time_apply_rotating(ctxs)
-        byts = algorithmic_bytes_per_apply(cfg.dim, ctxs[0][0].n_nodes, 8)
-        print(json.dumps({"apply_us": t_apply * 1e6, "GB/s": byts / t_apply / 1e9, "bytes_per_launch": byts,
-                          "timing": f"rotating through {N_ROTATE} contexts"}), flush=True)
-        for c, _, _ in ctxs:
-            c.close()
+        if cfg.dim == 2:
+            ctxs = product_contexts(cfg, N_ROTATE)
+            t_apply = time_apply_rotating(ctxs)
+            byts = algorithmic_bytes_per_apply(cfg.dim, ctxs[0][0].n_nodes, 8)
+            print(json.dumps({"apply_us": t_apply * 1e6, "GB/s": byts / t_apply / 1e9, "bytes_per_launch": byts,
+                              "timing": f"rotating through {N_ROTATE} contexts"}), flush=True)
+            for c, _, _ in ctxs:
+                c.close()
+        else:
+            # 3D: the finest-level product in FP64, then FP32 (50 back-to-back launches each; the
+            # operands, coefficient cache and element buffer exceed the last-level cache)
+            if args.contraction:
+                cfg = cfg.with_(contraction=args.contraction)
+            print(json.dumps(time_products_3d(cfg)), flush=True)
         return
     sec, infos = time_newton(ctx, state, args.steps, args.warmup)
     print(f"[bench] newton step {sec * 1e3:.2f} ms, iters {[i['iterations'] for i in infos]}", file=sys.stderr,
