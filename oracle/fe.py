@@ -57,13 +57,29 @@ def lagrange_derivs(k: int, x: np.ndarray) -> np.ndarray:
 
 
 class Mesh:
-    """Structured Q_k mesh of the unit square/cube."""
+    """Structured Q_k mesh of the unit square/cube.
 
-    def __init__(self, dim: int, N: int, k: int):
+    slit=True: the geometry of the single-edge-notched tests (Section 5.1), a slit on the
+    mid-plane of the last axis from the face x = 0 to x = 1/2, across which the cells do not
+    connect.  The nodes on the slit (last-axis coordinate 1/2, first coordinate below 1/2; the
+    tip at x = 1/2 is shared) exist twice: the grid node belongs to the cells below the slit, a
+    duplicate appended after the M^dim grid nodes to the cells above it.  Duplicates are numbered
+    like their grid nodes with the first axis fastest (3D: then the second axis).  N must be even."""
+
+    def __init__(self, dim: int, N: int, k: int, slit: bool = False):
         self.dim, self.N, self.k = dim, N, k
         self.h = 1.0 / N
         self.M = k * N + 1
-        self.n_nodes = self.M ** dim
+        self.slit = bool(slit)
+        self.n_grid = self.M ** dim
+        if self.slit:
+            assert N % 2 == 0, "the slit lies on a cell face only for even N"
+            self.n_slit_x = k * N // 2          # slit nodes per line along the first axis
+            self.n_dup = self.n_slit_x * (self.M ** (dim - 2))
+        else:
+            self.n_slit_x = 0
+            self.n_dup = 0
+        self.n_nodes = self.n_grid + self.n_dup
         self.n_cells = N ** dim
         self.P = (k + 1) ** dim   # nodes per cell == quadrature points per cell
 
@@ -88,10 +104,25 @@ class Mesh:
         lm = self.local_multi()                           # (P, dim)
         g = self.k * cm[:, None, :] + lm[None, :, :]      # (nc, P, dim)
         stride = self.M ** np.arange(self.dim)
-        return (g * stride).sum(-1)
+        ids = (g * stride).sum(-1)
+        if self.slit:
+            # cells just above the slit plane take the duplicates of their slit-plane nodes
+            d = self.dim
+            above = (cm[:, d - 1] == self.N // 2)[:, None] & (lm[None, :, d - 1] == 0)
+            on_slit = above & (g[:, :, 0] < self.n_slit_x)
+            dup = g[:, :, 0] + (self.n_slit_x * g[:, :, 1] if d == 3 else 0)
+            ids = np.where(on_slit, self.n_grid + dup, ids)
+        return ids
 
     def node_multi(self, nodes) -> np.ndarray:
+        """(n, dim) grid multi-indices of nodes (a duplicate has the one of its grid node)."""
         nodes = np.asarray(nodes)
+        if self.slit:
+            j = nodes - self.n_grid
+            orig = (j % self.n_slit_x) + self.M ** (self.dim - 1) * (self.M // 2)
+            if self.dim == 3:
+                orig = orig + self.M * (j // self.n_slit_x)
+            nodes = np.where(nodes >= self.n_grid, orig, nodes)
         return np.stack([(nodes // self.M ** a) % self.M for a in range(self.dim)], axis=1)
 
     def cells_of_nodes(self, nodes) -> np.ndarray:
@@ -111,7 +142,7 @@ class Mesh:
 
     def boundary_nodes(self, axis: int) -> np.ndarray:
         """Boolean mask of nodes on the two faces normal to ``axis``."""
-        i = (np.arange(self.n_nodes) // self.M ** axis) % self.M
+        i = self.node_multi(np.arange(self.n_nodes))[:, axis]
         return (i == 0) | (i == self.M - 1)
 
 

@@ -24,7 +24,7 @@ from .newton import pdas_solve
 
 def face_nodes(mesh: Mesh, top: bool) -> np.ndarray:
     """Indices of the nodes on the bottom (last-axis coordinate 0) or top (1) face."""
-    i = (np.arange(mesh.n_nodes) // mesh.M ** (mesh.dim - 1)) % mesh.M
+    i = mesh.node_multi(np.arange(mesh.n_nodes))[:, mesh.dim - 1]
     return np.flatnonzero(i == (mesh.M - 1 if top else 0))
 
 
@@ -53,7 +53,7 @@ def load_step(cfg, levels_nk, u, phi, phi_prev, phi_prev2, u_top, max_newton=20,
     """One load step: prescribe the boundary displacement, extrapolate phi~, run Algorithm 1
     to its stopping test from (u, phi); returns the new state, the loop's record, phi~ and the
     reactions on the top and bottom faces."""
-    mesh = Mesh(cfg.dim, cfg.N, cfg.k)
+    mesh = Mesh(cfg.dim, cfg.N, cfg.k, getattr(cfg, "slit", False))
     u0 = impose_displacement(mesh, u, u_top)
     pt = extrapolate(phi_prev, phi_prev2)
     out = pdas_solve(cfg, levels_nk, u0, np.array(phi, dtype=np.float64), np.asarray(phi_prev), pt, max_newton, tol)

@@ -77,7 +77,10 @@ class Hierarchy:
         dirichlet = cfg.dirichlet if dirichlet is None else dirichlet
         self.cfg = cfg
         self.m = op.material_of(cfg) if m is None else m
-        meshes = [Mesh(cfg.dim, N, k) for (N, k) in levels_nk]
+        slit = getattr(cfg, "slit", False)
+        if slit and len(levels_nk) > 1:
+            raise ValueError("multigrid levels on the slit mesh are not built: one level, exact coarse solve")
+        meshes = [Mesh(cfg.dim, N, k, slit) for (N, k) in levels_nk]
         L = len(meshes) - 1
         fields = [None] * (L + 1)
         fields[L] = (u, phi, phi_t, np.asarray(active).astype(np.uint8))

@@ -30,7 +30,7 @@ def active_set(mesh: Mesh, R, phi, phi_old, c=1.0):
 
 def newton_step(cfg, levels_nk, u, phi, phi_old, phi_t):
     """One step: residual, active set, linearisation, FGMRES + GMG, update."""
-    mesh = Mesh(cfg.dim, cfg.N, cfg.k)
+    mesh = Mesh(cfg.dim, cfg.N, cfg.k, getattr(cfg, "slit", False))
     m = op.material_of(cfg)
     R = op.residual(mesh, m, u, phi, phi_t)
     act, ind = active_set(mesh, R, phi, phi_old, cfg.as_c)
@@ -54,7 +54,7 @@ def pdas_solve(cfg, levels_nk, u, phi, phi_old, phi_t, max_newton=20, tol=1e-8):
     free dofs, ||P_k R_k||, is at most tol ||P_0 R_0|| (reading: the paper's eps_as taken relative
     to the first iterate).  Returns the final state, the number of Newton steps taken, the norms
     and the FGMRES iteration counts."""
-    mesh = Mesh(cfg.dim, cfg.N, cfg.k)
+    mesh = Mesh(cfg.dim, cfg.N, cfg.k, getattr(cfg, "slit", False))
     m = op.material_of(cfg)
     prev = None
     norms, iters = [], []

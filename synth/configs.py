@@ -38,6 +38,8 @@ class Config:
     dirichlet: bool = True    # delta u = 0 on the two faces normal to the last axis
     split: str = "amor"       # tension/compression split: "amor" (workloads), "miehe" (spectral), "none" (isotropic)
     pdas_project: bool = False  # Algorithm 1 as written (delta phi = 0 on A) or phi := phi_old on A first
+    slit: bool = False          # geometry of Section 5.1: a slit from x = 0 to 1/2 on the mid-plane of the
+                                # last axis, its nodes duplicated (single level); no phi = 0 notch band then
     contraction: str = "valu"   # 3D products at degree 3/4: 1D contractions on the vector unit or the matrix cores ("mfma")
     seed_index: int = 0
     lanczos_seed: int = 20050331
@@ -56,7 +58,9 @@ class Config:
 
     @property
     def n_nodes(self) -> int:
-        return self.M ** self.dim
+        # the slit's duplicated nodes: k N / 2 per line along the first axis, M lines in 3D
+        dup = (self.k * self.N // 2) * self.M ** (self.dim - 2) if self.slit else 0
+        return self.M ** self.dim + dup
 
     @property
     def n_dofs(self) -> int:

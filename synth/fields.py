@@ -29,13 +29,31 @@ def node_coords(dim: int, N: int, k: int) -> np.ndarray:
     return out
 
 
+def slit_duplicates(dim: int, N: int, k: int) -> np.ndarray:
+    """Grid node of each duplicated slit node, in the order the duplicates are numbered after the
+    M**dim grid nodes: the slit-plane nodes (last-axis index k*N/2) with first index below k*N/2,
+    first axis fastest (3D: then the second axis)."""
+    M = k * N + 1
+    i0 = np.arange(k * N // 2)
+    if dim == 2:
+        return i0 + M * (k * N // 2)
+    i1 = np.arange(M)
+    return (i0[None, :] + M * i1[:, None] + M * M * (k * N // 2)).ravel()
+
+
 def _coords(cfg):
-    return node_coords(cfg.dim, cfg.N, cfg.k)
+    X = node_coords(cfg.dim, cfg.N, cfg.k)
+    if getattr(cfg, "slit", False):
+        X = np.concatenate([X, X[slit_duplicates(cfg.dim, cfg.N, cfg.k)]])
+    return X
 
 
 def notch_mask(cfg) -> np.ndarray:
-    """Nodes of the one-cell band on the mid-plane of the last axis, first half of axis 0."""
+    """Nodes of the one-cell band on the mid-plane of the last axis, first half of axis 0 (none
+    on a slit mesh, where the slit itself is the notch)."""
     X = _coords(cfg)
+    if getattr(cfg, "slit", False):
+        return np.zeros(X.shape[0], dtype=bool)
     h = cfg.h
     y = X[:, cfg.dim - 1]
     return (np.abs(y - 0.5) <= h / 2 + 1e-12) & (X[:, 0] < 0.5 - 1e-12)
