@@ -111,6 +111,15 @@ typedef struct {
                                        set update) and linearises there */
   int contraction;                  /* mfpff_contraction: engine of the 1D contractions of the 3D
                                        products at degree 3 and 4 (volumetric/deviatoric split) */
+  int slit;                         /* 1: the slit geometry of the notched tests (Section 5.1): the
+                                       cells on the two sides of the mid-plane of the last axis are
+                                       not connected for x < 1/2.  Those slit-plane nodes exist
+                                       twice: the grid node belongs to the cells below the slit, a
+                                       duplicate, numbered after the M^dim grid nodes (first axis
+                                       fastest, then the second axis in 3D), to the cells above, so
+                                       n_nodes = M^dim + (kN/2) M^(dim-2).  Requires one level (the
+                                       exact coarse solve preconditions GMRES) and even N; products
+                                       use the cell kernel with the slit-aware node map */
 } mfpff_problem;
 
 typedef struct {

@@ -54,6 +54,7 @@ class Problem(ctypes.Structure):
         ("split", ctypes.c_int),
         ("pdas_project", ctypes.c_int),
         ("contraction", ctypes.c_int),
+        ("slit", ctypes.c_int),
     ]
 
 
@@ -168,7 +169,7 @@ def load_library(path=LIB_PATH):
 def make_problem(dim, levels, *, dirichlet=True, lam=121.15e3, mu=80.77e3, Gc=2.7, eps, kappa=1e-10, as_c=1.0,
                  cheb_degree=5, cheb_lo=0.24, cheb_hi=1.2, lanczos_steps=15, lanczos_seed=20050331,
                  vcycle_prec=F64, restart=30, max_iter=300, rtol=1e-8, split="amor", pdas_project=False,
-                 contraction="valu"):
+                 contraction="valu", slit=False):
     """levels: list of (N, k) from the coarsest to the finest."""
     p = Problem()
     p.dim = dim
@@ -189,6 +190,7 @@ def make_problem(dim, levels, *, dirichlet=True, lam=121.15e3, mu=80.77e3, Gc=2.
     if contraction not in CONTRACTIONS:
         raise ValueError(f"contraction must be one of {sorted(CONTRACTIONS)}")
     p.contraction = CONTRACTIONS[contraction]
+    p.slit = 1 if slit else 0
     return p
 
 
@@ -444,6 +446,6 @@ def problem_from(cfg, levels, vcycle_prec=None, dirichlet=None, **overrides):
               cheb_hi=cfg.cheb_hi, lanczos_steps=cfg.lanczos_steps, lanczos_seed=cfg.lanczos_seed,
               vcycle_prec=vp, restart=cfg.restart, max_iter=cfg.max_iter, rtol=cfg.rtol,
               split=getattr(cfg, "split", "amor"), pdas_project=getattr(cfg, "pdas_project", False),
-              contraction=getattr(cfg, "contraction", "valu"))
+              contraction=getattr(cfg, "contraction", "valu"), slit=getattr(cfg, "slit", False))
     kw.update(overrides)
     return make_problem(cfg.dim, levels, **kw)

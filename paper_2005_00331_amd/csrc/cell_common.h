@@ -70,11 +70,18 @@ __device__ __forceinline__ long long node_of(const Geom& g, long long cell, int 
   const long long cy = q1 % un;
   const int i0 = p % NP, i1 = (p / NP) % NP;
   long long node = (K * cx + i0) + M * (K * cy + i1);
+  long long clast = cy, ilast = i1;
   if (DIM == 3) {
     const long long cz = q1 / un;
     const int i2 = p / (NP * NP);
     node += M * M * (K * cz + i2);
+    clast = cz;
+    ilast = i2;
   }
+  // slit mesh: a cell just above the slit plane takes the duplicates of its slit-plane nodes
+  // that lie below x = 1/2 (the tip at x = 1/2 is shared)
+  if (g.slit && clast == N / 2 && ilast == 0 && K * cx + i0 < K * N / 2)
+    node = g.n_grid + (K * cx + i0) + (DIM == 3 ? (K * N / 2) * (K * cy + i1) : 0);
   return node;
 }
 

@@ -163,14 +163,16 @@ struct mfpff_ctx {
 
 namespace {
 
-Geom make_geom(int dim, int N, int k) {
+Geom make_geom(int dim, int N, int k, int slit = 0) {
   Geom g{};
   g.dim = dim;
   g.k = k;
   g.N = N;
   g.M = k * N + 1;
-  g.n_nodes = 1;
-  for (int a = 0; a < dim; ++a) g.n_nodes *= g.M;
+  g.n_grid = 1;
+  for (int a = 0; a < dim; ++a) g.n_grid *= g.M;
+  g.slit = slit;
+  g.n_nodes = g.n_grid + (slit ? (long long)(k * N / 2) * (dim == 3 ? g.M : 1) : 0);
   g.h = 1.0 / N;
   return g;
 }
@@ -320,6 +322,19 @@ void launch_2d(mfpff_ctx* c, const Level& L, int mode, int epi, const CellArgs<T
 // buffer, then the node gather
 template <typename T>
 void launch_fused(mfpff_ctx* c, const Level& L, int mode, int epi, CellArgs<T> a, const Epilogue<T>& e) {
+  if (L.g.slit) {
+    // slit levels: the cell kernel computes at the Gauss points and scatters through the slit-aware
+    // node map with atomics; the identity rows (and, for a residual, b) follow elementwise
+    if (epi == EPI_CHEB) throw StatusError{MFPFF_ERR_ARG, "no smoothing on a slit level (one level only)"};
+    k_fill<T>(e.y, T(0), L.n, c->s);
+    a.y = e.y;
+    a.qd = nullptr;
+    a.elem = nullptr;
+    HIPCHK(launch_cell<T>(mode, a, tab<T>(c, L.g.k), c->s));
+    k_slit_epilogue<T>(e.y, a.x, epi == EPI_RESID ? e.b : nullptr, a.mask, L.nn, c->dim, c->s);
+    LAUNCHCHK();
+    return;
+  }
   if (c->dim == 2) {
     launch_2d<T>(c, L, mode, epi, a, e);
     return;
@@ -339,7 +354,7 @@ void residual_launch(mfpff_ctx* c, const double* u, const double* phi, const dou
   a.phi = phi;
   a.phit = pt;
   a.mask = nullptr;
-  if (c->dim == 3) {
+  if (c->dim == 3 && !F.g.slit) {
     a.elem = (double*)c->elem;
     HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
     // the gather reads x at every node before it writes y there (same thread); with no mask
@@ -1078,6 +1093,9 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
   if (p.split != MFPFF_SPLIT_AMOR && p.split != MFPFF_SPLIT_MIEHE && p.split != MFPFF_SPLIT_NONE) return MFPFF_ERR_ARG;
   if (p.pdas_project != 0 && p.pdas_project != 1) return MFPFF_ERR_ARG;
   if (p.contraction != MFPFF_CONTRACT_VALU && p.contraction != MFPFF_CONTRACT_MFMA) return MFPFF_ERR_ARG;
+  // the slit geometry: one level (its exact coarse solve is the preconditioner), an even cell count
+  if (p.slit != 0 && p.slit != 1) return MFPFF_ERR_ARG;
+  if (p.slit && (p.n_levels != 1 || p.level_N[0] % 2 != 0)) return MFPFF_ERR_ARG;
   if (!(p.eps > 0.0) || !(p.kappa >= 0.0) || !(p.cheb_hi > p.cheb_lo) || !(p.cheb_lo > 0.0)) return MFPFF_ERR_ARG;
   for (int l = 0; l < p.n_levels; ++l) {
     if (p.level_N[l] < 1 || p.level_k[l] < 1 || p.level_k[l] > kMaxDeg) return MFPFF_ERR_ARG;
@@ -1103,7 +1121,7 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
     size_t elem_bytes = 0;
     for (int l = 0; l < p.n_levels; ++l) {
       Level& L = c->lv[l];
-      L.g = make_geom(d, p.level_N[l], p.level_k[l]);
+      L.g = make_geom(d, p.level_N[l], p.level_k[l], p.slit);
       L.nn = L.g.n_nodes;
       L.n = (long long)(d + 1) * L.nn;
       if (L.n >= (1LL << 31)) throw StatusError{MFPFF_ERR_ARG, "a level with 2^31 or more dofs is not supported"};
@@ -1119,7 +1137,7 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
         const size_t eb = (size_t)elem_len(L.g) * sizeof(double);
         if (eb > elem_bytes) elem_bytes = eb;
       }
-      if ((d == 2 && L.g.k <= 2) || d == 3) {
+      if (((d == 2 && L.g.k <= 2) || d == 3) && !p.slit) {
         const size_t nq = (size_t)(d == 2 ? rowcell_qdata_len(L.g, p.split) : cell_qdata_len(L.g, p.split));
         L.qd = dalloc<double>(nq);
         if (c->f32) L.qd32 = dalloc<float>(nq);

@@ -41,8 +41,12 @@ __device__ __forceinline__ T keep_if(T v, bool keep) {
 // Q_k with equispaced nodes, M = k*N + 1 nodes per direction.
 struct Geom {
   int dim, k, N, M;
-  long long n_nodes;
+  long long n_nodes;  // grid nodes plus, on a slit mesh, the duplicated slit nodes after them
   double h;
+  long long n_grid;   // M^dim
+  int slit;           // the slit of the notched tests (Section 5.1) on the mid-plane of the last axis,
+                      // x < 1/2: its k N / 2 (3D: times M) grid nodes belong to the cells below it and
+                      // duplicates, numbered n_grid + i0 (+ (k N / 2) i1), to the cells above it
 };
 
 struct MatParams {
@@ -175,6 +179,8 @@ void k_cheb_update(T* zout, T* d, const T* zin, const T* r, const T* t, const T*
 void k_cast_d2f(float* y, const double* x, long long n, hipStream_t s);
 void k_cast_f2d(double* y, const float* x, long long n, hipStream_t s);
 void k_mask_vec(double* y, const uint8_t* mask, long long nn, int dim, double scale, hipStream_t s);
+template <typename T>
+void k_slit_epilogue(T* y, const T* x, const T* b, const uint8_t* mask, long long nn, int dim, hipStream_t s);
 void k_inject(double* lin_c, uint8_t* mask_c, const double* lin_f, const uint8_t* mask_f,
               const Geom& gc, const Geom& gf, int dirichlet, hipStream_t s);
 void k_fine_fields(double* lin, uint8_t* mask, const double* u, const double* phi, const double* phit,

@@ -148,7 +148,7 @@ void k_mask_vec(double* y, const uint8_t* mask, long long nn, int dim, double sc
 }
 
 __device__ __forceinline__ uint8_t dirichlet_bit(long long node, const Geom& g, int dirichlet) {
-  if (!dirichlet) return 0;
+  if (!dirichlet || node >= g.n_grid) return 0;  // slit duplicates lie on the mid-plane
   long long stride = 1;
   for (int a = 0; a < g.dim - 1; ++a) stride *= g.M;
   const long long i = (node / stride) % g.M;
@@ -197,22 +197,59 @@ void k_inject(double* lin_c, uint8_t* mask_c, const double* lin_f, const uint8_t
 
 // Row-sum-lumped phi mass: product over axes of h * (sum of the 1D basis
 // integrals of the cells that share the node).
+// On a slit mesh a slit-plane node below x = 1/2 has only the cells below it (local index k along
+// the last axis), its duplicate only those above it (local index 0).
 __global__ void lumped_mass_kernel(double* ml, Geom g, const double* w1d) {
+  const long long ns = (long long)g.k * g.N / 2;  // slit nodes per line along the first axis
   GSTRIDE(i, g.n_nodes) {
-    long long rem = i;
+    long long gi = i;
+    int side = 0;  // 1: grid node on the slit (lower side), 2: duplicate (upper side)
+    if (g.slit) {
+      if (i >= g.n_grid) {
+        const long long j = i - g.n_grid;
+        gi = (j % ns) + (g.dim == 3 ? (long long)g.M * (j / ns) : 0) + (g.n_grid / g.M) * (g.M / 2);
+        side = 2;
+      } else if ((i / (g.n_grid / g.M)) == g.M / 2 && (i % g.M) < ns) {
+        side = 1;
+      }
+    }
+    long long rem = gi;
     double v = 1.0;
     for (int a = 0; a < g.dim; ++a) {
       const long long ia = rem % g.M;
       rem /= g.M;
       const int loc = (int)(ia % g.k);
       double wa;
-      if (loc == 0) wa = (ia > 0 ? w1d[g.k] : 0.0) + (ia < g.M - 1 ? w1d[0] : 0.0);
+      if (a == g.dim - 1 && side != 0) wa = side == 1 ? w1d[g.k] : w1d[0];
+      else if (loc == 0) wa = (ia > 0 ? w1d[g.k] : 0.0) + (ia < g.M - 1 ? w1d[0] : 0.0);
       else wa = w1d[loc];
       v *= g.h * wa;
     }
     ml[i] = v;
   }
 }
+
+// Slit levels: the epilogue of a product accumulated by the cell kernel's scatter into y
+// (y = P G P x, or -P G P x for a residual): identity at fixed rows, y = b + y for a residual.
+template <typename T>
+__global__ void slit_epilogue_kernel(T* y, const T* x, const T* b, const uint8_t* mask, long long nn, int dim) {
+  const long long n = (long long)(dim + 1) * nn;
+  GSTRIDE(i, n) {
+    const long long node = i % nn;
+    const int cc = (int)(i / nn);
+    const uint8_t m = mask ? mask[node] : (uint8_t)0;
+    const bool fixed = cc < dim ? (m & kMaskU) : (m & kMaskPhi);
+    const T gx = fixed ? (b ? -x[i] : x[i]) : y[i];
+    y[i] = b ? b[i] + gx : gx;
+  }
+}
+template <typename T>
+void k_slit_epilogue(T* y, const T* x, const T* b, const uint8_t* mask, long long nn, int dim, hipStream_t s) {
+  hipLaunchKernelGGL(slit_epilogue_kernel<T>, dim3(grid_for((long long)(dim + 1) * nn)), dim3(kThreads), 0, s, y, x, b, mask,
+                     nn, dim);
+}
+template void k_slit_epilogue<double>(double*, const double*, const double*, const uint8_t*, long long, int, hipStream_t);
+template void k_slit_epilogue<float>(float*, const float*, const float*, const uint8_t*, long long, int, hipStream_t);
 void k_lumped_mass(double* ml, const Geom& g, const double* w1d, hipStream_t s) {
   hipLaunchKernelGGL(lumped_mass_kernel, dim3(grid_for(g.n_nodes)), dim3(kThreads), 0, s, ml, g, w1d);
 }
@@ -244,7 +281,7 @@ __global__ void pdas_check_kernel(double* part, const double* R, const uint8_t* 
     // index of the node along the last axis (the Dirichlet faces are normal to it)
     const unsigned q = (unsigned)i / M;
     const unsigned last = dim == 2 ? q : q / M;
-    const bool dir = dirichlet && (last == 0 || last == M - 1);
+    const bool dir = dirichlet && i < g.n_grid && (last == 0 || last == M - 1);
     const bool a = act[i] != 0;
     if (!dir) {
       for (int cc = 0; cc < dim; ++cc) {
