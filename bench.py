@@ -315,7 +315,8 @@ def time_products_3d(cfg):
 
 def spmv_study():
     """Section 6's comparison on this GPU: per degree, the matrix-free product (unconstrained,
-    cached coefficients where the level has them) against the sparse product of the assembled
+    cached coefficients where the level has them; back to back, cache-resident, and rotating
+    through contexts, HBM-resident) against the sparse product of the assembled
     Jacobian (CSR with 32-bit indices, rocSPARSE's generic SpMV, the fastest of its adaptive,
     row-split and LRB algorithms), at about the
     same number of dofs; memory per dof of each.  Prints one JSON line per case."""
@@ -331,6 +332,14 @@ def spmv_study():
         zeros = torch.zeros(ctx.n_nodes, dtype=torch.uint8, device="cuda")
         ctx.set_point(st["u"], st["phi"], st["phi_old"], zeros, st["phi_tilde"])
         t_mf = time_apply(ctx)
+        # the same product with its operands in HBM (rotating through contexts that together
+        # exceed the last-level cache), the regime the CSR matrices (>= 258 MB) are always in
+        rot = product_contexts(cfg, N_ROTATE)
+        t_mf_hbm = time_apply_rotating(rot)
+        for c_, _, _ in rot:
+            c_.close()
+        del rot
+        torch.cuda.empty_cache()
         em = ctx.element_matrices(-1)
         A = assemble_csr(em, dim, N, k)
         del em
@@ -366,7 +375,8 @@ def spmv_study():
             ncoef = 5 if dim == 2 else 8
             qd = N ** dim * P * ncoef * 8 * (64 / 49 if dim == 2 else 1)
         out = {"dim": dim, "N": N, "k": k, "n_dofs": n, "nnz": nnz, "nnz_per_row": nnz / n,
-               "mf_us": t_mf * 1e6, "spmv_us": t_sp * 1e6, "spmv_over_mf": t_sp / t_mf,
+               "mf_us": t_mf * 1e6, "mf_us_hbm": t_mf_hbm * 1e6, "spmv_us": t_sp * 1e6,
+               "spmv_over_mf": t_sp / t_mf, "spmv_over_mf_hbm": t_sp / t_mf_hbm,
                "csr_bytes_per_dof": csr_bytes / n, "spmv_GBs": (csr_bytes + 16 * n) / t_sp / 1e9,
                "mf_state_bytes_per_dof": (algorithmic_bytes_per_apply(dim, ctx.n_nodes, 8) - 16 * n) / n,
                "mf_cache_bytes_per_dof": qd / n, "csr_vs_mf_rel_diff": err, "spmv_alg": alg_best}

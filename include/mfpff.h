@@ -94,7 +94,11 @@ typedef struct {
   int level_k[MFPFF_MAX_LEVELS];    /* degree, 1 .. 4 */
   int dirichlet;                    /* 1: delta u = 0 on the faces normal to the last axis */
   double lambda, mu;                /* Lame parameters */
-  double Gc, eps, kappa;            /* toughness, length scale, degradation floor (Section 2.1) */
+  double Gc, eps, kappa;            /* toughness, length scale, degradation floor (Section 2.1):
+                                       g(phi) = (1 - kappa) phi^2 + kappa.  The model takes
+                                       0 <= kappa << 1; any kappa in (-1, 1) is accepted, and a
+                                       negative one (g < 0 where phi is small) makes G^_uu
+                                       indefinite, which the coarse solve meets with LU */
   double as_c;                      /* constant c of the active-set rule of Algorithm 1 */
   int cheb_degree;                  /* Chebyshev polynomial degree s (s-1 operator products) */
   double cheb_lo, cheb_hi;          /* interval factors (Section 3.3: 0.24, 1.2) */
@@ -169,10 +173,12 @@ mfpff_status mfpff_level_info(mfpff_ctx* ctx, int level, mfpff_level_desc* out);
  * and phi_tilde (n_nodes each; phi_tilde NULL means phi_old) and the active
  * set (n_nodes bytes) on the finest level.  Injects fields and masks to every
  * coarser level, builds the diagonals, the Chebyshev intervals (CG-Lanczos
- * estimates) and the factorised coarse blocks.  Fails with MFPFF_ERR_NUMERIC
- * when an input field holds a non-finite value or a coarse block is not
- * positive definite, and with MFPFF_ERR_ARG when the coarsest level has more
- * than 16384 dofs (its dense factorisation is allocated on first use). */
+ * estimates) and the factorised coarse blocks (Cholesky; a block that is not
+ * positive definite is inverted by Gauss-Jordan elimination with partial
+ * pivoting instead).  Fails with MFPFF_ERR_NUMERIC when an input field holds a
+ * non-finite value or a coarse block is singular (a zero pivot), and with
+ * MFPFF_ERR_ARG when the coarsest level has more than 16384 dofs (its dense
+ * factorisation is allocated on first use). */
 mfpff_status mfpff_set_linearization(mfpff_ctx* ctx, const double* u, const double* phi,
                                      const double* phi_old, const uint8_t* active,
                                      const double* phi_tilde);
@@ -216,7 +222,8 @@ mfpff_status mfpff_transfer(mfpff_ctx* ctx, int level, int direction, const doub
 
 /* Exact FP64 solve with the coarsest level operator, using the block lower-triangular structure
  * of eq. (G) that Section 3.3 points out: x_u = G^_uu^-1 r_u, x_phi = G^_phiphi^-1 (r_phi -
- * G^_phiu x_u) (the paper runs Chebyshev over the whole spectrum there instead).  r, x: device,
+ * G^_phiu x_u) (the paper runs Chebyshev over the whole spectrum there instead), each block
+ * inverse from its Cholesky factor or, where that failed, from Gauss-Jordan.  r, x: device,
  * n_dofs of level 0.  MFPFF_ERR_STATE before mfpff_set_linearization. */
 mfpff_status mfpff_coarse_solve(mfpff_ctx* ctx, const double* r, double* x);
 

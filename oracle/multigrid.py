@@ -18,9 +18,13 @@ CG.  Readings where the paper is silent:
     start vector, Ritz value of the CG-Lanczos tridiagonal
     (Saad, Section 6.7.3);
   * coarsest level: exact FP64 solve using the block lower-triangular
-    structure (Cholesky of G_uu and G_phiphi), in place of the Chebyshev
-    coarse solver the paper uses.
+    structure (Cholesky of G_uu and G_phiphi; LU with partial pivoting for
+    a block that is not positive definite, which takes kappa < 0; a
+    singular block is an error), in place of the Chebyshev coarse solver
+    the paper uses.
 """
+import warnings
+
 import numpy as np
 import scipy.linalg as sla
 import scipy.sparse as sp
@@ -223,10 +227,19 @@ class CoarseSolver:
 
     @staticmethod
     def _factor(B):
+        """Cholesky where the block is positive definite (always, for kappa >= 0 and a regular
+        state); otherwise LU with partial pivoting.  A zero pivot in the LU means a singular
+        block, which has no solve: it is reported, not returned as inf/NaN."""
         try:
             return ("chol", sla.cho_factor(B, lower=True))
         except np.linalg.LinAlgError:
-            return ("lu", sla.lu_factor(B))
+            pass
+        with np.errstate(all="ignore"), warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            lu, piv = sla.lu_factor(B)
+        if np.any(np.diag(lu) == 0.0):
+            raise np.linalg.LinAlgError("coarse block is singular: zero pivot in the LU factorisation")
+        return ("lu", (lu, piv))
 
     @staticmethod
     def _solve(f, r):

@@ -7,7 +7,9 @@
 // factored in LDS, trailing updates as tiled products), and the inverse
 // factor W = L^-1 is formed by a blocked triangular solve, so that a V-cycle
 // applies the coarse inverse as four dense matrix-vector products
-// (A^-1 = W^T W) instead of sequential substitutions.
+// (A^-1 = W^T W) instead of sequential substitutions.  A block that is not
+// positive definite is inverted explicitly by Gauss-Jordan elimination with
+// partial pivoting instead (one product per solve).
 #include <cmath>
 
 #include "internal.h"
@@ -277,6 +279,98 @@ hipError_t tri_inverse_lower(double* W, const double* L, int n, hipStream_t s) {
       dim3 grid((ncols + TB - 1) / TB, (rows + TB - 1) / TB);
       hipLaunchKernelGGL(trsm_update_kernel, grid, dim3(kThreads), 0, s, W, L, n, k0, ncols);
     }
+  }
+  return hipGetLastError();
+}
+
+// Gauss-Jordan inversion with partial pivoting, the fallback for a coarse block whose Cholesky met
+// a non-positive pivot (an indefinite block, which a negative degradation floor produces).  Step k
+// takes the row of largest |M[i][k]|, i >= k (the first one on ties), swaps it into row k, scales
+// row k by the pivot and clears column k from every other row; the same row operations turn the
+// identity into M^-1.  work[0..n) holds the multipliers of a step, work[n..n+3) the pivot value,
+// its row and the old M[k][k].  Columns left of k in M are not kept up to date: no later step
+// reads them.
+constexpr int kPivLanes = 1024;
+__global__ __launch_bounds__(kPivLanes) void gj_pivot_kernel(const double* M, int n, int k, double* work, int* info) {
+  __shared__ double sv[kPivLanes];
+  __shared__ int si[kPivLanes];
+  double best = -1.0;
+  int bi = k;
+  for (int i = k + (int)threadIdx.x; i < n; i += kPivLanes) {
+    const double v = fabs(M[(long long)i * n + k]);
+    if (v > best) {
+      best = v;
+      bi = i;
+    }
+  }
+  sv[threadIdx.x] = best;
+  si[threadIdx.x] = bi;
+  __syncthreads();
+  for (int w = kPivLanes / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      const double ov = sv[threadIdx.x + w];
+      const int oi = si[threadIdx.x + w];
+      if (ov > sv[threadIdx.x] || (ov == sv[threadIdx.x] && oi < si[threadIdx.x])) {
+        sv[threadIdx.x] = ov;
+        si[threadIdx.x] = oi;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const int p = si[0];
+    double pv = M[(long long)p * n + k];
+    if (!(sv[0] > 0.0)) {  // a zero (or NaN) column: the block is singular
+      if (*info == 0) *info = k + 1;
+      pv = 1.0;
+    }
+    work[n] = pv;
+    work[n + 1] = (double)p;
+    work[n + 2] = M[(long long)k * n + k];
+  }
+}
+
+__global__ void gj_swap_scale_kernel(double* M, double* Inv, int n, int k, double* work) {
+  const double pv = work[n];
+  const int p = (int)work[n + 1];
+  const double mkk = work[n + 2];
+  const double rp = 1.0 / pv;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x) {
+    // multiplier of row j: column k after the swap (rows k and p are the only ones written here)
+    work[j] = j == k ? 0.0 : (j == p ? mkk : M[(long long)j * n + k]);
+    const double mk = M[(long long)k * n + j], mp = M[(long long)p * n + j];
+    const double ik = Inv[(long long)k * n + j], ip = Inv[(long long)p * n + j];
+    M[(long long)p * n + j] = mk;
+    Inv[(long long)p * n + j] = ik;
+    M[(long long)k * n + j] = mp * rp;
+    Inv[(long long)k * n + j] = ip * rp;
+  }
+}
+
+__global__ void gj_eliminate_kernel(double* M, double* Inv, int n, int k, const double* f) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  const double mk = M[(long long)k * n + j], ik = Inv[(long long)k * n + j];
+  for (int i = blockIdx.y; i < n; i += gridDim.y) {
+    const double fi = f[i];
+    if (i == k || fi == 0.0) continue;
+    if (j > k) M[(long long)i * n + j] -= fi * mk;
+    Inv[(long long)i * n + j] -= fi * ik;
+  }
+}
+
+hipError_t gauss_jordan_inverse(double* Inv, double* M, int n, int* info_dev, double* work, hipStream_t s) {
+  const long long total = (long long)n * n;
+  long long nb = (total + kThreads - 1) / kThreads;
+  if (nb > 65536) nb = 65536;
+  if (nb < 1) nb = 1;
+  hipLaunchKernelGGL(eye_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, Inv, n);
+  const unsigned gx = (unsigned)((n + kThreads - 1) / kThreads);
+  const unsigned gy = (unsigned)(n < 256 ? n : 256);
+  for (int k = 0; k < n; ++k) {
+    hipLaunchKernelGGL(gj_pivot_kernel, dim3(1), dim3(kPivLanes), 0, s, (const double*)M, n, k, work, info_dev);
+    hipLaunchKernelGGL(gj_swap_scale_kernel, dim3(gx), dim3(kThreads), 0, s, M, Inv, n, k, work);
+    hipLaunchKernelGGL(gj_eliminate_kernel, dim3(gx, gy), dim3(kThreads), 0, s, M, Inv, n, k, (const double*)work);
   }
   return hipGetLastError();
 }

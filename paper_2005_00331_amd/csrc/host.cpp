@@ -121,6 +121,9 @@ struct mfpff_ctx {
   double* cs_out = nullptr;
   double* cs_t = nullptr;
   int* info_dev = nullptr;
+  // a block whose Cholesky failed holds its explicit inverse in W (WT unused): one product
+  bool coarse_lu[2] = {false, false};
+  double* lu_work = nullptr;  // multipliers and pivot of the Gauss-Jordan fallback (allocated on first use)
   double* chol_scratch = nullptr;
   // Lanczos / scratch (finest size, FP64)
   LanczosState* lst = nullptr;
@@ -502,12 +505,21 @@ void transfer(mfpff_ctx* c, int l, int dir, const T* in, T* out, bool add, T* ta
 
 void coarse_solve64(mfpff_ctx* c, const double* r, double* x) {
   const int nu = c->nu0, np = c->np0;
-  // W = L^-1 is lower triangular and W^T upper: each product reads only the stored triangle
-  k_gemv(c->cs_t, c->Wu, nu, r, nu, nu, 1.0, nullptr, GEMV_LOWER, c->s);
-  k_gemv(x, c->WuT, nu, c->cs_t, nu, nu, 1.0, nullptr, GEMV_UPPER, c->s);
+  // W = L^-1 is lower triangular and W^T upper: each product reads only the stored triangle;
+  // after the LU fallback W is the block's full inverse
+  if (c->coarse_lu[0]) {
+    k_gemv(x, c->Wu, nu, r, nu, nu, 1.0, nullptr, GEMV_FULL, c->s);
+  } else {
+    k_gemv(c->cs_t, c->Wu, nu, r, nu, nu, 1.0, nullptr, GEMV_LOWER, c->s);
+    k_gemv(x, c->WuT, nu, c->cs_t, nu, nu, 1.0, nullptr, GEMV_UPPER, c->s);
+  }
   k_gemv(c->cs_t + nu, c->Gpu, nu, x, np, nu, -1.0, r + nu, GEMV_FULL, c->s);
-  k_gemv(c->cs_t, c->Wp, np, c->cs_t + nu, np, np, 1.0, nullptr, GEMV_LOWER, c->s);
-  k_gemv(x + nu, c->WpT, np, c->cs_t, np, np, 1.0, nullptr, GEMV_UPPER, c->s);
+  if (c->coarse_lu[1]) {
+    k_gemv(x + nu, c->Wp, np, c->cs_t + nu, np, np, 1.0, nullptr, GEMV_FULL, c->s);
+  } else {
+    k_gemv(c->cs_t, c->Wp, np, c->cs_t + nu, np, np, 1.0, nullptr, GEMV_LOWER, c->s);
+    k_gemv(x + nu, c->WpT, np, c->cs_t, np, np, 1.0, nullptr, GEMV_UPPER, c->s);
+  }
   LAUNCHCHK();
 }
 
@@ -730,6 +742,29 @@ void coarse_setup(mfpff_ctx* c) {
 void coarse_join(mfpff_ctx* c) {
   for (int b = 0; b < 2; ++b) HIPCHK(hipStreamWaitEvent(c->s, c->ev_join[b], 0));
 }
+// Blocks whose Cholesky met a non-positive pivot (failed[b] != 0): extracted again from the dense
+// coarse operator and inverted by Gauss-Jordan with partial pivoting.  Only a zero pivot there
+// (a singular block) is an error.
+void coarse_lu_fallback(mfpff_ctx* c, const int* failed) {
+  const int nu = c->nu0, np = c->np0;
+  const long long n = c->lv[0].n;
+  if (!c->lu_work) c->lu_work = dalloc<double>((size_t)std::max(nu, np) + 3);
+  HIPCHK(hipMemsetAsync(c->info_dev, 0, 2 * sizeof(int), c->s));
+  if (failed[0]) {
+    k_extract_block(c->Auu, nu, c->dense, n, 0, 0, nu, nu, c->s);
+    HIPCHK(gauss_jordan_inverse(c->Wu, c->Auu, nu, c->info_dev, c->lu_work, c->s));
+  }
+  if (failed[1]) {
+    k_extract_block(c->App, np, c->dense, n, nu, nu, np, np, c->s);
+    HIPCHK(gauss_jordan_inverse(c->Wp, c->App, np, c->info_dev + 1, c->lu_work, c->s));
+  }
+  int sing[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(sing, c->info_dev, 2 * sizeof(int), hipMemcpyDeviceToHost, c->s));
+  HIPCHK(hipStreamSynchronize(c->s));
+  if (sing[0] || sing[1]) throw StatusError{MFPFF_ERR_NUMERIC, "coarse block is singular (zero pivot in the LU after the Cholesky failed)"};
+  for (int b = 0; b < 2; ++b) c->coarse_lu[b] = failed[b] != 0;
+}
+
 
 // timing event owned for one scope (destroyed on every exit path, exceptions included)
 struct ScopedEvent {
@@ -975,7 +1010,8 @@ void set_linearization(mfpff_ctx* c, const double* u, const double* phi, const d
   int info[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(info, c->info_dev, 2 * sizeof(int), hipMemcpyDeviceToHost, c->s));
   HIPCHK(hipStreamSynchronize(c->s));
-  if (info[0] || info[1]) throw StatusError{MFPFF_ERR_NUMERIC, "coarse Cholesky factorisation failed (non-positive pivot)"};
+  c->coarse_lu[0] = c->coarse_lu[1] = false;
+  if (info[0] || info[1]) coarse_lu_fallback(c, info);
   for (int l = 1; l <= c->L; ++l) {
     Level& L = c->lv[l];
     for (int b = 0; b < 2; ++b) {
@@ -1096,7 +1132,7 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
   // the slit geometry: one level (its exact coarse solve is the preconditioner), an even cell count
   if (p.slit != 0 && p.slit != 1) return MFPFF_ERR_ARG;
   if (p.slit && (p.n_levels != 1 || p.level_N[0] % 2 != 0)) return MFPFF_ERR_ARG;
-  if (!(p.eps > 0.0) || !(p.kappa >= 0.0) || !(p.cheb_hi > p.cheb_lo) || !(p.cheb_lo > 0.0)) return MFPFF_ERR_ARG;
+  if (!(p.eps > 0.0) || !(p.kappa > -1.0 && p.kappa < 1.0) || !(p.cheb_hi > p.cheb_lo) || !(p.cheb_lo > 0.0)) return MFPFF_ERR_ARG;
   for (int l = 0; l < p.n_levels; ++l) {
     if (p.level_N[l] < 1 || p.level_k[l] < 1 || p.level_k[l] > kMaxDeg) return MFPFF_ERR_ARG;
     if (l > 0) {
@@ -1262,7 +1298,7 @@ void mfpff_destroy(mfpff_ctx* c) {
     F(c->tab32[k]);
   }
   void* ps[] = {c->elem, c->finite_flag, c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
-                c->WpT, c->Gpu, c->cs_in, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lst, c->part, c->V,
+                c->WpT, c->Gpu, c->cs_in, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lu_work, c->lst, c->part, c->V,
                 c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out, c->act_prev, c->pdas_part,
                 c->phit_ext, c->react};
   for (void* p : ps) F(p);

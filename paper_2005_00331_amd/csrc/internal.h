@@ -272,6 +272,9 @@ void k_dense_set_fixed_diag(double* A, long long ld, const uint8_t* mask, long l
 void k_extract_block(double* dst, long long ldd, const double* src, long long lds, long long r0, long long c0,
                      long long nr, long long nc, hipStream_t s);
 hipError_t cholesky_lower(double* A, int n, int* info_dev, double* scratch, hipStream_t s);  // info_dev zeroed by the caller
+// Inv = M^-1 by Gauss-Jordan with partial pivoting (M overwritten; *info_dev = first zero-pivot
+// step + 1, zeroed by the caller; work holds n + 3 doubles)
+hipError_t gauss_jordan_inverse(double* Inv, double* M, int n, int* info_dev, double* work, hipStream_t s);
 hipError_t tri_inverse_lower(double* W, const double* L, int n, hipStream_t s);
 void k_transpose(double* At, const double* A, int n, hipStream_t s);
 // y = alpha A x (+ yin); GEMV_LOWER / GEMV_UPPER read only row i's entries j <= i / j >= i

@@ -90,31 +90,32 @@ __device__ __forceinline__ Eig<DIM, T> eig_sym(const T (&e)[DIM][DIM]) {
 #pragma unroll
       for (int pq = 0; pq < 3; ++pq) {
         const int p = pq == 2 ? 1 : 0, q = pq == 0 ? 1 : 2;
+        // a rotation is taken unconditionally: where A[p][q] is already zero, t = 0 makes it the
+        // identity, so every lane follows the same instruction stream (selects, no branch)
         const T apq = A[p][q];
-        if (apq != T(0)) {
-          const T tau = (A[q][q] - A[p][p]) / (T(2) * apq);
-          const T t = (tau >= T(0) ? T(1) : T(-1)) / (fabs(tau) + sqrt(T(1) + tau * tau));
-          const T cs = T(1) / sqrt(T(1) + t * t), sn = t * cs;
-          // A <- J^T A J with J the rotation in the (p, q) plane
+        const bool live = apq != T(0);
+        const T tau = live ? (A[q][q] - A[p][p]) / (T(2) * apq) : T(0);
+        const T t = live ? (tau >= T(0) ? T(1) : T(-1)) / (fabs(tau) + sqrt(T(1) + tau * tau)) : T(0);
+        const T cs = T(1) / sqrt(T(1) + t * t), sn = t * cs;
+        // A <- J^T A J with J the rotation in the (p, q) plane
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const T akp = A[k][p], akq = A[k][q];
-            A[k][p] = cs * akp - sn * akq;
-            A[k][q] = sn * akp + cs * akq;
-          }
+        for (int k = 0; k < 3; ++k) {
+          const T akp = A[k][p], akq = A[k][q];
+          A[k][p] = cs * akp - sn * akq;
+          A[k][q] = sn * akp + cs * akq;
+        }
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const T apk = A[p][k], aqk = A[q][k];
-            A[p][k] = cs * apk - sn * aqk;
-            A[q][k] = sn * apk + cs * aqk;
-          }
-          A[p][q] = A[q][p] = T(0);
+        for (int k = 0; k < 3; ++k) {
+          const T apk = A[p][k], aqk = A[q][k];
+          A[p][k] = cs * apk - sn * aqk;
+          A[q][k] = sn * apk + cs * aqk;
+        }
+        A[p][q] = A[q][p] = T(0);
 #pragma unroll
-          for (int k = 0; k < 3; ++k) {
-            const T vkp = V[k][p], vkq = V[k][q];
-            V[k][p] = cs * vkp - sn * vkq;
-            V[k][q] = sn * vkp + cs * vkq;
-          }
+        for (int k = 0; k < 3; ++k) {
+          const T vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = cs * vkp - sn * vkq;
+          V[k][q] = sn * vkp + cs * vkq;
         }
       }
     }

@@ -50,7 +50,8 @@ def test_invalid_problems_rejected_without_device(lib):
     h = ctypes.c_void_p()
     good = binding.make_problem(2, [(4, 1), (8, 1)], eps=0.25)
     for field, bad in [("dim", 5), ("n_levels", 0), ("cheb_degree", 0), ("restart", 0), ("vcycle_prec", 7),
-                       ("split", 3), ("pdas_project", 2), ("contraction", 2), ("slit", 2), ("slit", 1)]:
+                       ("split", 3), ("pdas_project", 2), ("contraction", 2), ("slit", 2), ("slit", 1), ("kappa", -1.0), ("kappa", 1.0),
+                       ("kappa", float("nan"))]:
         p = binding.make_problem(2, [(4, 1), (8, 1)], eps=0.25)
         setattr(p, field, bad)
         assert lib.mfpff_setup_mesh_levels(ctypes.byref(p), None, ctypes.byref(h)) == 1

@@ -233,9 +233,34 @@ def test_nonfinite_input_rejected():
     assert ei.value.status == 6
 
 
+@pytest.mark.parametrize("dim,N", [(2, 8), (3, 4)])
+def test_indefinite_coarse_block_takes_the_lu_path(dim, N):
+    # kappa < 0: g < 0 where phi is small, so G_uu is indefinite and its Cholesky fails; the
+    # Gauss-Jordan inverse then gives the coarse solve, against the oracle's LU solve
+    cfg = CONFIGS["C1"].with_(dim=dim, N=N, n_h_levels=1, p_coarse=(), kappa=-0.5, phi_mode="smooth")
+    inp = make_inputs(cfg, ("rhs",))
+    H = mg.Hierarchy(cfg, [(cfg.N, cfg.k)], inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
+    assert H.coarse.fu[0] == "lu"
+    ctx = _ctx(cfg, [(cfg.N, cfg.k)])
+    say("indefinite coarse block", dim, N, H.coarse.nu, "u dofs")
+    ctx.set_linearization(dev(inp["u"]), dev(inp["phi"]), dev(inp["phi_old"]), dev(inp["active"]), dev(inp["phi_tilde"]))
+    b = inp["rhs"]
+    x = host(ctx.coarse_solve(dev(b)))
+    # two correct inverses of a block with condition number up to ~5e5 agree to ~cond * 2^-53
+    assert rel_err(x, H.coarse.solve(b)) <= 1e-9
+    # the same context linearised again at phi = phi~ = 1 (g = 1, G_uu definite) is back on the
+    # Cholesky path
+    one = np.ones(cfg.n_nodes)
+    ctx.set_linearization(dev(inp["u"]), dev(one), dev(one), dev(inp["active"]), dev(one))
+    H2 = mg.Hierarchy(cfg, [(cfg.N, cfg.k)], inp["u"], one, one, inp["active"])
+    assert H2.coarse.fu[0] == "chol"
+    assert rel_err(host(ctx.coarse_solve(dev(b))), H2.coarse.solve(b)) <= 1e-10
+
+
 def test_fully_broken_material_at_rest_rejected():
     # kappa = 0, phi = phi~ = 0, u = 0: g = 0 and tr e = 0 (tension branch), so every free
-    # displacement row of G is zero and the coarse Cholesky meets a zero pivot
+    # displacement row of G is zero: the coarse Cholesky fails and the LU meets a zero pivot
+    # (the oracle rejects the same state, as a singular block)
     from paper_2005_00331_amd import MfpffError
     cfg = CONFIGS["C1"].with_(kappa=0.0)
     z = np.zeros(cfg.n_nodes)

@@ -141,6 +141,53 @@ def test_two_grid_error_operator_contracts(name, kw):
     assert rho < 0.8
 
 
+@pytest.mark.parametrize("name,kw,split", [("C2", dict(N=4, n_h_levels=1, p_coarse=()), "amor"),
+                                           ("C2", dict(N=4, n_h_levels=1, p_coarse=()), "miehe"),
+                                           ("C3", dict(N=2, n_h_levels=1, p_coarse=()), "amor"),
+                                           ("C3", dict(N=2, n_h_levels=1, p_coarse=()), "miehe")])
+def test_coarse_blocks_are_positive_semidefinite(name, kw, split):
+    # the premise of the Cholesky-only coarse solve: on a random state, with phi~ outside [0, 1]
+    # (linear extrapolation can leave it) and no Dirichlet rows, both diagonal blocks of G are
+    # symmetric with no eigenvalue below -1e-12 of the largest (g >= 0, convex energies in e)
+    cfg = CONFIGS[name].with_(split=split, dirichlet=False, **kw)
+    inp = make_inputs(cfg)
+    rng = np.random.default_rng(11)
+    pt = rng.uniform(-0.3, 1.3, cfg.n_nodes)
+    u = rng.standard_normal((cfg.dim, cfg.n_nodes)) * 1e-3
+    mesh = fe.Mesh(cfg.dim, cfg.N, cfg.k)
+    A = op.assemble_jacobian(mesh, op.material_of(cfg), u, inp["phi"], pt).toarray()
+    nu = cfg.dim * mesh.n_nodes
+    for B in (A[:nu, :nu], A[nu:, nu:]):
+        assert np.abs(B - B.T).max() <= 1e-13 * np.abs(B).max()
+        ev = np.linalg.eigvalsh(B)
+        assert ev.min() >= -1e-12 * ev.max()
+
+
+def test_singular_coarse_block_is_rejected():
+    # kappa = 0 and phi = phi~ = 0 at u = 0: g = 0 and tr e = 0 (tension branch), so every free
+    # displacement row of G is zero; the coarse solve reports it instead of returning inf/NaN
+    cfg = CONFIGS["C1"].with_(N=4, n_h_levels=1, p_coarse=(), kappa=0.0)
+    z = np.zeros(cfg.n_nodes)
+    with pytest.raises(np.linalg.LinAlgError, match="singular"):
+        mg.Hierarchy(cfg, [(cfg.N, cfg.k)], np.zeros((cfg.dim, cfg.n_nodes)), z, z, np.zeros(cfg.n_nodes, np.uint8))
+
+
+def test_indefinite_coarse_block_takes_the_lu_path():
+    # kappa < 0 makes g negative where phi is small, so G_uu is indefinite: the Cholesky fails,
+    # the LU solves, and the result satisfies the block lower-triangular system exactly
+    cfg = CONFIGS["C1"].with_(N=8, n_h_levels=1, p_coarse=(), kappa=-0.5, phi_mode="smooth")
+    inp = make_inputs(cfg, ("rhs",))
+    H = mg.Hierarchy(cfg, [(cfg.N, cfg.k)], inp["u"], inp["phi"], inp["phi_tilde"], inp["active"])
+    cs = H.coarse
+    assert cs.fu[0] == "lu" and cs.fp[0] == "chol"
+    assert np.linalg.eigvalsh(cs.Auu).min() < 0
+    b = inp["rhs"]
+    x = cs.solve(b)
+    nu = cs.nu
+    Lx = np.concatenate([cs.Auu @ x[:nu], cs.Apu @ x[:nu] + cs.App @ x[nu:]])
+    assert np.abs(Lx - b).max() <= 1e-10 * np.abs(b).max()
+
+
 # ------------------------------------------------------------- FGMRES
 def test_fgmres_against_direct_solve_nonsymmetric():
     rng = np.random.default_rng(4)
