@@ -97,7 +97,6 @@ struct mfpff_ctx {
   std::vector<Level> lv;
   Tables<double>* tab64[kMaxDeg + 1] = {};
   Tables<float>* tab32[kMaxDeg + 1] = {};
-  Tables<double> tabh[kMaxDeg + 1] = {};  // host copies (by-value kernel arguments)
   double* w1d = nullptr;  // integrals of the finest-degree 1D basis functions
   double* ml = nullptr;   // lumped phi mass on the finest level
   // transfer temporaries (finest-level size)
@@ -121,10 +120,10 @@ struct mfpff_ctx {
   double* cs_out = nullptr;
   double* cs_t = nullptr;
   int* info_dev = nullptr;
+  double* chol_scratch = nullptr;
   // a block whose Cholesky failed holds its explicit inverse in W (WT unused): one product
   bool coarse_lu[2] = {false, false};
   double* lu_work = nullptr;  // multipliers and pivot of the Gauss-Jordan fallback (allocated on first use)
-  double* chol_scratch = nullptr;
   // Lanczos / scratch (finest size, FP64)
   LanczosState* lst = nullptr;
   double* s64[5] = {};
@@ -317,7 +316,7 @@ const Tables<float>* tab<float>(mfpff_ctx* c, int k) { return c->tab32[k]; }
 // 2D owner-computes launch: row-shared cell kernel for Q1/Q2, LDS tile kernel otherwise
 template <typename T>
 void launch_2d(mfpff_ctx* c, const Level& L, int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e) {
-  if (L.g.k <= 2) HIPCHK(launch_rowcell_2d<T>(mode, epi, a, e, c->tabh[L.g.k], tab<T>(c, L.g.k), c->s));
+  if (L.g.k <= 2) HIPCHK(launch_rowcell_2d<T>(mode, epi, a, e, c->s));
   else HIPCHK(launch_tile_2d<T>(mode, epi, a, e, tab<T>(c, L.g.k), c->s));
 }
 
@@ -742,6 +741,7 @@ void coarse_setup(mfpff_ctx* c) {
 void coarse_join(mfpff_ctx* c) {
   for (int b = 0; b < 2; ++b) HIPCHK(hipStreamWaitEvent(c->s, c->ev_join[b], 0));
 }
+
 // Blocks whose Cholesky met a non-positive pivot (failed[b] != 0): extracted again from the dense
 // coarse operator and inverted by Gauss-Jordan with partial pivoting.  Only a zero pivot there
 // (a singular block) is an error.
@@ -764,7 +764,6 @@ void coarse_lu_fallback(mfpff_ctx* c, const int* failed) {
   if (sing[0] || sing[1]) throw StatusError{MFPFF_ERR_NUMERIC, "coarse block is singular (zero pivot in the LU after the Cholesky failed)"};
   for (int b = 0; b < 2; ++b) c->coarse_lu[b] = failed[b] != 0;
 }
-
 
 // timing event owned for one scope (destroyed on every exit path, exceptions included)
 struct ScopedEvent {
@@ -1203,7 +1202,6 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
             tf.C[i][j] = (float)t.C[i][j];
           }
         }
-        c->tabh[k] = t;
         c->tab64[k] = dalloc<Tables<double>>(1);
         c->tab32[k] = dalloc<Tables<float>>(1);
         HIPCHK(hipMemcpy(c->tab64[k], &t, sizeof(t), hipMemcpyHostToDevice));

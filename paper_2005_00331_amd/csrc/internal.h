@@ -146,8 +146,7 @@ template <typename T>
 hipError_t launch_tile_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<T>* tab, hipStream_t s);
 long long tile_blocks_2d(const Geom& g);
 template <typename T>
-hipError_t launch_rowcell_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<double>& t64,
-                             const Tables<T>* tabd, hipStream_t s);
+hipError_t launch_rowcell_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, hipStream_t s);
 long long rowcell_blocks_2d(const Geom& g);
 
 // ---- launchers (cell_kernel.hip)
@@ -272,10 +271,10 @@ void k_dense_set_fixed_diag(double* A, long long ld, const uint8_t* mask, long l
 void k_extract_block(double* dst, long long ldd, const double* src, long long lds, long long r0, long long c0,
                      long long nr, long long nc, hipStream_t s);
 hipError_t cholesky_lower(double* A, int n, int* info_dev, double* scratch, hipStream_t s);  // info_dev zeroed by the caller
+hipError_t tri_inverse_lower(double* W, const double* L, int n, hipStream_t s);
 // Inv = M^-1 by Gauss-Jordan with partial pivoting (M overwritten; *info_dev = first zero-pivot
 // step + 1, zeroed by the caller; work holds n + 3 doubles)
 hipError_t gauss_jordan_inverse(double* Inv, double* M, int n, int* info_dev, double* work, hipStream_t s);
-hipError_t tri_inverse_lower(double* W, const double* L, int n, hipStream_t s);
 void k_transpose(double* At, const double* A, int n, hipStream_t s);
 // y = alpha A x (+ yin); GEMV_LOWER / GEMV_UPPER read only row i's entries j <= i / j >= i
 enum GemvShape : int { GEMV_FULL = 0, GEMV_LOWER = 1, GEMV_UPPER = 2 };

@@ -27,11 +27,34 @@ namespace mfpff {
 
 namespace {
 
-template <int NP, typename T>
-struct Tab2 {
-  T B[NP][NP];  // [q][i]
-  T D[NP][NP];
-  T w[NP];
+// The 1D tables of Q1 and Q2 as compile-time constants (the same quantities the library builds at
+// run time for every degree): Gauss-Legendre points on [0, 1], 1/2 -+ sqrt(3)/6 for two points and
+// 1/2, 1/2 -+ sqrt(15)/10 for three, equispaced Lagrange nodes.  B[q][i] = l_i(x_q),
+// D[q][i] = l_i'(x_q), w the Gauss weights.  As constants they need no scalar registers (the
+// by-value table spilled them into vector lanes), and the compiler folds the zeros and units:
+// the middle Gauss point of Q2 is a node, where B is a unit row and D = (-1, 0, 1).
+template <int NP>
+struct RowTab;
+template <>
+struct RowTab<2> {
+  static constexpr double s = 0.28867513459481288225;  // sqrt(3) / 6
+  static __device__ constexpr double x(int q) { return q == 0 ? 0.5 - s : 0.5 + s; }
+  static __device__ constexpr double B(int q, int i) { return i == 0 ? 1.0 - x(q) : x(q); }
+  static __device__ constexpr double D(int, int i) { return i == 0 ? -1.0 : 1.0; }
+  static __device__ constexpr double w(int) { return 0.5; }
+};
+template <>
+struct RowTab<3> {
+  static constexpr double s = 0.38729833462074168852;  // sqrt(15) / 10
+  static __device__ constexpr double x(int q) { return q == 0 ? 0.5 - s : (q == 1 ? 0.5 : 0.5 + s); }
+  // l_0 = 2 (x - 1/2)(x - 1), l_1 = 4 x (1 - x), l_2 = 2 x (x - 1/2)
+  static __device__ constexpr double B(int q, int i) {
+    return i == 0 ? 2.0 * (x(q) - 0.5) * (x(q) - 1.0) : (i == 1 ? 4.0 * x(q) * (1.0 - x(q)) : 2.0 * x(q) * (x(q) - 0.5));
+  }
+  static __device__ constexpr double D(int q, int i) {
+    return i == 0 ? 4.0 * x(q) - 3.0 : (i == 1 ? 4.0 - 8.0 * x(q) : 4.0 * x(q) - 1.0);
+  }
+  static __device__ constexpr double w(int q) { return q == 1 ? 4.0 / 9.0 : 5.0 / 18.0; }
 };
 
 }  // namespace
@@ -58,7 +81,7 @@ long long rowcell_qdata_len(const Geom& g, int split) {
 // and the phase coefficient, n_qcoef_miehe<2>() per point); MODE_QDATA writes either by a.m.split
 template <int K, typename T, int MODE, int EPI, bool QD, bool EARLY, int SPLIT = SPLIT_AMOR>
 __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_eu(EARLY || MODE == MODE_QDATA ? 1 : (SPLIT == SPLIT_MIEHE ? 3 : 4)))) void rowcell_kernel_2d(
-    CellArgs<T> a, Epilogue<T> e, Tab2<K + 1, T> tb, const Tables<T>* __restrict__ tabd) {
+    CellArgs<T> a, Epilogue<T> e) {
   constexpr int NP = K + 1;
   constexpr int NT = kRowCells * NP;
   constexpr int AN = K * kRowTile + 1;      // node box per direction
@@ -85,16 +108,22 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   const bool valid = cx >= 0 && cy >= 0 && cx < cx1 && cy < cy1;
   for (int i = tid; i < 3 * AN * AN; i += NT) acc[i] = T(0);
 
-  // table entries of row / column r (uniform loads from the device copy of the tables)
+  using TB = RowTab<NP>;
+  // table entries of row / column r (r is uniform per wavefront: scalar selects of constants)
   T Br[NP], Dr[NP], Bc[NP], Dc[NP];  // B[r][i], D[r][i], B[q][r], D[q][r]
+  T wr = T(0);
 #pragma unroll
-  for (int i = 0; i < NP; ++i) {
-    Br[i] = tabd->B[r][i];
-    Dr[i] = tabd->D[r][i];
-    Bc[i] = tabd->B[i][r];
-    Dc[i] = tabd->D[i][r];
+  for (int rr = 0; rr < NP; ++rr) {
+    if (r != rr) continue;
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      Br[i] = (T)TB::B(rr, i);
+      Dr[i] = (T)TB::D(rr, i);
+      Bc[i] = (T)TB::B(i, rr);
+      Dc[i] = (T)TB::D(i, rr);
+    }
+    wr = (T)TB::w(rr);
   }
-  const T wr = tabd->w[r];
 
   // ---- node row r of the cell: u_0, u_1, phi, phi~, x_0, x_1, x_phi (x zeroed at fixed dofs).
   // Every load is unconditional (invalid lanes read node 0 / their own tile slot) and the
@@ -240,8 +269,9 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
       T s = 0, sd = 0;
 #pragma unroll
       for (int i0 = 0; i0 < NP; ++i0) {
-        s += tb.B[q0][i0] * v[i0];
-        sd += tb.D[q0][i0] * v[i0];
+        // terms whose table entry is zero are dropped (constant after unrolling): x + 0 v = x
+        if (TB::B(q0, i0) != 0.0) s += (T)TB::B(q0, i0) * v[i0];
+        if (TB::D(q0, i0) != 0.0) sd += (T)TB::D(q0, i0) * v[i0];
       }
       t[q0] = s;
       td[q0] = sd;
@@ -412,7 +442,7 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   T F0x[NP], F1x[NP], F0y[NP], F1y[NP], Fv[NP], F0p[NP], F1p[NP];
 #pragma unroll
   for (int q0 = 0; q0 < NP; ++q0) {
-    const T wq = tb.w[q0] * wr;  // JxW / h^2
+    const T wq = (T)TB::w(q0) * wr;  // JxW / h^2
     const T dxx = gx00[q0] * ih, dyy = gx11[q0] * ih;
     const T dxy = T(0.5) * (gx01[q0] + gx10[q0]) * ih;
     const T dt = dxx + dyy;
@@ -456,8 +486,9 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
       T sa = 0, sb = 0;
 #pragma unroll
       for (int q0 = 0; q0 < NP; ++q0) {
-        sa += (has_v ? tb.B[q0][i0] * Fvv[q0] : T(0)) + tb.D[q0][i0] * F0[q0];
-        sb += tb.B[q0][i0] * F1[q0];
+        if (has_v && TB::B(q0, i0) != 0.0) sa += (T)TB::B(q0, i0) * Fvv[q0];
+        if (TB::D(q0, i0) != 0.0) sa += (T)TB::D(q0, i0) * F0[q0];
+        if (TB::B(q0, i0) != 0.0) sb += (T)TB::B(q0, i0) * F1[q0];
       }
       ka[i0] = sa;
       kb[i0] = sb;
@@ -503,16 +534,7 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
 }
 
 template <int K, typename T>
-static hipError_t launch_row_k(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<double>& t64,
-                               const Tables<T>* tabd, hipStream_t s) {
-  Tab2<K + 1, T> tb;
-  for (int q = 0; q <= K; ++q) {
-    tb.w[q] = (T)t64.w[q];
-    for (int i = 0; i <= K; ++i) {
-      tb.B[q][i] = (T)t64.B[q][i];
-      tb.D[q][i] = (T)t64.D[q][i];
-    }
-  }
+static hipError_t launch_row_k(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, hipStream_t s) {
   const long long nb = rowcell_blocks_2d(a.g);
   const bool early = nb <= 512;
   dim3 grid((unsigned)nb), block(kRowCells * (K + 1));
@@ -521,19 +543,19 @@ static hipError_t launch_row_k(int mode, int epi, const CellArgs<T>& a, const Ep
 #define MFPFF_R(MD, EP)                                                                                              \
   if (mode == MD && epi == EP) {                                                                                     \
     if (miehe && early)                                                                                              \
-      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, true, SPLIT_MIEHE>), grid, block, 0, s, a, e, tb, tabd); \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, true, SPLIT_MIEHE>), grid, block, 0, s, a, e); \
     else if (miehe)                                                                                                  \
-      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, false, SPLIT_MIEHE>), grid, block, 0, s, a, e, tb, tabd); \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, false, SPLIT_MIEHE>), grid, block, 0, s, a, e); \
     else if (a.qd && early)                                                                                          \
-      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, true>), grid, block, 0, s, a, e, tb, tabd);          \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, true>), grid, block, 0, s, a, e);          \
     else if (a.qd)                                                                                                   \
-      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, false>), grid, block, 0, s, a, e, tb, tabd);         \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, true, false>), grid, block, 0, s, a, e);         \
     else                                                                                                             \
-      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, false, false>), grid, block, 0, s, a, e, tb, tabd);        \
+      hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MD, EP, false, false>), grid, block, 0, s, a, e);        \
     return hipGetLastError();                                                                                        \
   }
   if (mode == MODE_QDATA) {
-    hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MODE_QDATA, EPI_APPLY, false, false>), grid, block, 0, s, a, e, tb, tabd);
+    hipLaunchKernelGGL((rowcell_kernel_2d<K, T, MODE_QDATA, EPI_APPLY, false, false>), grid, block, 0, s, a, e);
     return hipGetLastError();
   }
   MFPFF_R(MODE_APPLY, EPI_APPLY)
@@ -546,17 +568,14 @@ static hipError_t launch_row_k(int mode, int epi, const CellArgs<T>& a, const Ep
 }
 
 template <typename T>
-hipError_t launch_rowcell_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, const Tables<double>& t64,
-                             const Tables<T>* tabd, hipStream_t s) {
+hipError_t launch_rowcell_2d(int mode, int epi, const CellArgs<T>& a, const Epilogue<T>& e, hipStream_t s) {
   if (a.g.dim != 2) return hipErrorInvalidValue;
-  if (a.g.k == 1) return launch_row_k<1, T>(mode, epi, a, e, t64, tabd, s);
-  if (a.g.k == 2) return launch_row_k<2, T>(mode, epi, a, e, t64, tabd, s);
+  if (a.g.k == 1) return launch_row_k<1, T>(mode, epi, a, e, s);
+  if (a.g.k == 2) return launch_row_k<2, T>(mode, epi, a, e, s);
   return hipErrorInvalidValue;
 }
 
-template hipError_t launch_rowcell_2d<double>(int, int, const CellArgs<double>&, const Epilogue<double>&, const Tables<double>&,
-                                              const Tables<double>*, hipStream_t);
-template hipError_t launch_rowcell_2d<float>(int, int, const CellArgs<float>&, const Epilogue<float>&, const Tables<double>&,
-                                             const Tables<float>*, hipStream_t);
+template hipError_t launch_rowcell_2d<double>(int, int, const CellArgs<double>&, const Epilogue<double>&, hipStream_t);
+template hipError_t launch_rowcell_2d<float>(int, int, const CellArgs<float>&, const Epilogue<float>&, hipStream_t);
 
 }  // namespace mfpff
