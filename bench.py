@@ -458,6 +458,7 @@ def main():
                          "the FP64 and the FP32 V-cycle, printed as one record")
     ap.add_argument("--restart", type=int, default=None, help="with --solve: FGMRES restart length (default: the workload's)")
     ap.add_argument("--cheb-degree", type=int, default=None, help="with --solve: Chebyshev degree (default: the workload's)")
+    ap.add_argument("--max-iter", type=int, default=5000, help="with --solve: FGMRES iteration cap")
     ap.add_argument("--contraction", default=None, choices=("valu", "mfma"),
                     help="with --solve or --apply-only: 3D Q3/Q4 contractions on the vector unit or the matrix cores")
     ap.add_argument("--apply-only", action="store_true",
@@ -477,7 +478,7 @@ def main():
         print(json.dumps(time_autograd(CONFIGS["C5"])), flush=True)
         return
     if args.solve:
-        cfg = CONFIGS[args.solve].with_(max_iter=5000)
+        cfg = CONFIGS[args.solve].with_(max_iter=args.max_iter)
         for key, val in (("restart", args.restart), ("cheb_degree", args.cheb_degree), ("contraction", args.contraction)):
             if val is not None:
                 cfg = cfg.with_(**{key: val})
