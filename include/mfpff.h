@@ -147,7 +147,8 @@ typedef struct {
  * `prob` is read during the call only; `hip_stream` is a hipStream_t (NULL: the default stream)
  * on the current device, which every later call of the context uses.  On success *out owns every
  * device allocation.  MFPFF_ERR_ARG for an invalid description, including a level with 2^31 or
- * more dofs; MFPFF_ERR_OOM when device memory runs out. */
+ * more dofs or a 2D Q1/Q2 level with 2^28 or more nodes; MFPFF_ERR_OOM when device memory runs
+ * out. */
 mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream, mfpff_ctx** out);
 
 /* Release a context and everything it owns.  NULL is ignored.  (Library housekeeping; no passage
@@ -156,6 +157,14 @@ void mfpff_destroy(mfpff_ctx* ctx);
 
 /* Message describing the last failure on this context ("" if none).  (Library housekeeping.) */
 const char* mfpff_last_error(const mfpff_ctx* ctx);
+
+/* Debug kernel build (sources compiled with -DMFPFF_BOUNDS, libmfpff_bounds.so): the kernels check
+ * every node, cell and transfer index they compute against its range, count an index outside it
+ * and use 0 in its place (reported, never a memory fault).  Returns the number counted since the
+ * library was loaded, after synchronising the device; -1 from the regular build, which has no
+ * checks; -2 if the counters cannot be read.  For the library's own tests, not for production
+ * callers. */
+long long mfpff_debug_bounds_hits(void);
 
 /* Number of nodes and of dofs ((dim+1) * n_nodes, component-blocked) of level `level`
  * (0 = coarsest .. n_levels-1 = finest): the Q_k nodal dofs of Section 3.1 on that level.  Host only: no device work, no synchronisation.

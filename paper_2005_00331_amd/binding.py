@@ -11,7 +11,8 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmfpff.so")
+# MFPFF_LIB selects another build of the library (the bounds-checking debug build in its test)
+LIB_PATH = os.environ.get("MFPFF_LIB", os.path.join(_HERE, "libmfpff.so"))
 MAX_LEVELS = 16
 
 F64, F32 = 0, 1
@@ -120,6 +121,7 @@ EXPORTS = [
     "mfpff_vcycle", "mfpff_gmres_solve", "mfpff_residual", "mfpff_residual_param_vjp", "mfpff_active_set",
     "mfpff_residual_param_vjp_noalloc",
     "mfpff_newton_step", "mfpff_pdas_solve", "mfpff_element_matrices", "mfpff_load_step", "mfpff_sizes",
+    "mfpff_debug_bounds_hits",
 ]
 
 _lib = None
@@ -157,6 +159,7 @@ def load_library(path=LIB_PATH):
         "mfpff_element_matrices": ([VP, I, P], I),
         "mfpff_load_step": ([VP, P, P, P, P, ctypes.POINTER(D), P, I, D, ctypes.POINTER(LoadInfo)], I),
         "mfpff_sizes": ([VP, I, ctypes.POINTER(ctypes.c_size_t), ctypes.POINTER(ctypes.c_size_t)], I),
+        "mfpff_debug_bounds_hits": ([], ctypes.c_longlong),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)

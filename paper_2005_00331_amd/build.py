@@ -16,16 +16,27 @@ CXXFLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
             "-Wno-unused-command-line-argument"]
 
 
-def build(verbose=False, jobs=8):
-    """Compile every source to an object in _build/ (in parallel), then link the shared library."""
-    bdir = os.path.join(HERE, "_build")
+VARIANTS = {
+    # the library the package loads
+    "release": ("_build", LIB, []),
+    # debug kernel build: every computed node, cell and transfer index checked against its range
+    # (bounds.h); loaded only by its own test, through MFPFF_LIB
+    "bounds": ("_build_bounds", os.path.join(HERE, "libmfpff_bounds.so"), ["-DMFPFF_BOUNDS"]),
+}
+
+
+def build(verbose=False, jobs=8, variant="release"):
+    """Compile every source to an object in the variant's build folder (in parallel), then link
+    the variant's shared library."""
+    sub, lib, extra = VARIANTS[variant]
+    bdir = os.path.join(HERE, sub)
     os.makedirs(bdir, exist_ok=True)
     procs, objs = [], []
     for src in SOURCES:
         obj = os.path.join(bdir, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
         lang = ["-x", "hip"] if src.endswith(".cpp") else []
-        cmd = [HIPCC, *CXXFLAGS, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *CXXFLAGS, *extra, *lang, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
@@ -40,12 +51,12 @@ def build(verbose=False, jobs=8):
             sys.stderr.write(text)
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
-    tmp = LIB + ".tmp"
+    tmp = lib + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, variant="bounds" if "--bounds" in sys.argv else "release"))

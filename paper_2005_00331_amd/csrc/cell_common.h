@@ -8,6 +8,7 @@
 // transposed collocation and basis sweeps (Section 3.4: the element operator
 // is evaluated through the tensor-product structure of the unit cell).
 #pragma once
+#include "bounds.h"
 #include "internal.h"
 #include "miehe.h"
 
@@ -82,7 +83,7 @@ __device__ __forceinline__ long long node_of(const Geom& g, long long cell, int 
   // that lie below x = 1/2 (the tip at x = 1/2 is shared)
   if (g.slit && clast == N / 2 && ilast == 0 && K * cx + i0 < K * N / 2)
     node = g.n_grid + (K * cx + i0) + (DIM == 3 ? (K * N / 2) * (K * cy + i1) : 0);
-  return node;
+  return MFPFF_IN(node, g.n_nodes);
 }
 
 template <int NP, typename T>

@@ -543,7 +543,7 @@ __global__ __launch_bounds__(kThreads) void gather3d_kernel(const T* __restrict_
   for (int kz = 0; kz < nz; ++kz)
     for (int ky = 0; ky < ny; ++ky)
       for (int kx = 0; kx < nx; ++kx) {
-        const long long cell = cx[kx] + (long long)N * (cy[ky] + (long long)N * cz[kz]);
+        const long long cell = MFPFF_IN(cx[kx] + (long long)N * (cy[ky] + (long long)N * cz[kz]), (long long)N * N * N);
         const int p = lx[kx] + NP * (ly[ky] + NP * lz[kz]);
         const long long blk = cell / CPB;
         const T* src = E + (blk * NC * P + p) * CPB + (cell - blk * CPB);
@@ -609,3 +609,5 @@ template hipError_t launch_cell<float>(int, const CellArgs<float>&, const Tables
 template hipError_t launch_diag<double>(const CellArgs<double>&, const Tables<double>*, hipStream_t);
 
 }  // namespace mfpff
+
+MFPFF_BOUNDS_READER(bounds_hits_cell)

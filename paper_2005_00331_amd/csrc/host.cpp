@@ -132,6 +132,7 @@ struct mfpff_ctx {
   // GMRES
   int m = 30;
   double* V = nullptr;
+  long long ldv = 0;  // stride of the basis vectors in V
   double* Z = nullptr;
   double* gw = nullptr;
   double* gr = nullptr;
@@ -799,7 +800,10 @@ void ensure_gmres(mfpff_ctx* c) {
   if (c->V) return;
   const long long n = c->lv[c->L].n;
   c->m = c->prob.restart;
-  c->V = dalloc<double>((size_t)(c->m + 1) * n);
+  // basis vectors 512-byte aligned (stride a multiple of 64 elements): the orthogonalisation
+  // passes read them two elements per lane
+  c->ldv = (n + 63) / 64 * 64;
+  c->V = dalloc<double>((size_t)(c->m + 1) * c->ldv);
   c->Z = dalloc<double>((size_t)c->m * n);
   c->gw = dalloc<double>(n);
   c->gr = dalloc<double>(n);
@@ -844,7 +848,7 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
   void* vb = c->lv[c->L].w[WB];
   // step j: z_j = V(v_j), w = G^ z_j, CGS2 against v_0..v_j into buffer j % 2, copied to the host
   auto arnoldi = [&](int j) {
-    double* vj = c->V + (size_t)j * n;
+    double* vj = c->V + (size_t)j * c->ldv;
     double* zj = c->Z + (size_t)j * n;
     double* hb = c->hdev + (j & 1) * kHBuf;
     double *h1 = hb, *h2 = hb + 80, *hn = hb + 160;
@@ -852,16 +856,16 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
     apply_op<double>(c, c->L, MODE_APPLY, zj, c->gw, nullptr);
     if (j + 1 <= kOrthMax) {
       // three passes over V (each with all basis vectors at once)
-      k_orth_pass(0, c->gw, c->V, n, j + 1, nullptr, c->part, h1, n, c->s);
-      k_orth_pass(1, c->gw, c->V, n, j + 1, h1, c->part, h2, n, c->s);
-      k_orth_pass(2, c->gw, c->V, n, j + 1, h2, c->part, hn, n, c->s);
+      k_orth_pass(0, c->gw, c->V, c->ldv, j + 1, nullptr, c->part, h1, n, c->s);
+      k_orth_pass(1, c->gw, c->V, c->ldv, j + 1, h1, c->part, h2, n, c->s);
+      k_orth_pass(2, c->gw, c->V, c->ldv, j + 1, h2, c->part, hn, n, c->s);
     } else {
-      k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
+      k_multidot_partials(c->part, c->V, c->ldv, j + 1, c->gw, n, c->s);
       k_multidot_finish(h1, c->part, nb, j + 1, c->s);
-      k_maxpy_dev(c->gw, c->V, n, j + 1, h1, -1.0, n, c->s);
-      k_multidot_partials(c->part, c->V, n, j + 1, c->gw, n, c->s);
+      k_maxpy_dev(c->gw, c->V, c->ldv, j + 1, h1, -1.0, n, c->s);
+      k_multidot_partials(c->part, c->V, c->ldv, j + 1, c->gw, n, c->s);
       k_multidot_finish(h2, c->part, nb, j + 1, c->s);
-      k_maxpy_dev(c->gw, c->V, n, j + 1, h2, -1.0, n, c->s);
+      k_maxpy_dev(c->gw, c->V, c->ldv, j + 1, h2, -1.0, n, c->s);
       k_multidot_partials(c->part, c->gw, n, 1, c->gw, n, c->s);
       k_multidot_finish(hn, c->part, nb, 1, c->s);
     }
@@ -890,7 +894,7 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
     for (int j = 0; j < m; ++j) {
       if (j + 1 < m) {
         // queue step j+1: v_{j+1} = w / |w| with |w|^2 from buffer j % 2
-        k_scale_rsqrt_dev(c->V + (size_t)(j + 1) * n, c->gw, c->hdev + (j & 1) * kHBuf + 160, n, c->s, vb, c->f32);
+        k_scale_rsqrt_dev(c->V + (size_t)(j + 1) * c->ldv, c->gw, c->hdev + (j & 1) * kHBuf + 160, n, c->s, vb, c->f32);
         arnoldi(j + 1);
       }
       HIPCHK(hipEventSynchronize(c->hev[j & 1]));
@@ -1114,6 +1118,19 @@ void param_vjp(mfpff_ctx* c, const double* u, const double* phi, const double* p
 }
 }  // namespace
 
+// per-file counters of the bounds-checking build (bounds.h)
+#ifdef MFPFF_BOUNDS
+namespace mfpff {
+unsigned int bounds_hits_cell();
+unsigned int bounds_hits_linecell();
+unsigned int bounds_hits_mfma();
+unsigned int bounds_hits_rowcell();
+unsigned int bounds_hits_tile();
+unsigned int bounds_hits_transfer();
+unsigned int bounds_hits_vector();
+}  // namespace mfpff
+#endif
+
 extern "C" {
 
 mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream, mfpff_ctx** out) {
@@ -1160,6 +1177,9 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
       L.nn = L.g.n_nodes;
       L.n = (long long)(d + 1) * L.nn;
       if (L.n >= (1LL << 31)) throw StatusError{MFPFF_ERR_ARG, "a level with 2^31 or more dofs is not supported"};
+      // the 2D Q1/Q2 kernel addresses nodes by 32-bit byte offsets
+      if (d == 2 && L.g.k <= 2 && L.nn >= (1LL << 28))
+        throw StatusError{MFPFF_ERR_ARG, "a 2D Q1/Q2 level with 2^28 or more nodes is not supported"};
       L.lin = dalloc<double>((size_t)(d + 2) * L.nn);
       L.mask = dalloc<uint8_t>(L.nn);
       L.dinv = dalloc<double>(L.n);
@@ -1315,6 +1335,23 @@ void mfpff_destroy(mfpff_ctx* c) {
 }
 
 const char* mfpff_last_error(const mfpff_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+long long mfpff_debug_bounds_hits(void) {
+#ifdef MFPFF_BOUNDS
+  using namespace mfpff;
+  if (hipDeviceSynchronize() != hipSuccess) return -2;
+  const unsigned int h[] = {bounds_hits_cell(), bounds_hits_linecell(), bounds_hits_mfma(), bounds_hits_rowcell(),
+                            bounds_hits_tile(), bounds_hits_transfer(), bounds_hits_vector()};
+  long long sum = 0;
+  for (unsigned int v : h) {
+    if (v == ~0u) return -2;
+    sum += v;
+  }
+  return sum;
+#else
+  return -1;
+#endif
+}
 
 mfpff_status mfpff_sizes(const mfpff_ctx* c, int level, size_t* n_nodes, size_t* n_dofs) {
   if (!c || !n_nodes || !n_dofs || level < 0 || level > c->L) return MFPFF_ERR_ARG;

@@ -105,9 +105,10 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
   uint8_t mk[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
-    mk[i] = a.mask ? a.mask[n0 + i] : (uint8_t)0;
+    const long long nd = MFPFF_IN(n0 + i, nn);
+    mk[i] = a.mask ? a.mask[nd] : (uint8_t)0;
 #pragma unroll
-    for (int f = 0; f < NC; ++f) xl[f][i] = a.x[f * nn + n0 + i];
+    for (int f = 0; f < NC; ++f) xl[f][i] = a.x[f * nn + nd];
   }
 #pragma unroll
   for (int i = 0; i < NP; ++i) {
@@ -393,3 +394,5 @@ template hipError_t launch_linecell<double>(int, const CellArgs<double>&, const 
 template hipError_t launch_linecell<float>(int, const CellArgs<float>&, const Tables<float>*, hipStream_t);
 
 }  // namespace mfpff
+
+MFPFF_BOUNDS_READER(bounds_hits_linecell)

@@ -21,6 +21,7 @@
 // threads then apply the epilogue of the operation (product, residual with the
 // Chebyshev start, Chebyshev step).
 #include "internal.h"
+#include "bounds.h"
 #include "miehe.h"
 
 namespace mfpff {
@@ -58,6 +59,18 @@ struct RowTab<3> {
 };
 
 }  // namespace
+
+// element at a 32-bit byte offset from a uniform base: the address is the scalar base plus one
+// vector offset (no 64-bit address arithmetic per access); the set-up keeps 2D Q1/Q2 levels
+// below 2^28 nodes, so node * 8 fits in 32 bits
+template <typename T>
+__device__ __forceinline__ T& at_off(T* base, uint32_t boff) {
+  return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + boff);
+}
+template <typename T>
+__device__ __forceinline__ const T& at_off(const T* base, uint32_t boff) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + boff);
+}
 
 constexpr int kRowTile = 8;              // computed cells per direction per workgroup
 constexpr int kRowOwn = kRowTile - 1;    // owned cells per direction
@@ -100,7 +113,7 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   // range of tiles, so tiles that share halo nodes share that XCD's L2 (the cached coefficients
   // stay indexed by the hardware block, the same in the writing and the reading launch)
   const unsigned G = gridDim.x, bb = blockIdx.x, xcd = bb % 8, per = G / 8, rem = G % 8;
-  const int lt = (int)(xcd * per + min(xcd, rem) + bb / 8);
+  const int lt = (int)MFPFF_IN(xcd * per + min(xcd, rem) + bb / 8, (long long)ntx * ntx);
   const int tx = lt % ntx, ty = lt / ntx;
   const int cx0 = tx * kRowOwn, cy0 = ty * kRowOwn;
   const int cx1 = min(cx0 + kRowOwn, N), cy1 = min(cy0 + kRowOwn, N);
@@ -136,18 +149,18 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   uint8_t mk[NP];
 #pragma unroll
   for (int i0 = 0; i0 < NP; ++i0) {
-    const long long nd = nd0 + i0;
+    const uint32_t nd = (uint32_t)MFPFF_IN(nd0 + i0, nn), bo = nd * (uint32_t)sizeof(T);
     if (LIN) {
-      f[0][i0] = a.u[nd];
-      f[1][i0] = a.u[nn + nd];
-      f[2][i0] = a.phi[nd];
-      f[3][i0] = a.phit[nd];
+      f[0][i0] = at_off(a.u, bo);
+      f[1][i0] = at_off(a.u + nn, bo);
+      f[2][i0] = at_off(a.phi, bo);
+      f[3][i0] = at_off(a.phit, bo);
     }
     if (XIN) {
       mk[i0] = a.mask ? a.mask[nd] : (uint8_t)0;
-      f[4][i0] = a.x[nd];
-      f[5][i0] = a.x[nn + nd];
-      f[6][i0] = a.x[2 * nn + nd];
+      f[4][i0] = at_off(a.x, bo);
+      f[5][i0] = at_off(a.x + nn, bo);
+      f[6][i0] = at_off(a.x + 2 * nn, bo);
     }
   }
   // cached tangent coefficients of the Gauss row r, stored per tile (halo cells included) so
@@ -181,64 +194,71 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   // after the cell work so that they do not hold registers through it
   const int nox = K * (cx1 - cx0) + (cx1 == N ? 1 : 0);
   const int noy = K * (cy1 - cy0) + (cy1 == N ? 1 : 0);
-  const int nown = nox * noy;
-  constexpr int MAXO = ((K * kRowOwn + 1) * (K * kRowOwn + 1) + NT - 1) / NT;
+  // owned nodes enumerated in a box of power-of-two width OW >= K * kRowOwn + 1 (mask and shift,
+  // no division); slots past the tile's nox x noy nodes do nothing
+  constexpr int OW = K == 1 ? 8 : 16;
+  constexpr int OWL = K == 1 ? 3 : 4;
+  static_assert(OW >= K * kRowOwn + 1 && (1 << OWL) == OW, "owned-node box");
+  constexpr int MAXO = (OW * OW + NT - 1) / NT;
   struct Owned {
-    long long node;
+    uint32_t boff;  // byte offset of the node in a component block
+    bool ok;
     int bo;
     uint8_t m;
     T ea[3], eb[3], ec[3], ex[3];
   };
   auto eload = [&](int j, Owned& o) {
     const int id = tid + j * NT;
-    const bool ok = id < nown;
-    const int ox = ok ? id % nox : 0, oy = ok ? id / nox : 0;
-    o.node = ok ? (long long)(K * cx0 + ox) + M * (K * cy0 + oy) : -1;
+    const int ox = id & (OW - 1), oy = id >> OWL;
+    const bool ok = ox < nox && oy < noy;
+    o.ok = ok;
+    const uint32_t node = ok ? (uint32_t)MFPFF_IN((long long)(K * cx0 + ox) + M * (K * cy0 + oy), nn) : 0u;
+    o.boff = node * (uint32_t)sizeof(T);
     o.bo = (K + oy) * AN + K + ox;
-    o.m = (ok && a.mask) ? a.mask[o.node] : (uint8_t)0;
+    o.m = (ok && a.mask) ? a.mask[node] : (uint8_t)0;
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
-      const long long idx = cc * nn + o.node;
+      const long long cb = cc * nn;
       o.ea[cc] = o.eb[cc] = o.ec[cc] = o.ex[cc] = T(0);
       if (ok && EPI == EPI_RESID) {
-        o.ea[cc] = e.b[idx];
-        if (e.z0) o.eb[cc] = e.dinv[idx];
-        o.ex[cc] = a.x[idx];
+        o.ea[cc] = at_off(e.b + cb, o.boff);
+        if (e.z0) o.eb[cc] = at_off(e.dinv + cb, o.boff);
+        o.ex[cc] = at_off(a.x + cb, o.boff);
       } else if (ok && EPI == EPI_CHEB) {
-        o.ea[cc] = e.r[idx];
-        o.eb[cc] = e.d[idx];
-        o.ec[cc] = e.dinv[idx];
-        o.ex[cc] = a.x[idx];
+        o.ea[cc] = at_off(e.r + cb, o.boff);
+        o.eb[cc] = at_off(e.d + cb, o.boff);
+        o.ec[cc] = at_off(e.dinv + cb, o.boff);
+        o.ex[cc] = at_off(a.x + cb, o.boff);
       } else if (ok) {
-        o.ex[cc] = a.x[idx];
+        o.ex[cc] = at_off(a.x + cb, o.boff);
       }
     }
   };
   auto efinish = [&](const Owned& o) {
-    if (o.node < 0) return;
+    if (!o.ok) return;
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc) {
-      const long long idx = cc * nn + o.node;
+      const long long cb = cc * nn;
       const bool fixed = (cc < 2) ? (o.m & kMaskU) : (o.m & kMaskPhi);
       const T xo = o.ex[cc];
       const T gx = fixed ? xo : acc[cc * AN * AN + o.bo];
       if (EPI == EPI_APPLY) {
-        e.y[idx] = gx;
+        at_off(e.y + cb, o.boff) = gx;
       } else if (EPI == EPI_RESID) {
         const T rv = o.ea[cc] - gx;
-        e.y[idx] = rv;
+        at_off(e.y + cb, o.boff) = rv;
         if (e.z0) {
           const T zv = o.eb[cc] * rv * (cc < 2 ? e.ith_u : e.ith_p);
-          e.z0[idx] = zv;
-          e.d0[idx] = zv;
+          at_off(e.z0 + cb, o.boff) = zv;
+          at_off(e.d0 + cb, o.boff) = zv;
         }
       } else {
         const bool isu = cc < 2;
         const T dn = (isu ? e.c1u : e.c1p) * o.eb[cc] + (isu ? e.c2u : e.c2p) * o.ec[cc] * (o.ea[cc] - gx);
-        e.d[idx] = dn;
+        at_off(e.d + cb, o.boff) = dn;
         const T zn = xo + dn;
-        e.y[idx] = zn;
-        if (e.xout) e.xout[idx] = e.xacc[idx] + zn;
+        at_off(e.y + cb, o.boff) = zn;
+        if (e.xout) at_off(e.xout + cb, o.boff) = at_off(e.xacc + cb, o.boff) + zn;
       }
     }
   };
@@ -579,3 +599,5 @@ template hipError_t launch_rowcell_2d<double>(int, int, const CellArgs<double>&,
 template hipError_t launch_rowcell_2d<float>(int, int, const CellArgs<float>&, const Epilogue<float>&, hipStream_t);
 
 }  // namespace mfpff
+
+MFPFF_BOUNDS_READER(bounds_hits_rowcell)

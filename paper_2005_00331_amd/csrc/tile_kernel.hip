@@ -14,6 +14,7 @@
 //   EPI_CHEB  : t = diag(G^_uu, G^_phiphi) z; d = c1 d + c2 D^-1 (r - t);
 //               z' = z + d (one Chebyshev-Jacobi step of the smoother,
 //               Section 3.3), optionally x' = x + z'.
+#include "bounds.h"
 #include "cell_common.h"
 
 namespace mfpff {
@@ -76,7 +77,7 @@ __global__ __launch_bounds__(kThreads) void tile_kernel_2d(CellArgs<T> a, Epilog
       uint8_t mk = 0;
       if (valid) {
         const int cx = ccx0 + ci % ncx, cy = ccy0 + ci / ncx;
-        node = (long long)(K * cx + p % NP) + M * (K * cy + p / NP);
+        node = MFPFF_IN((long long)(K * cx + p % NP) + M * (K * cy + p / NP), nn);
         mk = a.mask ? a.mask[node] : (uint8_t)0;
       }
 #pragma unroll
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(kThreads) void tile_kernel_2d(CellArgs<T> a, Epilog
 
   // ---- fused epilogue on the owned nodes
   for (int o = tid; o < nown; o += kThreads) {
-    const long long node = (long long)(K * cx0 + o % nox) + M * (K * cy0 + o / nox);
+    const long long node = MFPFF_IN((long long)(K * cx0 + o % nox) + M * (K * cy0 + o / nox), nn);
     const uint8_t mk = a.mask ? a.mask[node] : (uint8_t)0;
 #pragma unroll
     for (int cc = 0; cc <= DIM; ++cc) {
@@ -189,3 +190,5 @@ template hipError_t launch_tile_2d<float>(int, int, const CellArgs<float>&, cons
                                           hipStream_t);
 
 }  // namespace mfpff
+
+MFPFF_BOUNDS_READER(bounds_hits_tile)

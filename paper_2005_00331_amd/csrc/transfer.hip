@@ -7,6 +7,7 @@
 // instead of (k+1)^3 times; the masks are fused into the first and last pass.
 // In 2D the prolongation is one gather pass (prolong_kernel), which saves a
 // launch on the small levels.
+#include "bounds.h"
 #include "internal.h"
 
 namespace mfpff {
@@ -54,7 +55,7 @@ __global__ void axis_apply_kernel(T* out, const T* in, const int* col, const dou
         const int ci = col[row * width + j];
         if (ci < 0) break;
         const T w = sizeof(T) == 8 ? (T)val[row * width + j] : (T)valf[row * width + j];
-        const long long ii = base + (long long)ci * sin[axis];
+        const long long ii = MFPFF_IN(base + (long long)ci * sin[axis], per_in * ncomp);
         if (in_mask && comp_fixed(in_mask, ii - comp * per_in, comp, dim)) continue;
         acc += w * in[ii];
       }
@@ -109,7 +110,7 @@ __global__ void prolong_kernel(T* out, const T* xc, const int* col, const double
 #pragma unroll
       for (int j0 = 0; j0 < W; ++j0) {
         const T w = w1[j1] * w0[j0];
-        const long long nc = c0[j0] + (long long)gc.M * c1[j1];
+        const long long nc = MFPFF_IN(c0[j0] + (long long)gc.M * c1[j1], nnc);
         const uint8_t mc = mask_c[nc];
 #pragma unroll
         for (int cc = 0; cc < 3; ++cc) {
@@ -201,3 +202,5 @@ template void k_add_masked<double>(double*, const double*, const uint8_t*, long 
 template void k_add_masked<float>(float*, const float*, const uint8_t*, long long, int, hipStream_t);
 
 }  // namespace mfpff
+
+MFPFF_BOUNDS_READER(bounds_hits_transfer)

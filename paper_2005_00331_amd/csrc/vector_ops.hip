@@ -2,6 +2,9 @@
 // Element-wise kernels are grid-stride loops over contiguous vectors; reductions
 // write one partial per workgroup and a single workgroup finishes them in a
 // fixed order, so repeated runs are bitwise identical.
+#include <type_traits>
+
+#include "bounds.h"
 #include "internal.h"
 
 namespace mfpff {
@@ -185,6 +188,7 @@ __global__ void inject_kernel(double* lin_c, uint8_t* mask_c, const double* lin_
       fi += ia * ratio * fs;
       fs *= gf.M;
     }
+    fi = MFPFF_IN(fi, nnf);
     for (int c = 0; c < gc.dim + 2; ++c) lin_c[c * nnc + i] = lin_f[c * nnf + fi];
     mask_c[i] = (uint8_t)(mask_f[fi] & kMaskPhi) | dirichlet_bit(i, gc, dirichlet);
   }
@@ -342,7 +346,7 @@ __global__ void impose_faces_kernel(double* u, Geom g, double t0, double t1, dou
   const long long top_off = (long long)(g.M - 1) * nf;
   GSTRIDE(i, 2 * nf) {
     const bool top = i >= nf;
-    const long long node = (top ? i - nf + top_off : i);
+    const long long node = MFPFF_IN(top ? i - nf + top_off : i, g.n_nodes);
     u[node] = top ? t0 : 0.0;
     u[g.n_nodes + node] = top ? t1 : 0.0;
     if (g.dim == 3) u[2 * g.n_nodes + node] = top ? t2 : 0.0;
@@ -370,6 +374,7 @@ __global__ void face_reaction_kernel(double* out, const double* R, Geom g) {
   const long long nf = g.dim == 2 ? (long long)g.M : (long long)g.M * g.M;
   const double* r = R + c * g.n_nodes + (f ? (long long)(g.M - 1) * nf : 0);
   double s = 0;
+  (void)MFPFF_IN((f ? (long long)(g.M - 1) * nf : 0) + nf - 1, g.n_nodes);  // the face's last node
   for (long long i = threadIdx.x; i < nf; i += blockDim.x) s += r[i];
   for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
   if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = s;
@@ -521,29 +526,40 @@ __global__ __launch_bounds__(kThreads) void orth_pass_kernel(double* __restrict_
   double acc[NA];
 #pragma unroll
   for (int j = 0; j < NA; ++j) acc[j] = 0.0;
-  const long long stride = (long long)gridDim.x * blockDim.x;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    double v[NV];
+  // one element (the scalar tail of an odd n) or two consecutive ones per step; the basis stride
+  // ldv is even and every vector 16-byte aligned, so a pair is one 16-byte load per vector
+  auto step = [&](long long i, auto tag) {
+    constexpr int W = decltype(tag)::value;
+    using V2 = typename std::conditional<W == 2, double2, double>::type;
+    V2 v[NV];
 #pragma unroll
-    for (int j = 0; j < NV; ++j) v[j] = V[(long long)j * ldv + i];
-    double wi = w[i];
-    // keep every load of the element in flight before the arithmetic (the register
-    // allocator would otherwise interleave them to save registers)
+    for (int j = 0; j < NV; ++j) v[j] = *reinterpret_cast<const V2*>(V + (long long)j * ldv + i);
+    V2 wi = *reinterpret_cast<const V2*>(w + i);
+    // keep every load of the step in flight before the arithmetic (the register allocator
+    // would otherwise interleave them to save registers)
     __builtin_amdgcn_sched_barrier(0);
-    if (MODE != ORTH_DOTS) {
-      double t = 0.0;
+    double* wl = reinterpret_cast<double*>(&wi);
 #pragma unroll
-      for (int j = 0; j < NV; ++j) t += c[j] * v[j];
-      wi -= t;
-      w[i] = wi;
-    }
-    if (MODE == ORTH_UPDATE_NORM) {
-      acc[0] += wi * wi;
-    } else {
+    for (int e = 0; e < W; ++e) {
+      if (MODE != ORTH_DOTS) {
+        double t = 0.0;
 #pragma unroll
-      for (int j = 0; j < NA; ++j) acc[j] += v[j] * wi;
+        for (int j = 0; j < NV; ++j) t += c[j] * reinterpret_cast<const double*>(&v[j])[e];
+        wl[e] -= t;
+      }
+      if (MODE == ORTH_UPDATE_NORM) {
+        acc[0] += wl[e] * wl[e];
+      } else {
+#pragma unroll
+        for (int j = 0; j < NA; ++j) acc[j] += reinterpret_cast<const double*>(&v[j])[e] * wl[e];
+      }
     }
-  }
+    if (MODE != ORTH_DOTS) *reinterpret_cast<V2*>(w + i) = wi;
+  };
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long p = gid; 2 * p + 1 < n; p += stride) step(2 * p, std::integral_constant<int, 2>());
+  if ((n & 1) && gid == 0) step(n - 1, std::integral_constant<int, 1>());
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
   for (int j = 0; j < NA; ++j) {
@@ -793,3 +809,5 @@ INST(float)
 #undef INST
 
 }  // namespace mfpff
+
+MFPFF_BOUNDS_READER(bounds_hits_vector)

@@ -271,6 +271,16 @@ def test_fully_broken_material_at_rest_rejected():
     assert ei.value.status == 6
 
 
+def test_2d_level_past_the_offset_range_rejected():
+    # the 2D Q1/Q2 kernel addresses nodes by 32-bit byte offsets: a level of 2^28 or more nodes
+    # (16384^2 Q1 cells: 16385^2 nodes) is refused at set-up, before its storage is allocated
+    from paper_2005_00331_amd import Context, MfpffError, problem_from
+    cfg = CONFIGS["C1"].with_(N=16384, n_h_levels=1, p_coarse=())
+    with pytest.raises(MfpffError) as ei:
+        Context(problem_from(cfg, [(16384, 1)]))
+    assert ei.value.status == 1
+
+
 def test_oversized_coarse_level_rejected_without_allocation():
     from paper_2005_00331_amd import MfpffError
     cfg = CONFIGS["C5"]
