@@ -17,6 +17,7 @@
 // A workgroup takes NOB consecutive blocks of that layout (CPB cells each), so the
 // coefficient cache and the element buffer are read and written in its order.
 #include "cell_common.h"
+#include "gauss_tables.h"
 #include "miehe.h"
 
 namespace mfpff {
@@ -86,16 +87,31 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
   const bool valid = cell < ncells;
   const long long vc = valid ? cell : 0;  // invalid lanes read cell 0 and store nothing
 
-  T Bm[NP][NP], Dm[NP][NP], w[NP];  // uniform: scalar registers
+  // 1D tables: compile-time constants up to Q3 (no scalar registers; the zero and unit entries
+  // fold).  At Q4 the constants would be kept in vector registers and spill to scratch, so the
+  // entries come from the device copy as uniform values, and only the rows q <= k/2: the points
+  // and nodes are symmetric about 1/2, so B[q][i] = B[k-q][k-i] and D[q][i] = -D[k-q][k-i]
+  // (31 values in scalar registers instead of 55, which spilled into vector lanes)
+  constexpr int NH = K / 2 + 1;
+  T Bh[NH][NP], Dh[NH][NP], wv[NH];
+  if (K == 4) {
 #pragma unroll
-  for (int q = 0; q < NP; ++q) {
-    w[q] = tabd->w[q];
+    for (int q = 0; q < NH; ++q) {
+      wv[q] = tabd->w[q];
 #pragma unroll
-    for (int i = 0; i < NP; ++i) {
-      Bm[q][i] = tabd->B[q][i];
-      Dm[q][i] = tabd->D[q][i];
+      for (int i = 0; i < NP; ++i) {
+        Bh[q][i] = tabd->B[q][i];
+        Dh[q][i] = tabd->D[q][i];
+      }
     }
   }
+  auto TBB = [&](int q, int i) -> T {
+    return K == 4 ? (q < NH ? Bh[q][i] : Bh[K - q][K - i]) : (T)ConstTab<K>::B(q, i);
+  };
+  auto TBD = [&](int q, int i) -> T {
+    return K == 4 ? (q < NH ? Dh[q][i] : -Dh[K - q][K - i]) : (T)ConstTab<K>::D(q, i);
+  };
+  auto TBW = [&](int q) -> T { return K == 4 ? (q < NH ? wv[q] : wv[K - q]) : (T)ConstTab<K>::w(q); };
 
   // ---- x-lines of the trial vector (node row (la, lb) of the cell), masked at fixed dofs
   const unsigned uc = (unsigned)vc, q1c = uc / N, cz = q1c / N;
@@ -135,8 +151,8 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
         T sb = 0, sd = 0;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-          sb += Bm[q][i] * xl[f][i];
-          sd += Dm[q][i] * xl[f][i];
+          sb += TBB(q, i) * xl[f][i];
+          sd += TBD(q, i) * xl[f][i];
         }
         s[xo + q] = sb;
         s[TS + xo + q] = sd;
@@ -157,9 +173,9 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
         T s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-          s0 += Bm[q][i] * k0[i];
-          s1 += Dm[q][i] * k0[i];
-          s2 += Bm[q][i] * k1[i];
+          s0 += TBB(q, i) * k0[i];
+          s1 += TBD(q, i) * k0[i];
+          s2 += TBB(q, i) * k1[i];
         }
         s[yo + NP * q] = s0;
         s[TS + yo + NP * q] = s1;
@@ -181,10 +197,10 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
         T dz = 0, dy = 0, dx = 0, v = 0;
 #pragma unroll
         for (int i = 0; i < NP; ++i) {
-          dz += Dm[q][i] * y0[i];
-          dy += Bm[q][i] * y1[i];
-          dx += Bm[q][i] * y2[i];
-          if (f == 3) v += Bm[q][i] * y0[i];
+          dz += TBD(q, i) * y0[i];
+          dy += TBB(q, i) * y1[i];
+          dx += TBB(q, i) * y2[i];
+          if (f == 3) v += TBB(q, i) * y0[i];
         }
         gr[f][0][q] = dx;
         gr[f][1][q] = dy;
@@ -265,7 +281,7 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
         if (MODE == MODE_APPLY_T) Su[i][j] += dph * gsp[i][j];
       }
     const T fval = cpp * dph + spde;
-    const T jxw = w[la] * w[lb] * w[q] * h * h * h;
+    const T jxw = TBW(la) * TBW(lb) * TBW(q) * h * h * h;
     const T jg = jxw * ih;
 #pragma unroll
     for (int cc = 0; cc < 3; ++cc)
@@ -288,10 +304,10 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
         T a1 = 0, a2 = 0, a3 = 0;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-          a1 += Dm[q][i] * gr[tc][2][q];
-          if (tc == 3) a1 += Bm[q][i] * pv[q];
-          a2 += Bm[q][i] * gr[tc][0][q];
-          a3 += Bm[q][i] * gr[tc][1][q];
+          a1 += TBD(q, i) * gr[tc][2][q];
+          if (tc == 3) a1 += TBB(q, i) * pv[q];
+          a2 += TBB(q, i) * gr[tc][0][q];
+          a3 += TBB(q, i) * gr[tc][1][q];
         }
         s[lo + L * i] = a1;
         s[TS + lo + L * i] = a2;
@@ -313,8 +329,8 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
         T b1 = 0, b2 = 0;
 #pragma unroll
         for (int q = 0; q < NP; ++q) {
-          b1 += Bm[q][i] * a1[q] + Dm[q][i] * a3[q];
-          b2 += Bm[q][i] * a2[q];
+          b1 += TBB(q, i) * a1[q] + TBD(q, i) * a3[q];
+          b2 += TBB(q, i) * a2[q];
         }
         s[yo + NP * i] = b1;
         s[TS + yo + NP * i] = b2;
@@ -332,7 +348,7 @@ __global__ __launch_bounds__(LineShape<K>::NT) __attribute__((amdgpu_waves_per_e
       for (int i = 0; i < NP; ++i) {
         T s = 0;
 #pragma unroll
-        for (int q = 0; q < NP; ++q) s += Bm[q][i] * b1[q] + Dm[q][i] * b2[q];
+        for (int q = 0; q < NP; ++q) s += TBB(q, i) * b1[q] + TBD(q, i) * b2[q];
         yl[tc][i] = s;
       }
     }

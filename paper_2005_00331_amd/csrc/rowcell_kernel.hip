@@ -22,43 +22,10 @@
 // Chebyshev start, Chebyshev step).
 #include "internal.h"
 #include "bounds.h"
+#include "gauss_tables.h"
 #include "miehe.h"
 
 namespace mfpff {
-
-namespace {
-
-// The 1D tables of Q1 and Q2 as compile-time constants (the same quantities the library builds at
-// run time for every degree): Gauss-Legendre points on [0, 1], 1/2 -+ sqrt(3)/6 for two points and
-// 1/2, 1/2 -+ sqrt(15)/10 for three, equispaced Lagrange nodes.  B[q][i] = l_i(x_q),
-// D[q][i] = l_i'(x_q), w the Gauss weights.  As constants they need no scalar registers (the
-// by-value table spilled them into vector lanes), and the compiler folds the zeros and units:
-// the middle Gauss point of Q2 is a node, where B is a unit row and D = (-1, 0, 1).
-template <int NP>
-struct RowTab;
-template <>
-struct RowTab<2> {
-  static constexpr double s = 0.28867513459481288225;  // sqrt(3) / 6
-  static __device__ constexpr double x(int q) { return q == 0 ? 0.5 - s : 0.5 + s; }
-  static __device__ constexpr double B(int q, int i) { return i == 0 ? 1.0 - x(q) : x(q); }
-  static __device__ constexpr double D(int, int i) { return i == 0 ? -1.0 : 1.0; }
-  static __device__ constexpr double w(int) { return 0.5; }
-};
-template <>
-struct RowTab<3> {
-  static constexpr double s = 0.38729833462074168852;  // sqrt(15) / 10
-  static __device__ constexpr double x(int q) { return q == 0 ? 0.5 - s : (q == 1 ? 0.5 : 0.5 + s); }
-  // l_0 = 2 (x - 1/2)(x - 1), l_1 = 4 x (1 - x), l_2 = 2 x (x - 1/2)
-  static __device__ constexpr double B(int q, int i) {
-    return i == 0 ? 2.0 * (x(q) - 0.5) * (x(q) - 1.0) : (i == 1 ? 4.0 * x(q) * (1.0 - x(q)) : 2.0 * x(q) * (x(q) - 0.5));
-  }
-  static __device__ constexpr double D(int q, int i) {
-    return i == 0 ? 4.0 * x(q) - 3.0 : (i == 1 ? 4.0 - 8.0 * x(q) : 4.0 * x(q) - 1.0);
-  }
-  static __device__ constexpr double w(int q) { return q == 1 ? 4.0 / 9.0 : 5.0 / 18.0; }
-};
-
-}  // namespace
 
 // element at a 32-bit byte offset from a uniform base: the address is the scalar base plus one
 // vector offset (no 64-bit address arithmetic per access); the set-up keeps 2D Q1/Q2 levels
@@ -121,7 +88,7 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
   const bool valid = cx >= 0 && cy >= 0 && cx < cx1 && cy < cy1;
   for (int i = tid; i < 3 * AN * AN; i += NT) acc[i] = T(0);
 
-  using TB = RowTab<NP>;
+  using TB = ConstTab<K>;  // compile-time 1D tables (no scalar registers, zero entries folded)
   // table entries of row / column r (r is uniform per wavefront: scalar selects of constants)
   T Br[NP], Dr[NP], Bc[NP], Dc[NP];  // B[r][i], D[r][i], B[q][r], D[q][r]
   T wr = T(0);
