@@ -528,8 +528,8 @@ def main():
                     help="only time the finest-level cell kernel (for kernel-trace and counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
-              f"(the multi-GPU sharding is a design in DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: the solver runs on one GPU only; --gpus {args.gpus} is not supported "
+              f"(sharding over several GPUs is a design only)", file=sys.stderr)
         sys.exit(2)
     import torch
     from synth import CONFIGS, level_list
@@ -687,7 +687,7 @@ def main():
             res[prec + "_vcycle"] = time_solve(c3, prec)
             print(f"[bench] C3 solve, phi = 1 off the notch, {prec} V-cycle: {res[prec + '_vcycle']}", file=sys.stderr,
                   flush=True)
-        # the smooth seeded phi field in [0, 1] off the notch (the survey's input recipe for C2-C5)
+        # the smooth seeded phi field in [0, 1] off the notch (the input recipe of the C2-C5 workloads)
         c3s = c3.with_(phi_mode="smooth", max_iter=2000)
         for prec in ("f64", "f32"):
             res["smooth_phi_" + prec + "_vcycle"] = time_solve(c3s, prec, warm=False)

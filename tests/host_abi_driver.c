@@ -100,7 +100,7 @@ int main(void) {
   mfpff_pdas_info pi;
   mfpff_load_info li;
   EXPECT(strcmp(mfpff_last_error(NULL), "null context") == 0);
-  EXPECT(mfpff_debug_bounds_hits() == -1); /* this build has no index checks */
+  EXPECT(mfpff_debug_bounds_hits() == -1); /* the regular library has no index checks */
   mfpff_destroy(NULL);
   EXPECT(mfpff_sizes(NULL, 0, &nn, &nd) == MFPFF_ERR_ARG);
   EXPECT(mfpff_level_info(NULL, 0, &desc) == MFPFF_ERR_ARG);

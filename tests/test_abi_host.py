@@ -75,7 +75,7 @@ def test_null_context_paths(lib):
     assert L.mfpff_level_info(None, 0, ctypes.byref(d)) == 1
     nn, nd = ctypes.c_size_t(), ctypes.c_size_t()
     assert L.mfpff_sizes(None, 0, ctypes.byref(nn), ctypes.byref(nd)) == 1
-    assert L.mfpff_debug_bounds_hits() == -1   # the regular build has no index checks
+    assert L.mfpff_debug_bounds_hits() == -1   # the regular library has no index checks
 
 
 def _c_struct_fields(name):
