@@ -522,6 +522,8 @@ def main():
     ap.add_argument("--restart", type=int, default=None, help="with --solve: FGMRES restart length (default: the workload's)")
     ap.add_argument("--cheb-degree", type=int, default=None, help="with --solve: Chebyshev degree (default: the workload's)")
     ap.add_argument("--max-iter", type=int, default=5000, help="with --solve: FGMRES iteration cap")
+    ap.add_argument("--phi", default=None, choices=("ones", "smooth"),
+                    help="with --solve: the phase field off the notch (default: the workload's)")
     ap.add_argument("--contraction", default=None, choices=("valu", "mfma"),
                     help="with --solve or --apply-only: 3D Q3/Q4 contractions on the vector unit or the matrix cores")
     ap.add_argument("--apply-only", action="store_true",
@@ -545,12 +547,14 @@ def main():
         return
     if args.solve:
         cfg = CONFIGS[args.solve].with_(max_iter=args.max_iter)
-        for key, val in (("restart", args.restart), ("cheb_degree", args.cheb_degree), ("contraction", args.contraction)):
+        for key, val in (("restart", args.restart), ("cheb_degree", args.cheb_degree), ("contraction", args.contraction),
+                         ("phi_mode", args.phi)):
             if val is not None:
                 cfg = cfg.with_(**{key: val})
         rec = {"workload": f"{cfg.name}: {cfg.dim}D {cfg.N}^{cfg.dim} cells Q{cfg.k}, {cfg.n_dofs} dofs, levels "
                            f"{level_list(cfg)}, seeded state, active set and right-hand side, rtol {cfg.rtol}",
-               "restart": cfg.restart, "cheb_degree": cfg.cheb_degree, "contraction": cfg.contraction}
+               "restart": cfg.restart, "cheb_degree": cfg.cheb_degree, "contraction": cfg.contraction,
+               "phi_mode": cfg.phi_mode}
         for prec in ("f64", "f32"):
             rec[prec + "_vcycle"] = time_solve(cfg, prec, warm=False)
             print(f"[bench] {cfg.name} solve, {prec} V-cycle: {rec[prec + '_vcycle']}", file=sys.stderr, flush=True)
