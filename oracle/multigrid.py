@@ -35,14 +35,51 @@ from .splitmix import uniform_pm1
 
 
 def injection_index(fine: Mesh, coarse: Mesh) -> np.ndarray:
-    """For each coarse node, the fine node at the same position."""
+    """For each coarse node, the fine node at the same position (on slit meshes a coarse
+    duplicate maps to the fine duplicate there: the same side of the slit)."""
     num = fine.k * fine.N
     den = coarse.k * coarse.N
     assert num % den == 0
     r = num // den
     cm = coarse.node_multi(np.arange(coarse.n_nodes))
     stride = fine.M ** np.arange(fine.dim)
-    return ((cm * r) * stride).sum(1)
+    idx = ((cm * r) * stride).sum(1)
+    if coarse.slit:
+        assert fine.slit
+        dup = np.arange(coarse.n_grid, coarse.n_nodes)
+        fm = cm[dup] * r
+        idx[dup] = fine.n_grid + fm[:, 0] + (fine.n_slit_x * fm[:, 1] if fine.dim == 3 else 0)
+    return idx
+
+
+def slit_prolongation(fine: Mesh, coarse: Mesh, Pn) -> sp.csr_matrix:
+    """Per-component prolongation between two slit meshes: the tensor-product interpolation Pn
+    between the grid nodes, with every fine node taking the coarse values of its own side of the
+    slit.  Where a fine node strictly above the slit plane, or a fine duplicate, reads a coarse
+    slit node (a grid node with a duplicate), it reads that node's duplicate instead; below the
+    slit, on the plane's grid nodes and at the shared tip nothing changes.  A fine duplicate
+    interpolates like its grid node, along the plane."""
+    d = fine.dim
+    Pg = sp.csr_matrix(Pn)
+    cm = coarse.node_multi(np.arange(coarse.n_grid))
+    c_slit = (cm[:, d - 1] == coarse.M // 2) & (cm[:, 0] < coarse.n_slit_x)
+    c_dup = coarse.n_grid + cm[:, 0] + (coarse.n_slit_x * cm[:, 1] if d == 3 else 0)
+    fm = fine.node_multi(np.arange(fine.n_grid))
+    f_above = fm[:, d - 1] > fine.M // 2
+
+    def remap(block, above_rows):
+        b = block.tocoo()
+        m = above_rows[b.row] & c_slit[b.col]
+        return b.row, np.where(m, c_dup[b.col], b.col), b.data
+
+    r1, c1, v1 = remap(Pg, f_above)
+    dup_grid = fine.node_multi(np.arange(fine.n_grid, fine.n_nodes))
+    dup_grid = (dup_grid * (fine.M ** np.arange(d))).sum(1)
+    r2, c2, v2 = remap(Pg[dup_grid], np.ones(dup_grid.size, bool))
+    rows = np.concatenate([r1, fine.n_grid + r2])
+    cols = np.concatenate([c1, c2])
+    vals = np.concatenate([v1, v2])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(fine.n_nodes, coarse.n_nodes))
 
 
 def prolongation_1d(fine: Mesh, coarse: Mesh) -> np.ndarray:
@@ -82,8 +119,6 @@ class Hierarchy:
         self.cfg = cfg
         self.m = op.material_of(cfg) if m is None else m
         slit = getattr(cfg, "slit", False)
-        if slit and len(levels_nk) > 1:
-            raise ValueError("multigrid levels on the slit mesh are not built: one level, exact coarse solve")
         meshes = [Mesh(cfg.dim, N, k, slit) for (N, k) in levels_nk]
         L = len(meshes) - 1
         fields = [None] * (L + 1)
@@ -102,6 +137,8 @@ class Hierarchy:
             Pn = P1
             for _ in range(cfg.dim - 1):
                 Pn = sp.kron(P1, Pn)
+            if slit:
+                Pn = slit_prolongation(f.mesh, c.mesh, Pn)
             Pfull = sp.block_diag([Pn] * (cfg.dim + 1))
             self.P[l] = (sp.diags(f.pvec) @ Pfull @ sp.diags(c.pvec)).tocsr()
         # smoother intervals on levels >= 1

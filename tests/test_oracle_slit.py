@@ -93,3 +93,66 @@ def test_lumped_mass_splits_between_the_two_sides():
     assert np.allclose(merged, Mf, rtol=1e-14, atol=0)
     assert np.all(Ms > 0)
     assert np.allclose(Ms[dup], Ms[mf.n_nodes:], rtol=1e-14)   # symmetric about the slit plane
+
+
+# ------------------------------------------------------------- multigrid on slit meshes
+def _coarse_value(coarse: Mesh, vc, x, above):
+    """The coarse slit-mesh finite-element function with nodal values vc at the point x, taken
+    in a coarse cell that contains x; a point on the slit plane is taken on the side `above`
+    names (the cells above the slit for a duplicate).  Elsewhere the function is continuous, so
+    any containing cell gives the same value."""
+    from oracle.fe import lagrange_values
+    d, N, k = coarse.dim, coarse.N, coarse.k
+    cm = [min(int(np.floor(x[a] * N + 1e-12)), N - 1) for a in range(d)]
+    if abs(x[d - 1] - 0.5) < 1e-12:
+        cm[d - 1] = N // 2 if above else N // 2 - 1
+    cell = sum(cm[a] * N ** a for a in range(d))
+    nodes = coarse.cell_nodes([cell])[0]
+    lm = coarse.local_multi()
+    basis = np.ones(len(nodes))
+    for a in range(d):
+        basis *= lagrange_values(k, np.array([x[a] * N - cm[a]]))[0][lm[:, a]]
+    return basis @ vc[nodes]
+
+
+def _positions(mesh):
+    from synth.fields import node_coords
+    X = node_coords(mesh.dim, mesh.N, mesh.k)
+    return np.concatenate([X, X[slit_duplicates(mesh.dim, mesh.N, mesh.k)]])
+
+
+@pytest.mark.parametrize("dim,levels", [(2, [(4, 1), (8, 1)]), (2, [(4, 2), (8, 2)]), (2, [(4, 1), (4, 2)]),
+                                        (2, [(4, 2), (4, 4)]), (3, [(2, 1), (4, 1)]), (3, [(2, 1), (2, 2)])])
+def test_slit_prolongation_interpolates_each_side(dim, levels):
+    # P applied to any coarse slit-mesh function gives that function at every fine node, on the
+    # fine node's own side of the slit (brute-force evaluation in the containing coarse cell)
+    from oracle import multigrid as mg
+    (Nc, kc), (Nf, kf) = levels
+    mc, mf = Mesh(dim, Nc, kc, slit=True), Mesh(dim, Nf, kf, slit=True)
+    P1 = sp.csr_matrix(mg.prolongation_1d(mf, mc))
+    Pn = P1
+    for _ in range(dim - 1):
+        Pn = sp.kron(P1, Pn)
+    P = mg.slit_prolongation(mf, mc, Pn)
+    assert P.shape == (mf.n_nodes, mc.n_nodes)
+    vc = np.random.default_rng(21).standard_normal(mc.n_nodes)
+    X = _positions(mf)
+    above = np.arange(mf.n_nodes) >= mf.n_grid
+    ref = np.array([_coarse_value(mc, vc, X[i], above[i]) for i in range(mf.n_nodes)])
+    assert np.abs(P @ vc - ref).max() <= 1e-13 * np.abs(ref).max()
+    # and the jump across the slit survives: fine duplicates differ from their grid nodes
+    dup_grid = slit_duplicates(dim, Nf, kf)
+    assert np.abs((P @ vc)[mf.n_grid:] - (P @ vc)[dup_grid]).max() > 1e-3
+
+
+@pytest.mark.parametrize("dim,levels", [(2, [(4, 1), (8, 1)]), (2, [(4, 1), (4, 2)]), (3, [(2, 1), (4, 1)])])
+def test_slit_injection_keeps_the_side(dim, levels):
+    # every coarse node is injected from the fine node at its position and on its side: a coarse
+    # duplicate from a fine duplicate, a coarse grid node from a fine grid node
+    from oracle import multigrid as mg
+    (Nc, kc), (Nf, kf) = levels
+    mc, mf = Mesh(dim, Nc, kc, slit=True), Mesh(dim, Nf, kf, slit=True)
+    idx = mg.injection_index(mf, mc)
+    Xc, Xf = _positions(mc), _positions(mf)
+    assert np.allclose(Xf[idx], Xc, atol=1e-14)
+    assert np.array_equal(idx >= mf.n_grid, np.arange(mc.n_nodes) >= mc.n_grid)

@@ -188,6 +188,25 @@ def test_indefinite_coarse_block_takes_the_lu_path():
     assert np.abs(Lx - b).max() <= 1e-10 * np.abs(b).max()
 
 
+@pytest.mark.parametrize("name,kw", [("C1", dict(N=16, n_h_levels=2)), ("C2", dict(N=8, n_h_levels=2)),
+                                     ("C1", dict(dim=3, N=4, n_h_levels=2))])
+def test_two_grid_contracts_on_the_slit_mesh(name, kw):
+    # intact material on the slit mesh, no active set: the two-grid error operator with the
+    # slit-aware transfers contracts like on the uniform mesh
+    cfg = CONFIGS[name].with_(slit=True, **kw)
+    inp = make_inputs(cfg)
+    one = np.ones(cfg.n_nodes)
+    H = mg.Hierarchy(cfg, level_list(cfg)[-2:], inp["u"], one, one, np.zeros(cfg.n_nodes, np.uint8))
+    A = H.levels[-1].A
+    e = np.random.default_rng(3).standard_normal(A.shape[0])
+    rho = 0.0
+    for _ in range(25):
+        e_new = e - H.vcycle(A @ e)
+        rho = np.linalg.norm(e_new) / np.linalg.norm(e)
+        e = e_new / np.linalg.norm(e_new)
+    assert rho < 0.8, rho
+
+
 # ------------------------------------------------------------- FGMRES
 def test_fgmres_against_direct_solve_nonsymmetric():
     rng = np.random.default_rng(4)
@@ -385,6 +404,9 @@ VCYCLE_PIN_CASES = {
     "q2_pstep": ("C2", dict(N=8, n_h_levels=2, p_coarse=(1,)), None),
     # 3D Q1, two levels (2^3 -> 4^3)
     "3d_q1": ("C3", dict(N=4, k=1, n_h_levels=2, vcycle_prec="f64"), None),
+    # the slit mesh of Section 5.1 on every level (slit-aware injection and transfers)
+    "slit_q1": ("C1", dict(N=8, n_h_levels=2, slit=True, phi_mode="smooth"), None),
+    "slit_q2_pstep": ("C2", dict(N=4, n_h_levels=2, p_coarse=(1,), slit=True), None),
 }
 
 
