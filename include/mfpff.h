@@ -121,9 +121,14 @@ typedef struct {
                                        twice: the grid node belongs to the cells below the slit, a
                                        duplicate, numbered after the M^dim grid nodes (first axis
                                        fastest, then the second axis in 3D), to the cells above, so
-                                       n_nodes = M^dim + (kN/2) M^(dim-2).  Requires one level (the
-                                       exact coarse solve preconditions GMRES) and even N; products
-                                       use the cell kernel with the slit-aware node map */
+                                       n_nodes = M^dim + (kN/2) M^(dim-2).  Requires even N on
+                                       every level (each level is a slit mesh); products use the
+                                       cell kernel with the slit-aware node map.  A coarse
+                                       duplicate is injected from the fine duplicate at its
+                                       position; the prolongation gives every fine node the coarse
+                                       values of its own side of the slit (a fine node above the
+                                       plane, or a fine duplicate, reads a coarse slit node's
+                                       duplicate), and the restriction is its transpose */
 } mfpff_problem;
 
 typedef struct {

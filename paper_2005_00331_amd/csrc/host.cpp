@@ -65,6 +65,20 @@ struct DevSparse {
   float* valf = nullptr;
 };
 
+// a CSR matrix on the host and its device copy (the per-component transfers of slit levels)
+struct HostCsr {
+  int n_rows = 0, n_cols = 0;
+  std::vector<int> rowptr, col;
+  std::vector<double> val;
+};
+struct DevCsrBuf {
+  int* rowptr = nullptr;
+  int* col = nullptr;
+  double* val = nullptr;
+  float* valf = nullptr;
+  CsrDev view() const { return CsrDev{rowptr, col, val, valf}; }
+};
+
 struct Level {
   Geom g{};
   long long nn = 0, n = 0;
@@ -83,6 +97,7 @@ struct Level {
   double ith_u = 1.0, ith_p = 1.0;
   void* w[7] = {};  // V-cycle vectors b, x, r, t, d, z, z2
   DevSparse P1, R1;  // transfer from level-1 to this level
+  DevCsrBuf SP, SR;  // slit levels: the same transfer as CSR matrices (prolongation, restriction)
 };
 enum { WB = 0, WX = 1, WR = 2, WT = 3, WD = 4, WZ = 5, WZ2 = 6, NW = 7 };
 
@@ -221,6 +236,97 @@ void build_transfer(const Geom& gf, const Geom& gc, HostSparse& P, HostSparse& R
   pack(cols, gf.M, R);
 }
 
+// Prolongation between two slit levels (rows: fine nodes, columns: coarse nodes), per component.
+// Between grid nodes it is the tensor product of the 1D interpolation P1; each fine node takes
+// the coarse values of its own side of the slit: a fine grid node strictly above the slit plane,
+// and every fine duplicate (which interpolates like its grid node, along the plane), reads the
+// duplicate of a coarse slit node (plane index kN/2, first index below kN/2) in place of that
+// node.  Grid nodes below the plane or on it (the lower side) and the tip are unchanged.
+HostCsr build_slit_prolongation(const Geom& gf, const Geom& gc, const HostSparse& P1) {
+  const int d = gf.dim;
+  const long long Mf = gf.M, Mc = gc.M, nsf = (long long)gf.k * gf.N / 2, nsc = (long long)gc.k * gc.N / 2;
+  const long long plane_f = Mf / 2, plane_c = Mc / 2;
+  HostCsr A;
+  A.n_rows = (int)gf.n_nodes;
+  A.n_cols = (int)gc.n_nodes;
+  A.rowptr.assign((size_t)gf.n_nodes + 1, 0);
+  auto emit_row = [&](const long long* fm, bool other_side) {
+    // the tensor product of the 1D rows of fm's indices
+    int cnt[3] = {1, 1, 1};
+    for (int a = 0; a < d; ++a) {
+      cnt[a] = 0;
+      while (cnt[a] < P1.width && P1.col[(size_t)fm[a] * P1.width + cnt[a]] >= 0) ++cnt[a];
+    }
+    for (int e2 = 0; e2 < (d == 3 ? cnt[2] : 1); ++e2)
+      for (int e1 = 0; e1 < cnt[1]; ++e1)
+        for (int e0 = 0; e0 < cnt[0]; ++e0) {
+          const int es[3] = {e0, e1, e2};
+          long long cm[3] = {0, 0, 0}, col = 0, stride = 1;
+          double w = 1.0;
+          for (int a = 0; a < d; ++a) {
+            const size_t o = (size_t)fm[a] * P1.width + es[a];
+            cm[a] = P1.col[o];
+            w *= P1.val[o];
+            col += cm[a] * stride;
+            stride *= Mc;
+          }
+          if (other_side && cm[d - 1] == plane_c && cm[0] < nsc) col = gc.n_grid + cm[0] + (d == 3 ? nsc * cm[1] : 0);
+          A.col.push_back((int)col);
+          A.val.push_back(w);
+        }
+  };
+  long long row = 0;
+  for (long long f = 0; f < gf.n_grid; ++f, ++row) {
+    long long fm[3] = {0, 0, 0}, rem = f;
+    for (int a = 0; a < d; ++a) {
+      fm[a] = rem % Mf;
+      rem /= Mf;
+    }
+    emit_row(fm, fm[d - 1] > plane_f);
+    A.rowptr[(size_t)row + 1] = (int)A.col.size();
+  }
+  for (long long j = 0; j < gf.n_nodes - gf.n_grid; ++j, ++row) {
+    const long long fm[3] = {j % nsf, d == 3 ? j / nsf : plane_f, plane_f};
+    emit_row(fm, true);
+    A.rowptr[(size_t)row + 1] = (int)A.col.size();
+  }
+  return A;
+}
+
+HostCsr csr_transpose(const HostCsr& A) {
+  HostCsr T;
+  T.n_rows = A.n_cols;
+  T.n_cols = A.n_rows;
+  T.rowptr.assign((size_t)A.n_cols + 1, 0);
+  for (int c : A.col) ++T.rowptr[(size_t)c + 1];
+  for (int i = 0; i < A.n_cols; ++i) T.rowptr[(size_t)i + 1] += T.rowptr[i];
+  T.col.resize(A.col.size());
+  T.val.resize(A.val.size());
+  std::vector<int> next(T.rowptr.begin(), T.rowptr.end() - 1);
+  for (int r = 0; r < A.n_rows; ++r)  // rows in order: each transposed row lists its entries by fine node
+    for (int e = A.rowptr[r]; e < A.rowptr[(size_t)r + 1]; ++e) {
+      const int o = next[A.col[e]]++;
+      T.col[o] = r;
+      T.val[o] = A.val[e];
+    }
+  return T;
+}
+
+DevCsrBuf upload_csr(const HostCsr& h) {
+  DevCsrBuf d;
+  const size_t nnz = h.col.size();
+  d.rowptr = dalloc<int>(h.rowptr.size());
+  d.col = dalloc<int>(nnz);
+  d.val = dalloc<double>(nnz);
+  d.valf = dalloc<float>(nnz);
+  std::vector<float> vf(h.val.begin(), h.val.end());
+  HIPCHK(hipMemcpy(d.rowptr, h.rowptr.data(), h.rowptr.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d.col, h.col.data(), nnz * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d.val, h.val.data(), nnz * sizeof(double), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(d.valf, vf.data(), nnz * sizeof(float), hipMemcpyHostToDevice));
+  return d;
+}
+
 DevSparse upload(const HostSparse& h, hipStream_t s) {
   DevSparse d;
   const size_t n = (size_t)h.n_out * h.width;
@@ -327,14 +433,17 @@ template <typename T>
 void launch_fused(mfpff_ctx* c, const Level& L, int mode, int epi, CellArgs<T> a, const Epilogue<T>& e) {
   if (L.g.slit) {
     // slit levels: the cell kernel computes at the Gauss points and scatters through the slit-aware
-    // node map with atomics; the identity rows (and, for a residual, b) follow elementwise
-    if (epi == EPI_CHEB) throw StatusError{MFPFF_ERR_ARG, "no smoothing on a slit level (one level only)"};
+    // node map with atomics; the identity rows (and, for a residual, b) follow elementwise, then
+    // the Chebyshev start or step (a step's product t = A_blk z is formed in z')
     k_fill<T>(e.y, T(0), L.n, c->s);
     a.y = e.y;
     a.qd = nullptr;
     a.elem = nullptr;
     HIPCHK(launch_cell<T>(mode, a, tab<T>(c, L.g.k), c->s));
     k_slit_epilogue<T>(e.y, a.x, epi == EPI_RESID ? e.b : nullptr, a.mask, L.nn, c->dim, c->s);
+    if (epi == EPI_RESID && e.z0) k_cheb_init<T>(e.z0, e.d0, e.y, e.dinv, L.nn, c->dim, e.ith_u, e.ith_p, c->s);
+    if (epi == EPI_CHEB)
+      k_cheb_update<T>(e.y, e.d, a.x, e.r, e.y, e.dinv, L.nn, c->dim, e.c1u, e.c2u, e.c1p, e.c2p, e.xacc, e.xout, c->s);
     LAUNCHCHK();
     return;
   }
@@ -471,6 +580,17 @@ void transfer(mfpff_ctx* c, int l, int dir, const T* in, T* out, bool add, T* ta
   Level& F = c->lv[l];
   Level& C = c->lv[l - 1];
   const int d = c->dim, nc = d + 1;
+  if (F.g.slit) {
+    // slit levels: the CSR prolongation or its transpose, masked on both sides
+    if (dir == 0) {
+      k_csr_transfer<T>(out, in, F.SP.view(), C.mask, F.mask, F.nn, C.nn, d, add, c->s);
+    } else {
+      k_csr_transfer<T>(out, in, F.SR.view(), F.mask, C.mask, C.nn, F.nn, d, false, c->s);
+      if (cs.z0) k_cheb_init<T>(cs.z0, cs.d0, out, cs.dinv, C.nn, d, cs.ith_u, cs.ith_p, c->s);
+    }
+    LAUNCHCHK();
+    return;
+  }
   if (dir == 0 && d == 2 && F.P1.s.width <= 5) {
     k_prolong<T>(out, in, F.P1.s, C.mask, F.mask, F.g, C.g, add, c->s);
   } else if (dir == 0) {
@@ -1145,9 +1265,10 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
   if (p.split != MFPFF_SPLIT_AMOR && p.split != MFPFF_SPLIT_MIEHE && p.split != MFPFF_SPLIT_NONE) return MFPFF_ERR_ARG;
   if (p.pdas_project != 0 && p.pdas_project != 1) return MFPFF_ERR_ARG;
   if (p.contraction != MFPFF_CONTRACT_VALU && p.contraction != MFPFF_CONTRACT_MFMA) return MFPFF_ERR_ARG;
-  // the slit geometry: one level (its exact coarse solve is the preconditioner), an even cell count
+  // the slit geometry: an even cell count on every level (the slit ends at a node)
   if (p.slit != 0 && p.slit != 1) return MFPFF_ERR_ARG;
-  if (p.slit && (p.n_levels != 1 || p.level_N[0] % 2 != 0)) return MFPFF_ERR_ARG;
+  for (int l = 0; p.slit && l < p.n_levels; ++l)
+    if (p.level_N[l] % 2 != 0) return MFPFF_ERR_ARG;
   if (!(p.eps > 0.0) || !(p.kappa > -1.0 && p.kappa < 1.0) || !(p.cheb_hi > p.cheb_lo) || !(p.cheb_lo > 0.0)) return MFPFF_ERR_ARG;
   for (int l = 0; l < p.n_levels; ++l) {
     if (p.level_N[l] < 1 || p.level_k[l] < 1 || p.level_k[l] > kMaxDeg) return MFPFF_ERR_ARG;
@@ -1208,6 +1329,13 @@ mfpff_status mfpff_setup_mesh_levels(const mfpff_problem* prob, void* hip_stream
         build_transfer(L.g, c->lv[l - 1].g, P, R);
         L.P1 = upload(P, c->s);
         L.R1 = upload(R, c->s);
+        if (p.slit) {
+          const long long nnz = (long long)L.nn * (long long)std::pow((double)P.width, d);
+          if (nnz >= (1LL << 31)) throw StatusError{MFPFF_ERR_ARG, "slit level too large for its CSR transfer"};
+          const HostCsr SP = build_slit_prolongation(L.g, c->lv[l - 1].g, P);
+          L.SP = upload_csr(SP);
+          L.SR = upload_csr(csr_transpose(SP));
+        }
       }
       const int k = L.g.k;
       if (!c->tab64[k]) {
@@ -1310,6 +1438,12 @@ void mfpff_destroy(mfpff_ctx* c) {
     F(L.R1.col);
     F(L.R1.val);
     F(L.R1.valf);
+    for (DevCsrBuf* b : {&L.SP, &L.SR}) {
+      F(b->rowptr);
+      F(b->col);
+      F(b->val);
+      F(b->valf);
+    }
   }
   for (int k = 0; k <= kMaxDeg; ++k) {
     F(c->tab64[k]);

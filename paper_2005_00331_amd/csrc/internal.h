@@ -242,6 +242,16 @@ struct Sparse1D {
   const double* val;        // n_out*width
   const float* valf;
 };
+// a CSR matrix on the device (the transfers of slit levels)
+struct CsrDev {
+  const int* rowptr;  // n_rows + 1
+  const int* col;
+  const double* val;
+  const float* valf;
+};
+template <typename T>
+void k_csr_transfer(T* out, const T* in, const CsrDev& A, const uint8_t* mask_in, const uint8_t* mask_out, long long n_out,
+                    long long n_in, int dim, bool add, hipStream_t s);
 // Chebyshev start written by a restriction's last pass: z0 = d0 = D^-1 out / theta_b (z0 null: none)
 template <typename T>
 struct ChebStart {

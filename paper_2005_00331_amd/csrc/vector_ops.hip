@@ -188,6 +188,13 @@ __global__ void inject_kernel(double* lin_c, uint8_t* mask_c, const double* lin_
       fi += ia * ratio * fs;
       fs *= gf.M;
     }
+    if (gc.slit && i >= gc.n_grid) {
+      // a coarse duplicate (slit node, side above the slit) takes the fine duplicate at its
+      // position: duplicates are numbered along the first axis, then the second (3D)
+      const long long sx_c = (long long)gc.k * gc.N / 2, sx_f = (long long)gf.k * gf.N / 2;
+      const long long j = i - gc.n_grid, i0 = j % sx_c, i1 = j / sx_c;
+      fi = gf.n_grid + i0 * ratio + (gc.dim == 3 ? sx_f * (i1 * ratio) : 0);
+    }
     fi = MFPFF_IN(fi, nnf);
     for (int c = 0; c < gc.dim + 2; ++c) lin_c[c * nnc + i] = lin_f[c * nnf + fi];
     mask_c[i] = (uint8_t)(mask_f[fi] & kMaskPhi) | dirichlet_bit(i, gc, dirichlet);
@@ -257,6 +264,43 @@ template void k_slit_epilogue<float>(float*, const float*, const float*, const u
 void k_lumped_mass(double* ml, const Geom& g, const double* w1d, hipStream_t s) {
   hipLaunchKernelGGL(lumped_mass_kernel, dim3(grid_for(g.n_nodes)), dim3(kThreads), 0, s, ml, g, w1d);
 }
+
+// Transfer between a slit level and the next coarser one by a CSR matrix per component (rows:
+// output nodes): out = M_out A M_in in, i.e. fixed outputs are 0 (left unchanged with add) and
+// fixed inputs are skipped; the prolongation and its transpose, the restriction, both use it
+template <typename T>
+__global__ void csr_transfer_kernel(T* out, const T* in, CsrDev A, const uint8_t* mask_in, const uint8_t* mask_out,
+                                    long long n_out, long long n_in, int dim, int add) {
+  const long long n = (long long)(dim + 1) * n_out;
+  GSTRIDE(i, n) {
+    const int cc = (int)(i / n_out);
+    const long long node = i - (long long)cc * n_out;
+    const bool ofix = mask_out && fixed_at(mask_out, i, n_out, dim);
+    T acc = 0;
+    if (!ofix) {
+      for (int e = A.rowptr[node]; e < A.rowptr[node + 1]; ++e) {
+        const long long j = (long long)cc * n_in + MFPFF_IN(A.col[e], n_in);
+        if (mask_in && fixed_at(mask_in, j, n_in, dim)) continue;
+        acc += (sizeof(T) == 8 ? (T)A.val[e] : (T)A.valf[e]) * in[j];
+      }
+    }
+    if (add) {
+      if (!ofix) out[i] += acc;
+    } else {
+      out[i] = ofix ? T(0) : acc;
+    }
+  }
+}
+template <typename T>
+void k_csr_transfer(T* out, const T* in, const CsrDev& A, const uint8_t* mask_in, const uint8_t* mask_out, long long n_out,
+                    long long n_in, int dim, bool add, hipStream_t s) {
+  hipLaunchKernelGGL(csr_transfer_kernel<T>, dim3(grid_for((long long)(dim + 1) * n_out)), dim3(kThreads), 0, s, out, in, A,
+                     mask_in, mask_out, n_out, n_in, dim, add ? 1 : 0);
+}
+template void k_csr_transfer<double>(double*, const double*, const CsrDev&, const uint8_t*, const uint8_t*, long long,
+                                     long long, int, bool, hipStream_t);
+template void k_csr_transfer<float>(float*, const float*, const CsrDev&, const uint8_t*, const uint8_t*, long long,
+                                    long long, int, bool, hipStream_t);
 
 // Algorithm 1 active set: -(M_L^-1 R_phi)_i + c (phi - phi_old)_i > 0
 __global__ void active_set_kernel(uint8_t* act, const double* R, const double* phi, const double* phi_old, const double* ml,

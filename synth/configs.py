@@ -39,7 +39,7 @@ class Config:
     split: str = "amor"       # tension/compression split: "amor" (workloads), "miehe" (spectral), "none" (isotropic)
     pdas_project: bool = False  # Algorithm 1 as written (delta phi = 0 on A) or phi := phi_old on A first
     slit: bool = False          # geometry of Section 5.1: a slit from x = 0 to 1/2 on the mid-plane of the
-                                # last axis, its nodes duplicated (single level); no phi = 0 notch band then
+                                # last axis, its nodes duplicated (on every level); no phi = 0 notch band then
     contraction: str = "valu"   # 3D products at degree 3/4: 1D contractions on the vector unit or the matrix cores ("mfma")
     seed_index: int = 0
     lanczos_seed: int = 20050331

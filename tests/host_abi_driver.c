@@ -73,7 +73,7 @@ int main(void) {
   p = good(); p.pdas_project = 2; expect_rejected(p);
   p = good(); p.contraction = 2; expect_rejected(p);
   p = good(); p.slit = 2; expect_rejected(p);
-  p = good(); p.slit = 1; expect_rejected(p);                 /* two levels */
+  p = good(); p.slit = 1; p.level_N[0] = 3; p.level_N[1] = 6; expect_rejected(p);  /* odd coarse N */
   p = good(); p.n_levels = 1; p.level_N[0] = 7; p.slit = 1; expect_rejected(p);  /* odd N */
   p = good(); p.eps = 0.0; expect_rejected(p);
   p = good(); p.kappa = -1.0; expect_rejected(p);

@@ -50,7 +50,7 @@ def test_invalid_problems_rejected_without_device(lib):
     h = ctypes.c_void_p()
     good = binding.make_problem(2, [(4, 1), (8, 1)], eps=0.25)
     for field, bad in [("dim", 5), ("n_levels", 0), ("cheb_degree", 0), ("restart", 0), ("vcycle_prec", 7),
-                       ("split", 3), ("pdas_project", 2), ("contraction", 2), ("slit", 2), ("slit", 1), ("kappa", -1.0), ("kappa", 1.0),
+                       ("split", 3), ("pdas_project", 2), ("contraction", 2), ("slit", 2), ("kappa", -1.0), ("kappa", 1.0),
                        ("kappa", float("nan"))]:
         p = binding.make_problem(2, [(4, 1), (8, 1)], eps=0.25)
         setattr(p, field, bad)
@@ -58,6 +58,8 @@ def test_invalid_problems_rejected_without_device(lib):
     p = binding.make_problem(2, [(4, 1), (8, 2)], eps=0.25)       # neither an h- nor a p-step
     assert lib.mfpff_setup_mesh_levels(ctypes.byref(p), None, ctypes.byref(h)) == 1
     p = binding.make_problem(2, [(7, 1)], eps=0.25, slit=True)     # the slit needs an even N
+    assert lib.mfpff_setup_mesh_levels(ctypes.byref(p), None, ctypes.byref(h)) == 1
+    p = binding.make_problem(2, [(3, 1), (6, 1)], eps=0.25, slit=True)  # ... on every level
     assert lib.mfpff_setup_mesh_levels(ctypes.byref(p), None, ctypes.byref(h)) == 1
     p = binding.make_problem(2, [(8, 5)], eps=0.25)                # degree above 4
     assert lib.mfpff_setup_mesh_levels(ctypes.byref(p), None, ctypes.byref(h)) == 1

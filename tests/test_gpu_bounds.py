@@ -3,7 +3,7 @@
 range, and an index outside it is counted (and replaced by 0, so nothing faults).  A child process
 loads that build and runs every parity case through every entry point (products on every level,
 diagonals, smoothing, transfers, coarse solve, V-cycle, FGMRES, residual and its cotangents), the
-slit meshes, a full-size 2D product (the many-tile launch) and a load step; no index may be out
+slit meshes and slit hierarchies, a full-size 2D product (the many-tile launch) and a load step; no index may be out
 of range, and the finest-level products still match the oracle."""
 import os
 import subprocess
@@ -79,6 +79,11 @@ for name in sorted(CASES):
 for base, kw in (("C1", dict(N=16)), ("C2", dict(N=8)), ("C1", dict(dim=3, N=6))):
     cfg = CONFIGS[base].with_(n_h_levels=1, p_coarse=(), slit=True, phi_mode="smooth", **kw)
     run_case("slit_" + base + str(kw), cfg, [(cfg.N, cfg.k)], level_args)
+# slit hierarchies: side-aware transfers, injection of duplicates, smoothing on slit levels
+for base, levels, kw in (("C2", [(4, 1), (4, 2), (8, 2)], {}), ("C1", [(2, 1), (4, 1)], dict(dim=3))):
+    cfg = CONFIGS[base].with_(N=levels[-1][0], k=levels[-1][1], n_h_levels=1, p_coarse=(), slit=True,
+                              phi_mode="smooth", **kw)
+    run_case("slit_mg_" + base + str(levels), cfg, levels, None)
 # the full-size 2D Q2 level (1369 tiles: the many-workgroup launch of the 2D kernel)
 cfg = CONFIGS["C2"]
 inp = make_inputs(cfg)
