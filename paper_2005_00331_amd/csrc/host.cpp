@@ -692,12 +692,27 @@ void vcycle_rec(mfpff_ctx* c, int l, bool started = false) {
   post_smooth<T>(c, l, b, x, r, zA, zB, d, t);
 }
 
+// the finest level's Chebyshev start is written with its right-hand side (vstart)
 void vcycle_body(mfpff_ctx* c) {
-  if (c->f32) vcycle_rec<float>(c, c->L);
-  else vcycle_rec<double>(c, c->L);
+  if (c->f32) vcycle_rec<float>(c, c->L, c->L > 0);
+  else vcycle_rec<double>(c, c->L, c->L > 0);
 }
 
-// Record the V-cycle (finest WB -> WX) into a graph on a private stream.  The
+// where the V-cycle's input writes the finest level's Chebyshev start (none on one level)
+VStart vstart(mfpff_ctx* c) {
+  VStart v{};
+  if (c->L == 0) return v;
+  Level& F = c->lv[c->L];
+  v.z0 = F.w[c->prob.cheb_degree == 1 ? WX : WZ];
+  v.d0 = F.w[WD];
+  v.dinv = c->f32 ? (const void*)F.dinv32 : (const void*)F.dinv;
+  v.ith_u = F.ith_u;
+  v.ith_p = F.ith_p;
+  v.nu = (long long)c->dim * F.nn;
+  return v;
+}
+
+// Record the V-cycle (finest WB and its Chebyshev start -> WX) into a graph on a private stream.  The
 // launches only read level buffers, tables and coefficients that stay fixed
 // until the next linearisation.  Any failure leaves the direct launch path.
 void capture_vcycle(mfpff_ctx* c) {
@@ -737,13 +752,12 @@ void capture_vcycle(mfpff_ctx* c) {
   }
 }
 
-// z = V(r) on the finest level, FP64 in/out
-// z = V(r); b_ready: the caller has already written r into the finest level's right-hand side
+// z = V(r) on the finest level, FP64 in/out; b_ready: the caller has already written r into the
+// finest level's right-hand side and its Chebyshev start
 void precondition(mfpff_ctx* c, const double* r, double* z, bool b_ready = false) {
   Level& F = c->lv[c->L];
   if (!b_ready) {
-    if (c->f32) k_cast_d2f((float*)F.w[WB], r, F.n, c->s);
-    else k_copy<double>((double*)F.w[WB], r, F.n, c->s);
+    k_vcycle_input(F.w[WB], c->f32, r, F.n, vstart(c), c->s);
     LAUNCHCHK();
   }
   if (c->vgraph) HIPCHK(hipGraphLaunch(c->vgraph, c->s));
@@ -964,8 +978,10 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
   if (bnorm == 0.0) {
     conv = true;
   }
-  // v_j is written together with the V-cycle's right-hand side (FP32 for the mixed V-cycle)
+  // v_j is written together with the V-cycle's right-hand side (FP32 for the mixed V-cycle) and
+  // the finest level's Chebyshev start
   void* vb = c->lv[c->L].w[WB];
+  const VStart vs = vstart(c);
   // step j: z_j = V(v_j), w = G^ z_j, CGS2 against v_0..v_j into buffer j % 2, copied to the host
   auto arnoldi = [&](int j) {
     double* vj = c->V + (size_t)j * c->ldv;
@@ -1008,13 +1024,14 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
     g[0] = beta;
     c->hhost[kHostBeta] = beta;  // pinned staging, not a target of any device-to-host copy
     HIPCHK(hipMemcpyAsync(c->ycoef, &c->hhost[kHostBeta], sizeof(double), hipMemcpyHostToDevice, c->s));
-    k_scale_dev(c->V, c->gr, c->ycoef, n, c->s, vb, c->f32);
+    k_scale_dev(c->V, c->gr, c->ycoef, n, c->s, vb, c->f32, vs);
     arnoldi(0);
     int jend = 0;
     for (int j = 0; j < m; ++j) {
       if (j + 1 < m) {
         // queue step j+1: v_{j+1} = w / |w| with |w|^2 from buffer j % 2
-        k_scale_rsqrt_dev(c->V + (size_t)(j + 1) * c->ldv, c->gw, c->hdev + (j & 1) * kHBuf + 160, n, c->s, vb, c->f32);
+        k_scale_rsqrt_dev(c->V + (size_t)(j + 1) * c->ldv, c->gw, c->hdev + (j & 1) * kHBuf + 160, n, c->s, vb, c->f32,
+                          vs);
         arnoldi(j + 1);
       }
       HIPCHK(hipEventSynchronize(c->hev[j & 1]));

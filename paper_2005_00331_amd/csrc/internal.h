@@ -207,11 +207,23 @@ void k_multidot_partials(double* part, const double* V, long long ldv, int nvec,
 void k_multidot_finish(double* out, const double* part, int nblocks, int nvec, hipStream_t s);
 void k_seg_dot_partials(double* part, const double* a, const double* b, long long nu, long long n, hipStream_t s);
 void k_maxpy_dev(double* w, const double* V, long long ldv, int nvec, const double* coef, double sign, long long n, hipStream_t s);
+// The finest level's Chebyshev start written with the V-cycle's right-hand side b (in the
+// V-cycle's precision): z0 = d0 = D^-1 b / theta per block (z0 null: none, a one-level V-cycle)
+struct VStart {
+  void* z0 = nullptr;
+  void* d0 = nullptr;
+  const void* dinv = nullptr;
+  double ith_u = 1.0, ith_p = 1.0;
+  long long nu = 0;  // displacement dofs (the u block ends there)
+};
 // y = x / denom[0] (rsqrt: x / sqrt(denom[0])); y2, if given, receives a copy (FP32 when y2_f32)
+// and then vs the Chebyshev start from that copy
 void k_scale_dev(double* y, const double* x, const double* denom, long long n, hipStream_t s, void* y2 = nullptr,
-                 bool y2_f32 = false);
+                 bool y2_f32 = false, const VStart& vs = VStart{});
 void k_scale_rsqrt_dev(double* y, const double* x, const double* sq, long long n, hipStream_t s, void* y2 = nullptr,
-                       bool y2_f32 = false);
+                       bool y2_f32 = false, const VStart& vs = VStart{});
+// b = r in the V-cycle's precision and the Chebyshev start from it
+void k_vcycle_input(void* b, bool b_f32, const double* r, long long n, const VStart& vs, hipStream_t s);
 // Arnoldi passes (modes: 0 dots, 1 update + dots, 2 update + squared norm), each followed by
 // a one-workgroup launch that finishes the reduction into out; nvec <= kOrthMax; part holds
 // orth_blocks(n) * nvec doubles

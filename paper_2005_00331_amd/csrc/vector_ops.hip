@@ -659,27 +659,74 @@ void k_orth_pass(int mode, double* w, const double* V, long long ldv, int nvec, 
 }
 
 // y = x / d with d = denom[0], or d = sqrt(denom[0]) when SQ; optionally also y2 = y in the
-// precision of the V-cycle (the preconditioner's input)
+// precision of the V-cycle (the preconditioner's input) and the finest level's Chebyshev start
+// from y2 (the same expression as cheb_init_kernel)
+template <typename T2>
+struct StartT {
+  T2* z0;
+  T2* d0;
+  const T2* dinv;
+  T2 itu, itp;
+  long long nu;
+};
+template <typename T2>
+StartT<T2> start_t(const VStart& v) {
+  return StartT<T2>{(T2*)v.z0, (T2*)v.d0, (const T2*)v.dinv, (T2)v.ith_u, (T2)v.ith_p, v.nu};
+}
+template <typename T2>
+__device__ __forceinline__ void write_start(const StartT<T2>& cs, long long i, T2 b) {
+  if (cs.z0) {
+    const T2 z = cs.dinv[i] * b * (i < cs.nu ? cs.itu : cs.itp);
+    cs.z0[i] = z;
+    cs.d0[i] = z;
+  }
+}
 template <bool SQ, typename T2>
-__global__ void scale_dev_kernel(double* y, T2* y2, const double* x, const double* denom, long long n) {
+__global__ void scale_dev_kernel(double* y, T2* y2, const double* x, const double* denom, long long n, StartT<T2> cs) {
   const double d = SQ ? sqrt(denom[0]) : denom[0];
   GSTRIDE(i, n) {
     const double v = x[i] / d;
     y[i] = v;
-    if (y2) y2[i] = (T2)v;
+    if (y2) {
+      const T2 b = (T2)v;
+      y2[i] = b;
+      write_start(cs, i, b);
+    }
   }
 }
-void k_scale_dev(double* y, const double* x, const double* denom, long long n, hipStream_t s, void* y2, bool y2_f32) {
+template <bool SQ>
+void launch_scale(double* y, const double* x, const double* denom, long long n, hipStream_t s, void* y2, bool y2_f32,
+                  const VStart& vs) {
   if (y2_f32)
-    hipLaunchKernelGGL((scale_dev_kernel<false, float>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, (float*)y2, x, denom, n);
+    hipLaunchKernelGGL((scale_dev_kernel<SQ, float>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, (float*)y2, x, denom, n,
+                       start_t<float>(vs));
   else
-    hipLaunchKernelGGL((scale_dev_kernel<false, double>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, (double*)y2, x, denom, n);
+    hipLaunchKernelGGL((scale_dev_kernel<SQ, double>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, (double*)y2, x, denom, n,
+                       start_t<double>(vs));
 }
-void k_scale_rsqrt_dev(double* y, const double* x, const double* sq, long long n, hipStream_t s, void* y2, bool y2_f32) {
-  if (y2_f32)
-    hipLaunchKernelGGL((scale_dev_kernel<true, float>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, (float*)y2, x, sq, n);
+void k_scale_dev(double* y, const double* x, const double* denom, long long n, hipStream_t s, void* y2, bool y2_f32,
+                 const VStart& vs) {
+  launch_scale<false>(y, x, denom, n, s, y2, y2_f32, vs);
+}
+void k_scale_rsqrt_dev(double* y, const double* x, const double* sq, long long n, hipStream_t s, void* y2, bool y2_f32,
+                       const VStart& vs) {
+  launch_scale<true>(y, x, sq, n, s, y2, y2_f32, vs);
+}
+template <typename T2>
+__global__ void vcycle_input_kernel(T2* b, const double* r, long long n, StartT<T2> cs) {
+  GSTRIDE(i, n) {
+    const T2 v = (T2)r[i];
+    b[i] = v;
+    write_start(cs, i, v);
+  }
+}
+void k_vcycle_input(void* b, bool b_f32, const double* r, long long n, const VStart& vs, hipStream_t s) {
+  if (b_f32)
+    hipLaunchKernelGGL(vcycle_input_kernel<float>, dim3(grid_for(n)), dim3(kThreads), 0, s, (float*)b, r, n,
+                       start_t<float>(vs));
   else
-    hipLaunchKernelGGL((scale_dev_kernel<true, double>), dim3(grid_for(n)), dim3(kThreads), 0, s, y, (double*)y2, x, sq, n);
+    hipLaunchKernelGGL(vcycle_input_kernel<double>, dim3(grid_for(n)), dim3(kThreads), 0, s, (double*)b, r, n,
+                       start_t<double>(vs));
 }
 __global__ void sum_pvjp_kernel(double* out, const double* part, int nb) {
   __shared__ double sh[8];
