@@ -59,10 +59,25 @@ __global__ __launch_bounds__(kPanelLanes) void potrf_panel_kernel(double* A, int
   __shared__ double col[TB];
   __shared__ double rinv[TB];  // 1 / L[j][j]
   const int tid = threadIdx.x;
-  for (int e = tid; e < TB * TB; e += blockDim.x) {
-    const int i = e / TB, j = e % TB;
-    const int gi = k0 + i, gj = k0 + j;
-    L[i][j] = (gi < n && gj < n) ? A[(long long)gi * n + gj] : (i == j ? 1.0 : 0.0);
+  // every load of the block (the diagonal block and, for b >= 1, its panel rows) is issued before
+  // the first LDS store, so the block waits for memory once; lane t takes column t % TB of the
+  // rows t / TB + 2 q
+  constexpr int PER = TB * TB / kPanelLanes;
+  const int lj = tid % TB, li = tid / TB;
+  const int r0 = k0 + blockIdx.x * TB;
+  double lv[PER], xv[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = li + q * (kPanelLanes / TB);
+    const int gi = k0 + i, gj = k0 + lj, gx = r0 + i;
+    lv[q] = (gi < n && gj < n) ? A[(long long)gi * n + gj] : (i == lj ? 1.0 : 0.0);
+    xv[q] = (blockIdx.x > 0 && gx < n && gj < n) ? A[(long long)gx * n + gj] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = li + q * (kPanelLanes / TB);
+    L[i][lj] = lv[q];
+    X[i][lj] = xv[q];
   }
   __syncthreads();
   {
@@ -105,13 +120,6 @@ __global__ __launch_bounds__(kPanelLanes) void potrf_panel_kernel(double* A, int
     for (int e = tid; e < TB * TB; e += blockDim.x) diag[e] = L[e / TB][e % TB];
     return;
   }
-  const int r0 = k0 + blockIdx.x * TB;
-  for (int e = tid; e < TB * TB; e += blockDim.x) {
-    const int i = e / TB, j = e % TB;
-    const int gi = r0 + i, gj = k0 + j;
-    X[i][j] = (gi < n && gj < n) ? A[(long long)gi * n + gj] : 0.0;
-  }
-  __syncthreads();
   if (tid < TB) {
     // row tid of X L11^T = A_panel, unrolled so the row stays in registers
     const int i = tid;
@@ -165,11 +173,20 @@ __global__ __launch_bounds__(kThreads) void syrk_update_kernel(double* A, int n,
   const int bj = t;
   const int ri = k1 + bi * TB, rj = k1 + bj * TB;
   const int tid = threadIdx.x;
-  for (int e = tid; e < TB * TB; e += blockDim.x) {
-    const int i = e / TB, l = e % TB;
-    const int gl = k0 + l;
-    Li[i][l] = (ri + i < n && gl < n) ? A[(long long)(ri + i) * n + gl] : 0.0;
-    Lj[i][l] = (rj + i < n && gl < n) ? A[(long long)(rj + i) * n + gl] : 0.0;
+  constexpr int PER = TB * TB / kThreads;
+  const int ll = tid % TB, l0 = tid / TB;
+  double a[PER], b[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = l0 + q * (kThreads / TB);
+    const int gl = k0 + ll;
+    a[q] = (ri + i < n && gl < n) ? A[(long long)(ri + i) * n + gl] : 0.0;
+    b[q] = (rj + i < n && gl < n) ? A[(long long)(rj + i) * n + gl] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    Li[l0 + q * (kThreads / TB)][ll] = a[q];
+    Lj[l0 + q * (kThreads / TB)][ll] = b[q];
   }
   __syncthreads();
   for (int e = tid; e < TB * TB; e += blockDim.x) {
@@ -214,15 +231,26 @@ __global__ __launch_bounds__(kTrsmLanes) void trsm_diag_kernel(double* W, const 
   __shared__ double xs[TB][kTrsmLanes];
   __shared__ double rinv[TB];  // 1 / L11[j][j]
   const int tid = threadIdx.x;
-  for (int e = tid; e < TB * TB; e += blockDim.x) {
-    const int i = e / TB, j = e % TB;
-    const int gi = k0 + i, gj = k0 + j;
-    L11[i][j] = (gi < n && gj < n) ? L[(long long)gi * n + gj] : (i == j ? 1.0 : 0.0);
-  }
-  if (tid < TB) rinv[tid] = (k0 + tid < n) ? 1.0 / L[(long long)(k0 + tid) * n + k0 + tid] : 1.0;
   const int col = blockIdx.x * kTrsmLanes + tid;
   const bool ok = col < ncols;
-  for (int i = 0; i < TB; ++i) xs[i][tid] = (ok && k0 + i < n) ? W[(long long)(k0 + i) * n + col] : 0.0;
+  // all loads (L11 and this lane's column of the TB rows of W) before the first LDS store
+  constexpr int PER = TB * TB / kTrsmLanes;
+  const int lj = tid % TB, li = tid / TB;
+  double lv[PER], wv[TB];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = li + q * (kTrsmLanes / TB);
+    const int gi = k0 + i, gj = k0 + lj;
+    lv[q] = (gi < n && gj < n) ? L[(long long)gi * n + gj] : (i == lj ? 1.0 : 0.0);
+  }
+#pragma unroll
+  for (int i = 0; i < TB; ++i) wv[i] = (ok && k0 + i < n) ? W[(long long)(k0 + i) * n + col] : 0.0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) L11[li + q * (kTrsmLanes / TB)][lj] = lv[q];
+#pragma unroll
+  for (int i = 0; i < TB; ++i) xs[i][tid] = wv[i];
+  __syncthreads();
+  if (tid < TB) rinv[tid] = 1.0 / L11[tid][tid];
   __syncthreads();
   double xr[TB];
 #pragma clang loop unroll(full)
@@ -248,10 +276,19 @@ __global__ __launch_bounds__(kThreads) void trsm_update_kernel(double* W, const 
   const int r0 = k0 + TB + blockIdx.y * TB;
   const int c0 = blockIdx.x * TB;
   const int tid = threadIdx.x;
-  for (int e = tid; e < TB * TB; e += blockDim.x) {
-    const int i = e / TB, l = e % TB;
-    Ls[i][l] = (r0 + i < n && k0 + l < n) ? L[(long long)(r0 + i) * n + k0 + l] : 0.0;
-    Ws[i][l] = (k0 + i < n && c0 + l < ncols) ? W[(long long)(k0 + i) * n + c0 + l] : 0.0;
+  constexpr int PER = TB * TB / kThreads;
+  const int ll = tid % TB, l0 = tid / TB;
+  double a[PER], b[PER];
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int i = l0 + q * (kThreads / TB);
+    a[q] = (r0 + i < n && k0 + ll < n) ? L[(long long)(r0 + i) * n + k0 + ll] : 0.0;
+    b[q] = (k0 + i < n && c0 + ll < ncols) ? W[(long long)(k0 + i) * n + c0 + ll] : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    Ls[l0 + q * (kThreads / TB)][ll] = a[q];
+    Ws[l0 + q * (kThreads / TB)][ll] = b[q];
   }
   __syncthreads();
   for (int e = tid; e < TB * TB; e += blockDim.x) {
