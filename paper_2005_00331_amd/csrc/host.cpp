@@ -991,10 +991,11 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
     precondition(c, vj, zj, true);
     apply_op<double>(c, c->L, MODE_APPLY, zj, c->gw, nullptr);
     if (j + 1 <= kOrthMax) {
-      // three passes over V (each with all basis vectors at once)
+      // two passes over V (each with all basis vectors at once): h1 = V^T w; w -= V h1 with
+      // h2 = V^T w and |w|^2.  The second projection w -= V h2 is applied with the
+      // normalisation of v_{j+1} (k_orth_normalize), |w - V h2|^2 = |w|^2 - |h2|^2
       k_orth_pass(0, c->gw, c->V, c->ldv, j + 1, nullptr, c->part, h1, n, c->s);
-      k_orth_pass(1, c->gw, c->V, c->ldv, j + 1, h1, c->part, h2, n, c->s);
-      k_orth_pass(2, c->gw, c->V, c->ldv, j + 1, h2, c->part, hn, n, c->s);
+      k_orth_pass(3, c->gw, c->V, c->ldv, j + 1, h1, c->part, h2, n, c->s);
     } else {
       k_multidot_partials(c->part, c->V, c->ldv, j + 1, c->gw, n, c->s);
       k_multidot_finish(h1, c->part, nb, j + 1, c->s);
@@ -1029,14 +1030,25 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
     int jend = 0;
     for (int j = 0; j < m; ++j) {
       if (j + 1 < m) {
-        // queue step j+1: v_{j+1} = w / |w| with |w|^2 from buffer j % 2
-        k_scale_rsqrt_dev(c->V + (size_t)(j + 1) * c->ldv, c->gw, c->hdev + (j & 1) * kHBuf + 160, n, c->s, vb, c->f32,
-                          vs);
+        // queue step j+1: v_{j+1} from w and the sums of step j in buffer j % 2
+        double* hb = c->hdev + (j & 1) * kHBuf;
+        if (j + 1 <= kOrthMax)
+          k_orth_normalize(c->V + (size_t)(j + 1) * c->ldv, vb, c->f32, c->gw, c->V, c->ldv, j + 1, hb + 80, n, vs, c->s);
+        else
+          k_scale_rsqrt_dev(c->V + (size_t)(j + 1) * c->ldv, c->gw, hb + 160, n, c->s, vb, c->f32, vs);
         arnoldi(j + 1);
       }
       HIPCHK(hipEventSynchronize(c->hev[j & 1]));
       const double* hh = c->hhost + (j & 1) * kHBuf;
-      const double hnorm = std::sqrt(hh[160]);
+      double hnorm;
+      if (j + 1 <= kOrthMax) {
+        // |w - V h2| by Pythagoras, in the order the normalisation kernel takes
+        double hn2 = hh[80 + j + 1];
+        for (int i = 0; i <= j; ++i) hn2 -= hh[80 + i] * hh[80 + i];
+        hnorm = hn2 > 0.0 ? std::sqrt(hn2) : 0.0;
+      } else {
+        hnorm = std::sqrt(hh[160]);
+      }
       for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[80 + i];
       H[(size_t)(j + 1) * m + j] = hnorm;
       for (int i = 0; i < j; ++i) {

@@ -224,13 +224,17 @@ void k_scale_rsqrt_dev(double* y, const double* x, const double* sq, long long n
                        bool y2_f32 = false, const VStart& vs = VStart{});
 // b = r in the V-cycle's precision and the Chebyshev start from it
 void k_vcycle_input(void* b, bool b_f32, const double* r, long long n, const VStart& vs, hipStream_t s);
-// Arnoldi passes (modes: 0 dots, 1 update + dots, 2 update + squared norm), each followed by
-// a one-workgroup launch that finishes the reduction into out; nvec <= kOrthMax; part holds
-// orth_blocks(n) * nvec doubles
+// Arnoldi passes (modes: 0 dots, 1 update + dots, 2 update + squared norm, 3 update + dots +
+// squared norm), each followed by a one-workgroup launch that finishes the reduction into out;
+// nvec <= kOrthMax; part holds orth_blocks(n) * (nvec + 1) doubles
 constexpr int kOrthMax = 32;
 int orth_blocks(long long n);
 void k_orth_pass(int mode, double* w, const double* V, long long ldv, int nvec, const double* coef, double* part,
                  double* out, long long n, hipStream_t s);
+// vout = (w - V c) / sqrt(c[nvec] - |c|^2) with c from mode 3 (0 when that is not positive), and
+// y2 = vout in the V-cycle's precision with the Chebyshev start vs
+void k_orth_normalize(double* vout, void* y2, bool y2_f32, const double* w, const double* V, long long ldv, int nvec,
+                      const double* coef, long long n, const VStart& vs, hipStream_t s);
 void k_sum_pvjp(double* out2, const double* part, int nblocks, hipStream_t s);
 
 // CG-Lanczos device scalars

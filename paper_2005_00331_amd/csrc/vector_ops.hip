@@ -548,7 +548,8 @@ void k_maxpy_dev(double* w, const double* V, long long ldv, int nvec, const doub
 //   ORTH_DOTS:        part -> V_j . w
 //   ORTH_UPDATE_DOTS: w <- w - V c;  part -> V_j . w        (c on the device)
 //   ORTH_UPDATE_NORM: w <- w - V c;  part -> w . w
-enum OrthMode : int { ORTH_DOTS = 0, ORTH_UPDATE_DOTS = 1, ORTH_UPDATE_NORM = 2 };
+//   ORTH_UPDATE_DOTS_NORM: w <- w - V c;  part -> V_j . w, then w . w (nvec + 1 sums)
+enum OrthMode : int { ORTH_DOTS = 0, ORTH_UPDATE_DOTS = 1, ORTH_UPDATE_NORM = 2, ORTH_UPDATE_DOTS_NORM = 3 };
 
 __device__ __forceinline__ double wave_sum(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -559,7 +560,7 @@ template <int MODE, int NV>
 __global__ __launch_bounds__(kThreads) void orth_pass_kernel(double* __restrict__ w, const double* __restrict__ V,
                                                              long long ldv, const double* __restrict__ coef,
                                                              double* __restrict__ part, long long n) {
-  constexpr int NA = MODE == ORTH_UPDATE_NORM ? 1 : NV;  // accumulators per thread
+  constexpr int NA = MODE == ORTH_UPDATE_NORM ? 1 : (MODE == ORTH_UPDATE_DOTS_NORM ? NV + 1 : NV);  // sums per thread
   constexpr int NW = kThreads / 64;
   __shared__ double sh[NW][NA];
   double c[NV];
@@ -595,7 +596,8 @@ __global__ __launch_bounds__(kThreads) void orth_pass_kernel(double* __restrict_
         acc[0] += wl[e] * wl[e];
       } else {
 #pragma unroll
-        for (int j = 0; j < NA; ++j) acc[j] += reinterpret_cast<const double*>(&v[j])[e] * wl[e];
+        for (int j = 0; j < NV; ++j) acc[j] += reinterpret_cast<const double*>(&v[j])[e] * wl[e];
+        if (MODE == ORTH_UPDATE_DOTS_NORM) acc[NV] += wl[e] * wl[e];
       }
     }
     if (MODE != ORTH_DOTS) *reinterpret_cast<V2*>(w + i) = wi;
@@ -652,9 +654,11 @@ void k_orth_pass(int mode, double* w, const double* V, long long ldv, int nvec, 
     launch_orth<ORTH_DOTS, 1>(nvec, w, V, ldv, coef, part, n, s);
   else if (mode == ORTH_UPDATE_DOTS)
     launch_orth<ORTH_UPDATE_DOTS, 1>(nvec, w, V, ldv, coef, part, n, s);
-  else
+  else if (mode == ORTH_UPDATE_NORM)
     launch_orth<ORTH_UPDATE_NORM, 1>(nvec, w, V, ldv, coef, part, n, s);
-  const int nout = mode == ORTH_UPDATE_NORM ? 1 : nvec;
+  else
+    launch_orth<ORTH_UPDATE_DOTS_NORM, 1>(nvec, w, V, ldv, coef, part, n, s);
+  const int nout = mode == ORTH_UPDATE_NORM ? 1 : (mode == ORTH_UPDATE_DOTS_NORM ? nvec + 1 : nvec);
   hipLaunchKernelGGL(orth_finish_kernel, dim3(1), dim3(kFinishThreads), 0, s, out, part, orth_blocks(n), nout);
 }
 
@@ -712,6 +716,77 @@ void k_scale_rsqrt_dev(double* y, const double* x, const double* sq, long long n
                        const VStart& vs) {
   launch_scale<true>(y, x, sq, n, s, y2, y2_f32, vs);
 }
+// The second Gram-Schmidt projection fused with the normalisation (CGS2 with the norm taken by
+// Pythagoras): c = (h2_0 .. h2_{NV-1}, |w|^2) from ORTH_UPDATE_DOTS_NORM, |w - V h2|^2 =
+// |w|^2 - |h2|^2 since the basis is orthonormal; v = (w - V h2) / |w - V h2| goes to vout and,
+// in the V-cycle's precision, to y2 with the finest level's Chebyshev start.  A non-positive
+// |w - V h2|^2 (w in the span of the basis: the Krylov space is invariant) writes v = 0.
+template <int NV, typename T2>
+__global__ __launch_bounds__(kThreads) void orth_normalize_kernel(double* __restrict__ vout, T2* __restrict__ y2,
+                                                                  const double* __restrict__ w, const double* __restrict__ V,
+                                                                  long long ldv, const double* __restrict__ coef, long long n,
+                                                                  StartT<T2> cs) {
+  double c[NV];
+  double hn2 = coef[NV];
+#pragma unroll
+  for (int j = 0; j < NV; ++j) {
+    c[j] = coef[j];
+    hn2 -= c[j] * c[j];
+  }
+  const double hn = hn2 > 0.0 ? sqrt(hn2) : 0.0;
+  auto one = [&](long long i, double wi, const double* vj) {
+    double t = 0.0;
+#pragma unroll
+    for (int j = 0; j < NV; ++j) t += c[j] * vj[j];
+    const double v = hn > 0.0 ? (wi - t) / hn : 0.0;
+    vout[i] = v;
+    const T2 b = (T2)v;
+    y2[i] = b;
+    write_start(cs, i, b);
+  };
+  const long long stride = (long long)gridDim.x * blockDim.x;
+  const long long gid = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  for (long long p = gid; 2 * p + 1 < n; p += stride) {
+    const long long i = 2 * p;
+    double2 v[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) v[j] = *reinterpret_cast<const double2*>(V + (long long)j * ldv + i);
+    const double2 wi = *reinterpret_cast<const double2*>(w + i);
+    __builtin_amdgcn_sched_barrier(0);
+    double a[NV], b[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) {
+      a[j] = v[j].x;
+      b[j] = v[j].y;
+    }
+    one(i, wi.x, a);
+    one(i + 1, wi.y, b);
+  }
+  if ((n & 1) && gid == 0) {
+    double a[NV];
+#pragma unroll
+    for (int j = 0; j < NV; ++j) a[j] = V[(long long)j * ldv + n - 1];
+    one(n - 1, w[n - 1], a);
+  }
+}
+template <int NV, typename T2>
+static void launch_normalize(int nvec, double* vout, T2* y2, const double* w, const double* V, long long ldv,
+                             const double* coef, long long n, const StartT<T2>& cs, hipStream_t s) {
+  if constexpr (NV <= kOrthMax) {
+    if (nvec == NV) {
+      hipLaunchKernelGGL((orth_normalize_kernel<NV, T2>), dim3(grid_for(n / 2 + 1)), dim3(kThreads), 0, s, vout, y2, w, V, ldv,
+                         coef, n, cs);
+      return;
+    }
+    launch_normalize<NV + 1, T2>(nvec, vout, y2, w, V, ldv, coef, n, cs, s);
+  }
+}
+void k_orth_normalize(double* vout, void* y2, bool y2_f32, const double* w, const double* V, long long ldv, int nvec,
+                      const double* coef, long long n, const VStart& vs, hipStream_t s) {
+  if (y2_f32) launch_normalize<1, float>(nvec, vout, (float*)y2, w, V, ldv, coef, n, start_t<float>(vs), s);
+  else launch_normalize<1, double>(nvec, vout, (double*)y2, w, V, ldv, coef, n, start_t<double>(vs), s);
+}
+
 template <typename T2>
 __global__ void vcycle_input_kernel(T2* b, const double* r, long long n, StartT<T2> cs) {
   GSTRIDE(i, n) {
