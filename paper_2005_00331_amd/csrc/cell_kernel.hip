@@ -559,6 +559,7 @@ __global__ __launch_bounds__(kThreads) void gather3d_kernel(const T* __restrict_
     const T gx = fixed ? xo : sum[cc];
     if (EPI == EPI_APPLY) {
       e.y[idx] = gx;
+      if (e.xcopy) e.xcopy[idx] = xo;
     } else if (EPI == EPI_RESID) {
       const T rv = e.b[idx] - gx;
       e.y[idx] = rv;

@@ -441,6 +441,7 @@ void launch_fused(mfpff_ctx* c, const Level& L, int mode, int epi, CellArgs<T> a
     a.elem = nullptr;
     HIPCHK(launch_cell<T>(mode, a, tab<T>(c, L.g.k), c->s));
     k_slit_epilogue<T>(e.y, a.x, epi == EPI_RESID ? e.b : nullptr, a.mask, L.nn, c->dim, c->s);
+    if (epi == EPI_APPLY && e.xcopy) k_copy<T>(e.xcopy, a.x, L.n, c->s);
     if (epi == EPI_RESID && e.z0) k_cheb_init<T>(e.z0, e.d0, e.y, e.dinv, L.nn, c->dim, e.ith_u, e.ith_p, c->s);
     if (epi == EPI_CHEB)
       k_cheb_update<T>(e.y, e.d, a.x, e.r, e.y, e.dinv, L.nn, c->dim, e.c1u, e.c2u, e.c1p, e.c2p, e.xacc, e.xout, c->s);
@@ -481,10 +482,11 @@ void residual_launch(mfpff_ctx* c, const double* u, const double* phi, const dou
   HIPCHK(launch_cell<double>(MODE_RESIDUAL, a, c->tab64[F.g.k], c->s));
 }
 
-// y = op(G^) x on level l, or y = b - G^ x when b != null (op = G);
+// y = op(G^) x on level l, or y = b - G^ x when b != null (op = G); xcopy (b null): also a copy
+// of x, written by the product's epilogue;
 // accumulate: y += P op(G) P x without initialising y (atomic cell kernel)
 template <typename T>
-void apply_op(mfpff_ctx* c, int l, int mode, const T* x, T* y, const T* b, bool accumulate = false) {
+void apply_op(mfpff_ctx* c, int l, int mode, const T* x, T* y, const T* b, bool accumulate = false, T* xcopy = nullptr) {
   Level& L = c->lv[l];
   const T scale = b ? T(-1) : T(1);
   CellArgs<T> a = cell_args<T>(c, L, level_lin<T>(c, L), x, y, scale);
@@ -492,6 +494,7 @@ void apply_op(mfpff_ctx* c, int l, int mode, const T* x, T* y, const T* b, bool 
     Epilogue<T> e{};
     e.y = y;
     e.b = b;
+    e.xcopy = b ? nullptr : xcopy;
     launch_fused<T>(c, L, mode, b ? EPI_RESID : EPI_APPLY, a, e);
     return;
   }
@@ -753,7 +756,8 @@ void capture_vcycle(mfpff_ctx* c) {
 }
 
 // z = V(r) on the finest level, FP64 in/out; b_ready: the caller has already written r into the
-// finest level's right-hand side and its Chebyshev start
+// finest level's right-hand side and its Chebyshev start; z null (FP64 V-cycle only): the result
+// stays in the finest level's x
 void precondition(mfpff_ctx* c, const double* r, double* z, bool b_ready = false) {
   Level& F = c->lv[c->L];
   if (!b_ready) {
@@ -763,7 +767,7 @@ void precondition(mfpff_ctx* c, const double* r, double* z, bool b_ready = false
   if (c->vgraph) HIPCHK(hipGraphLaunch(c->vgraph, c->s));
   else vcycle_body(c);
   if (c->f32) k_cast_f2d(z, (const float*)F.w[WX], F.n, c->s);
-  else k_copy<double>(z, (const double*)F.w[WX], F.n, c->s);
+  else if (z) k_copy<double>(z, (const double*)F.w[WX], F.n, c->s);
   LAUNCHCHK();
 }
 
@@ -988,8 +992,14 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
     double* zj = c->Z + (size_t)j * n;
     double* hb = c->hdev + (j & 1) * kHBuf;
     double *h1 = hb, *h2 = hb + 80, *hn = hb + 160;
-    precondition(c, vj, zj, true);
-    apply_op<double>(c, c->L, MODE_APPLY, zj, c->gw, nullptr);
+    if (c->f32) {
+      precondition(c, vj, zj, true);
+      apply_op<double>(c, c->L, MODE_APPLY, zj, c->gw, nullptr);
+    } else {
+      // the product reads z_j where the V-cycle left it and its epilogue stores the copy in Z
+      precondition(c, vj, nullptr, true);
+      apply_op<double>(c, c->L, MODE_APPLY, (const double*)c->lv[c->L].w[WX], c->gw, nullptr, false, zj);
+    }
     if (j + 1 <= kOrthMax) {
       // two passes over V (each with all basis vectors at once): h1 = V^T w; w -= V h1 with
       // h2 = V^T w and |w|^2.  The second projection w -= V h2 is applied with the

@@ -128,6 +128,7 @@ struct Epilogue {
   T c1u, c2u, c1p, c2p; // cheb: d = c1 d + c2 D^-1 (r - t)
   const T* xacc;        // cheb: optional xout = xacc + z'
   T* xout;
+  T* xcopy;             // apply: optional copy of x (every node written)
 };
 // node gather of the 3D element results (cell_kernel with a.elem) with a fused epilogue
 template <typename T>

@@ -211,6 +211,7 @@ __global__ __launch_bounds__(kRowCells*(K + 1)) __attribute__((amdgpu_waves_per_
       const T gx = fixed ? xo : acc[cc * AN * AN + o.bo];
       if (EPI == EPI_APPLY) {
         at_off(e.y + cb, o.boff) = gx;
+        if (e.xcopy) at_off(e.xcopy + cb, o.boff) = xo;
       } else if (EPI == EPI_RESID) {
         const T rv = o.ea[cc] - gx;
         at_off(e.y + cb, o.boff) = rv;

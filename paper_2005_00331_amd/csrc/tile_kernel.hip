@@ -136,6 +136,7 @@ __global__ __launch_bounds__(kThreads) void tile_kernel_2d(CellArgs<T> a, Epilog
       const T gx = fixed ? a.x[idx] : acc[cc * AN + o];
       if (EPI == EPI_APPLY) {
         e.y[idx] = gx;
+        if (e.xcopy) e.xcopy[idx] = a.x[idx];
       } else if (EPI == EPI_RESID) {
         const T rv = e.b[idx] - gx;
         e.y[idx] = rv;
