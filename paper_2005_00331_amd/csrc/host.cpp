@@ -250,6 +250,10 @@ HostCsr build_slit_prolongation(const Geom& gf, const Geom& gc, const HostSparse
   A.n_rows = (int)gf.n_nodes;
   A.n_cols = (int)gc.n_nodes;
   A.rowptr.assign((size_t)gf.n_nodes + 1, 0);
+  size_t per_row = 1;
+  for (int a = 0; a < d; ++a) per_row *= (size_t)P1.width;
+  A.col.reserve((size_t)gf.n_nodes * per_row);
+  A.val.reserve((size_t)gf.n_nodes * per_row);
   auto emit_row = [&](const long long* fm, bool other_side) {
     // the tensor product of the 1D rows of fm's indices
     int cnt[3] = {1, 1, 1};
