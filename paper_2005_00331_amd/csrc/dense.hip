@@ -48,6 +48,14 @@ void k_extract_block(double* dst, long long ldd, const double* src, long long ld
   hipLaunchKernelGGL(extract_block_kernel, dim3((unsigned)nb), dim3(kThreads), 0, s, dst, ldd, src, lds, r0, c0, nr, nc);
 }
 
+// v from lane `lane` (uniform), as two 32-bit reads into scalar registers
+__device__ __forceinline__ double readlane_f64(double v, int lane) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
 // Factor the diagonal block at k0 (identity padding past n) with one wavefront: lane i < TB
 // holds row i in registers, each column of L goes through LDS once.  Block 0 writes L11 to
 // `diag` (copied into A by the next launch, so that no block reads a half-written diagonal
@@ -87,18 +95,19 @@ __global__ __launch_bounds__(kPanelLanes) void potrf_panel_kernel(double* A, int
     for (int l = 0; l < TB; ++l) row[l] = L[i][l];
 #pragma clang loop unroll(full)
     for (int j = 0; j < TB; ++j) {
-      if (tid == j) {
-        double d = row[j];
-        if (!(d > 0.0)) {
-          if (blockIdx.x == 0) atomicMax(info, k0 + j + 1);
-          d = 1.0;
-        }
-        row[j] = sqrt(d);
-        rinv[j] = 1.0 / row[j];
+      // every lane reads the pivot from lane j and takes r = 1 / sqrt(pivot) itself (one
+      // reciprocal square root, no LDS round trip): L[j][j] = pivot * r, L[i][j] = A[i][j] * r
+      double d = readlane_f64(row[j], j);
+      if (!(d > 0.0)) {
+        if (tid == j && blockIdx.x == 0) atomicMax(info, k0 + j + 1);
+        d = 1.0;
       }
-      __syncthreads();
-      if (tid > j && tid < TB) {
-        row[j] *= rinv[j];
+      const double r = rsqrt(d);
+      if (tid == j) {
+        row[j] = d * r;
+        rinv[j] = r;
+      } else if (tid > j && tid < TB) {
+        row[j] *= r;
         col[tid] = row[j];
       }
       __syncthreads();
