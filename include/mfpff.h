@@ -248,7 +248,8 @@ mfpff_status mfpff_coarse_solve(mfpff_ctx* ctx, const double* r, double* x);
 mfpff_status mfpff_vcycle(mfpff_ctx* ctx, const double* r, double* z);
 
 /* The linear solve of each Newton step of Algorithm 1 (Section 3.3: GMRES preconditioned by the
- * multigrid V-cycle): right-preconditioned flexible GMRES(m), classical Gram-Schmidt twice,
+ * multigrid V-cycle): right-preconditioned flexible GMRES(m), classical Gram-Schmidt twice (the
+ * norm after the second projection taken as sqrt(|w|^2 - |h2|^2), the basis being orthonormal),
  * x0 = 0, until ||b - G^ x|| <= rtol ||b|| (FP64 outer iteration; V-cycle precision per the
  * problem).  b, x: device, finest n_dofs.  MFPFF_ERR_NOCONV leaves the last iterate in x (info
  * filled); MFPFF_ERR_STATE before mfpff_set_linearization.  Synchronises. */
