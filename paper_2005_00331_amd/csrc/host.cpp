@@ -990,7 +990,8 @@ mfpff_status gmres(mfpff_ctx* c, const double* b, double* x, mfpff_solve_info* i
   // the finest level's Chebyshev start
   void* vb = c->lv[c->L].w[WB];
   const VStart vs = vstart(c);
-  // step j: z_j = V(v_j), w = G^ z_j, CGS2 against v_0..v_j into buffer j % 2, copied to the host
+  // step j: z_j = V(v_j), w = G^ z_j, the CGS2 sums against v_0..v_j into buffer j % 2 (the
+  // second projection itself is applied when v_{j+1} is normalised), copied to the host
   auto arnoldi = [&](int j) {
     double* vj = c->V + (size_t)j * c->ldv;
     double* zj = c->Z + (size_t)j * n;
