@@ -444,8 +444,15 @@ void k_transpose(double* At, const double* A, int n, hipStream_t s) {
 // (the tail of a chunk reads a clamped in-range column with weight 0), so a row of a few
 // thousand columns costs one or two memory round trips; then a fixed-order block reduction.
 constexpr int kGemvChunk = 8;
-__global__ __launch_bounds__(kThreads) void gemv_kernel(double* y, const double* A, long long lda, const double* x,
-                                                        int cols, double alpha, const double* yin, int shape) {
+// Vec: x and yin as FP64 or FP32 (the FP32 V-cycle's coarse right-hand side is read as it is);
+// y32, if given, receives y rounded to FP32 as well (the FP32 V-cycle's coarse solution); y may
+// be null then
+__device__ __forceinline__ double vec_at(const void* v, int f32, int j) {
+  return f32 ? (double)static_cast<const float*>(v)[j] : static_cast<const double*>(v)[j];
+}
+__global__ __launch_bounds__(kThreads) void gemv_kernel(double* y, float* y32, const double* A, long long lda,
+                                                        const void* x, int x32, int cols, double alpha, const void* yin,
+                                                        int yin32, int shape) {
   __shared__ double part[kThreads / 64];
   const int row = blockIdx.x;
   const int t = threadIdx.x;
@@ -459,7 +466,7 @@ __global__ __launch_bounds__(kThreads) void gemv_kernel(double* y, const double*
     for (int i = 0; i < kGemvChunk; ++i) {
       const int j = min(base + i * kThreads, j1 - 1);
       av[i] = a[j];
-      xv[i] = x[j];
+      xv[i] = vec_at(x, x32, j);
     }
 #pragma unroll
     for (int i = 0; i < kGemvChunk; ++i) acc += base + i * kThreads < j1 ? av[i] * xv[i] : 0.0;
@@ -471,13 +478,20 @@ __global__ __launch_bounds__(kThreads) void gemv_kernel(double* y, const double*
     double s = 0;
 #pragma unroll
     for (int w = 0; w < kThreads / 64; ++w) s += part[w];
-    y[row] = alpha * s + (yin ? yin[row] : 0.0);
+    const double v = alpha * s + (yin ? vec_at(yin, yin32, row) : 0.0);
+    if (y) y[row] = v;
+    if (y32) y32[row] = (float)v;
   }
 }
 void k_gemv(double* y, const double* A, long long lda, const double* x, int rows, int cols, double alpha, const double* yin,
             int shape, hipStream_t s) {
+  k_gemv_mixed(y, nullptr, A, lda, x, false, rows, cols, alpha, yin, false, shape, s);
+}
+void k_gemv_mixed(double* y, float* y32, const double* A, long long lda, const void* x, bool x32, int rows, int cols,
+                  double alpha, const void* yin, bool yin32, int shape, hipStream_t s) {
   if (rows <= 0) return;
-  hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)rows), dim3(kThreads), 0, s, y, A, lda, x, cols, alpha, yin, shape);
+  hipLaunchKernelGGL(gemv_kernel, dim3((unsigned)rows), dim3(kThreads), 0, s, y, y32, A, lda, x, x32 ? 1 : 0, cols, alpha,
+                     yin, yin32 ? 1 : 0, shape);
 }
 
 }  // namespace mfpff

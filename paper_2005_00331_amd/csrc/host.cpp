@@ -131,7 +131,6 @@ struct mfpff_ctx {
   double* Wp = nullptr;
   double* WpT = nullptr;
   double* Gpu = nullptr;
-  double* cs_in = nullptr;
   double* cs_out = nullptr;
   double* cs_t = nullptr;
   int* info_dev = nullptr;
@@ -630,25 +629,35 @@ void transfer(mfpff_ctx* c, int l, int dir, const T* in, T* out, bool add, T* ta
   LAUNCHCHK();
 }
 
-void coarse_solve64(mfpff_ctx* c, const double* r, double* x) {
+// x = G^_0^-1 r by the block lower-triangular structure.  r in FP64 or FP32 (r32); the solution
+// goes to x64 (FP64) and/or x32 (FP32, the FP32 V-cycle); without x64 the u part is kept in FP64
+// in cs_out for the coupling product
+void coarse_solve_any(mfpff_ctx* c, const void* r, bool r32, double* x64, float* x32) {
   const int nu = c->nu0, np = c->np0;
+  double* xu = x64 ? x64 : c->cs_out;
+  float* xu32 = x32;
+  float* xp32 = x32 ? x32 + nu : nullptr;
+  double* xp = x64 ? x64 + nu : nullptr;
+  const void* rp = r32 ? (const void*)((const float*)r + nu) : (const void*)((const double*)r + nu);
   // W = L^-1 is lower triangular and W^T upper: each product reads only the stored triangle;
   // after the LU fallback W is the block's full inverse
   if (c->coarse_lu[0]) {
-    k_gemv(x, c->Wu, nu, r, nu, nu, 1.0, nullptr, GEMV_FULL, c->s);
+    k_gemv_mixed(xu, xu32, c->Wu, nu, r, r32, nu, nu, 1.0, nullptr, false, GEMV_FULL, c->s);
   } else {
-    k_gemv(c->cs_t, c->Wu, nu, r, nu, nu, 1.0, nullptr, GEMV_LOWER, c->s);
-    k_gemv(x, c->WuT, nu, c->cs_t, nu, nu, 1.0, nullptr, GEMV_UPPER, c->s);
+    k_gemv_mixed(c->cs_t, nullptr, c->Wu, nu, r, r32, nu, nu, 1.0, nullptr, false, GEMV_LOWER, c->s);
+    k_gemv_mixed(xu, xu32, c->WuT, nu, c->cs_t, false, nu, nu, 1.0, nullptr, false, GEMV_UPPER, c->s);
   }
-  k_gemv(c->cs_t + nu, c->Gpu, nu, x, np, nu, -1.0, r + nu, GEMV_FULL, c->s);
+  k_gemv_mixed(c->cs_t + nu, nullptr, c->Gpu, nu, xu, false, np, nu, -1.0, rp, r32, GEMV_FULL, c->s);
   if (c->coarse_lu[1]) {
-    k_gemv(x + nu, c->Wp, np, c->cs_t + nu, np, np, 1.0, nullptr, GEMV_FULL, c->s);
+    k_gemv_mixed(xp, xp32, c->Wp, np, c->cs_t + nu, false, np, np, 1.0, nullptr, false, GEMV_FULL, c->s);
   } else {
     k_gemv(c->cs_t, c->Wp, np, c->cs_t + nu, np, np, 1.0, nullptr, GEMV_LOWER, c->s);
-    k_gemv(x + nu, c->WpT, np, c->cs_t, np, np, 1.0, nullptr, GEMV_UPPER, c->s);
+    k_gemv_mixed(xp, xp32, c->WpT, np, c->cs_t, false, np, np, 1.0, nullptr, false, GEMV_UPPER, c->s);
   }
   LAUNCHCHK();
 }
+
+void coarse_solve64(mfpff_ctx* c, const double* r, double* x) { coarse_solve_any(c, r, false, x, nullptr); }
 
 template <typename T>
 void coarse_solve_T(mfpff_ctx* c, const T* r, T* x);
@@ -656,12 +665,10 @@ template <>
 void coarse_solve_T<double>(mfpff_ctx* c, const double* r, double* x) {
   coarse_solve64(c, r, x);
 }
+// the FP32 V-cycle: FP32 right-hand side read and FP32 solution written by the FP64 products
 template <>
 void coarse_solve_T<float>(mfpff_ctx* c, const float* r, float* x) {
-  const long long n = c->lv[0].n;
-  k_cast_f2d(c->cs_in, r, n, c->s);
-  coarse_solve64(c, c->cs_in, c->cs_out);
-  k_cast_d2f(x, c->cs_out, n, c->s);
+  coarse_solve_any(c, r, true, nullptr, x);
 }
 
 template <typename T>
@@ -844,7 +851,6 @@ void coarse_alloc(mfpff_ctx* c) {
   c->Wp = dalloc<double>((size_t)c->np0 * c->np0);
   c->WpT = dalloc<double>((size_t)c->np0 * c->np0);
   c->Gpu = dalloc<double>((size_t)c->np0 * c->nu0);
-  c->cs_in = dalloc<double>(n0);
   c->cs_out = dalloc<double>(n0);
   c->cs_t = dalloc<double>(n0);
 }
@@ -1494,7 +1500,7 @@ void mfpff_destroy(mfpff_ctx* c) {
     F(c->tab32[k]);
   }
   void* ps[] = {c->elem, c->finite_flag, c->w1d, c->ml, c->t64a, c->t64b, c->t32a, c->t32b, c->dense, c->Auu, c->App, c->Wu, c->WuT, c->Wp,
-                c->WpT, c->Gpu, c->cs_in, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lu_work, c->lst, c->part, c->V,
+                c->WpT, c->Gpu, c->cs_out, c->cs_t, c->info_dev, c->chol_scratch, c->lu_work, c->lst, c->part, c->V,
                 c->Z, c->gw, c->gr, c->hdev, c->ycoef, c->R, c->b, c->dU, c->pvjp_part, c->pvjp_out, c->act_prev, c->pdas_part,
                 c->phit_ext, c->react};
   for (void* p : ps) F(p);

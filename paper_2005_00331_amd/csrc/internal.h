@@ -307,5 +307,9 @@ void k_transpose(double* At, const double* A, int n, hipStream_t s);
 enum GemvShape : int { GEMV_FULL = 0, GEMV_LOWER = 1, GEMV_UPPER = 2 };
 void k_gemv(double* y, const double* A, long long lda, const double* x, int rows, int cols, double alpha,
             const double* yin, int shape, hipStream_t s);
+// the same with x and yin in FP64 or FP32 (x32, yin32) and an optional FP32 copy of y (y32; y may
+// then be null)
+void k_gemv_mixed(double* y, float* y32, const double* A, long long lda, const void* x, bool x32, int rows, int cols,
+                  double alpha, const void* yin, bool yin32, int shape, hipStream_t s);
 
 }  // namespace mfpff
