@@ -61,7 +61,11 @@ def test_active_set_matches_oracle_rule():
                                           # Q4 with p-coarsening Q4 -> Q2 -> Q1 on the coarsest mesh
                                           ("C4", dict(dim=2, N=8, n_h_levels=2), "f64"),
                                           ("C4", dict(dim=2, N=8, n_h_levels=2), "f32"),
-                                          ("C4", dict(dim=2, N=8, n_h_levels=2, phi_mode="ones"), "f64")])
+                                          ("C4", dict(dim=2, N=8, n_h_levels=2, phi_mode="ones"), "f64"),
+                                          # restart 48: the basis outgrows the fused two-pass
+                                          # orthogonalisation (32 vectors) within each cycle
+                                          ("C4", dict(dim=2, N=8, n_h_levels=2, restart=48), "f64"),
+                                          ("C4", dict(dim=2, N=8, n_h_levels=2, restart=48), "f32")])
 def test_fgmres_solve(name, kw, prec):
     cfg = CONFIGS[name].with_(**kw)
     levels = level_list(cfg)
